@@ -1,0 +1,180 @@
+"""Riemannian L-BFGS with a Wolfe / approximate-Wolfe line search (oracle; test infrastructure only).
+
+Sec. 3 of the paper. Readings where the paper leaves details open (constants are "free" in the paper):
+  * Wolfe conditions on phi(alpha) = C(R_W(d, alpha)) with slope phi'(alpha) = g(G', X'), X' = dR/dalpha
+    (eqs. wolfe_1, wolfe_2). eq. wolfe_1 as printed lacks alpha and its sign allows an increase; it is read as the
+    Armijo rule phi(alpha) <= phi(0) + c1 alpha phi'(0). c1 = 1e-4, c2 = 0.9.
+  * Approximate-Wolfe switch in the spirit of the Hager-Zhang line search cited in Sec. 3:
+    (2 c1 - 1) phi'(0) >= phi'(alpha) >= c2 phi'(0) together with phi(alpha) <= phi(0) + eps |phi(0)|, eps = 1e-6.
+  * Trial steps: alpha = 1 first; while no upper bracket exists, double; afterwards a safeguarded secant on the
+    slopes, falling back to bisection; at most `max_evals` evaluations.
+  * L-BFGS (Sec. 3): two-loop recursion over the last m pairs, transported to the current point; initial inverse
+    Hessian gamma * P with P the preconditioner and gamma = <s, y> / <y, P y> from the newest pair;
+    s_k = T(alpha d_k), y_k = G_{k+1} - T(G_k); a pair with <s, y> <= 1e-12 |s| |y| is not stored; if the
+    direction is not a descent direction the history is dropped and d = -P(G).
+"""
+import math
+import numpy as np
+
+from . import manifold as mf
+from . import mera as om
+
+
+def _axpy(a, X, Y):
+    return [y + a * x for x, y in zip(X, Y)]
+
+
+def _scale(a, X):
+    return [a * x for x in X]
+
+
+class LBFGSHistory:
+    """Limited-memory pairs (s_i, y_i) with 1/<s_i, y_i>, oldest first."""
+
+    def __init__(self, m):
+        self.m = m
+        self.S, self.Y, self.R = [], [], []
+
+    def reset(self):
+        self.S, self.Y, self.R = [], [], []
+
+    def direction(self, G, precond):
+        """Two-loop recursion: returns d = -H G with H0 = gamma P."""
+        q = [g.copy() for g in G]
+        alphas = []
+        for s, y, r in zip(reversed(self.S), reversed(self.Y), reversed(self.R)):
+            a = r * mf.inner(s, q)
+            q = _axpy(-a, y, q)
+            alphas.append(a)
+        z = precond(q)
+        if self.S:
+            py = precond(self.Y[-1])
+            z = _scale(mf.inner(self.S[-1], self.Y[-1]) / mf.inner(self.Y[-1], py), z)
+        for (s, y, r), a in zip(zip(self.S, self.Y, self.R), reversed(alphas)):
+            b = r * mf.inner(y, z)
+            z = _axpy(a - b, s, z)
+        return _scale(-1.0, z)
+
+    def transport(self, Wnew):
+        self.S = [[mf.transport(w, x) for w, x in zip(Wnew, s)] for s in self.S]
+        self.Y = [[mf.transport(w, x) for w, x in zip(Wnew, y)] for y in self.Y]
+
+    def push(self, s, y):
+        sy = mf.inner(s, y)
+        if sy <= 1e-12 * math.sqrt(mf.inner(s, s) * mf.inner(y, y)):
+            return False
+        self.S.append(s)
+        self.Y.append(y)
+        self.R.append(1.0 / sy)
+        if len(self.S) > self.m:
+            self.S.pop(0)
+            self.Y.pop(0)
+            self.R.pop(0)
+        return True
+
+
+def line_search(phi, f0, df0, alpha0=1.0, c1=1e-4, c2=0.9, eps=1e-6, max_evals=10):
+    """Find alpha meeting the Wolfe or approximate-Wolfe conditions. phi(alpha) -> (f, df, payload).
+
+    Returns (ok, alpha, f, df, payload, evals).
+    """
+    epsk = eps * abs(f0)
+    lo_a, lo_df = 0.0, df0
+    hi_a, hi_df = math.inf, None
+    alpha = alpha0
+    for n in range(1, max_evals + 1):
+        f, df, payload = phi(alpha)
+        if not (math.isfinite(f) and math.isfinite(df)):
+            hi_a, hi_df = alpha, math.inf
+        else:
+            wolfe = f <= f0 + c1 * alpha * df0 and df >= c2 * df0
+            approx = (2.0 * c1 - 1.0) * df0 >= df >= c2 * df0 and f <= f0 + epsk
+            if wolfe or approx:
+                return True, alpha, f, df, payload, n
+            if df >= 0.0 or f > f0 + epsk:
+                hi_a, hi_df = alpha, df
+            else:
+                lo_a, lo_df = alpha, df
+        if math.isinf(hi_a):
+            alpha = 2.0 * alpha
+            continue
+        width = hi_a - lo_a
+        trial = None
+        if hi_df is not None and math.isfinite(hi_df) and hi_df >= 0.0 and hi_df > lo_df:
+            trial = (lo_a * hi_df - hi_a * lo_df) / (hi_df - lo_df)
+        if trial is None or not (lo_a + 0.1 * width <= trial <= hi_a - 0.1 * width):
+            trial = lo_a + 0.5 * width
+        alpha = trial
+    return False, alpha, None, None, None, max_evals
+
+
+class Problem:
+    """The MERA cost on the product of Stiefel manifolds, flattened as [u_1, w_1, ..., u_s, w_s]."""
+
+    def __init__(self, h3, chi, T, d=4):
+        self.h3, self.chi, self.T, self.d = h3, chi, T, d
+        self.dims = om.layer_dims(chi, T, d)
+        self.evals = 0
+
+    def evaluate(self, W):
+        params = [(W[2 * i], W[2 * i + 1]) for i in range(len(self.dims))]
+        ev = om.evaluate(params, self.h3, self.chi, self.T, self.d)
+        self.evals += 1
+        D = [m for pair in ev['grads'] for m in pair]
+        G = [mf.project(w, dd) for w, dd in zip(W, D)]
+        rdms = om.preconditioner_rdms(ev['rhos'], params, self.dims)
+        rv = [m for pair in rdms for m in pair]
+        return ev['energy'], G, rv
+
+
+def optimize(W0, problem, m=8, max_iter=200, grad_tol=1e-10, use_precond=True, ls_max_evals=10, log=None):
+    """Riemannian L-BFGS driver (Sec. 3) on the flattened parameter list W0. Returns (W, energy, |G|, info)."""
+    W = [w.copy() for w in W0]
+    f, G, rv = problem.evaluate(W)
+    hist = LBFGSHistory(m)
+    it = 0
+    status = 'maxiter'
+    for it in range(max_iter):
+        gnorm = math.sqrt(mf.inner(G, G))
+        if log is not None:
+            log.append(dict(iter=it, energy=f, gnorm=gnorm, evals=problem.evals))
+        if gnorm <= grad_tol:
+            status = 'converged'
+            break
+
+        def P(X, _W=W, _rv=rv):
+            if not use_precond:
+                return [x.copy() for x in X]
+            return [mf.precondition(w, x, r) for w, x, r in zip(_W, X, _rv)]
+        d = hist.direction(G, P)
+        slope = mf.inner(G, d)
+        if not slope < 0.0:
+            hist.reset()
+            d = _scale(-1.0, P(G))
+            slope = mf.inner(G, d)
+
+        def phi(alpha, _W=W, _d=d):
+            pairs = [mf.retract(w, x, alpha) for w, x in zip(_W, _d)]
+            Wn = [p[0] for p in pairs]
+            Xp = [p[1] for p in pairs]
+            fn, Gn, rvn = problem.evaluate(Wn)
+            return fn, mf.inner(Gn, Xp), (Wn, Gn, rvn)
+        ok, alpha, fn, dfn, payload, _ = line_search(phi, f, slope, max_evals=ls_max_evals)
+        if not ok and hist.S:
+            hist.reset()
+            d = _scale(-1.0, P(G))
+            slope = mf.inner(G, d)
+            ok, alpha, fn, dfn, payload, _ = line_search(phi, f, slope, max_evals=ls_max_evals)
+        if not ok:
+            status = 'linesearch_failed'
+            break
+        Wn, Gn, rvn = payload
+        s = [mf.transport(w, alpha * x) for w, x in zip(Wn, d)]
+        y = [gn - mf.transport(w, g) for w, gn, g in zip(Wn, Gn, G)]
+        hist.transport(Wn)
+        hist.push(s, y)
+        W, f, G, rv = Wn, fn, Gn, rvn
+    else:
+        it = max_iter
+    gnorm = math.sqrt(mf.inner(G, G))
+    return W, f, gnorm, dict(iterations=it, evals=problem.evals, status=status)
