@@ -7,8 +7,11 @@ around the ring. Reduced density matrices are taken directly from the state vect
 import numpy as np
 
 
-def apply_layer(psi, u, w, a, b):
-    """Lower a ring state by one layer. psi has n legs of dim b (leg k = site k); returns 2n legs of dim a."""
+def apply_layer(psi, u, w, a, b, isometries_only=False):
+    """Lower a ring state by one layer. psi has n legs of dim b (leg k = site k); returns 2n legs of dim a.
+
+    With isometries_only the disentanglers are not applied (the state between the two rows of the layer).
+    """
     n = psi.ndim
     Wt = w.reshape(a, a, b)
     U = u.reshape(a, a, a, a)
@@ -17,6 +20,8 @@ def apply_layer(psi, u, w, a, b):
         pos = 2 * j
         psi = np.tensordot(psi, Wt, axes=([pos], [2]))           # new legs appended at the end
         psi = np.moveaxis(psi, [psi.ndim - 2, psi.ndim - 1], [pos, pos + 1])
+    if isometries_only:
+        return psi
     m = 2 * n
     for j in range(n):
         s1, s2 = (2 * j + 1) % m, (2 * j + 2) % m

@@ -260,13 +260,17 @@ def energy_bottom(params, h3, chi, T, d=4):
 def preconditioner_rdms(rhos, params, dims):
     """Reduced density matrices rho_v on the top legs of each tensor (Sec. 4, eq. mera_diagonal_inner_product).
 
+    rhos[t] is the density matrix at the bottom of layer t (rhos[T] = rho_s), as returned by `evaluate`; the
+    top of transition layer t is therefore rhos[t + 1], and the top of the scale-invariant layer is rho_s.
     Reading: rho_w is the one-site marginal (middle site) of the position-averaged 3-site rho at the top of the
     layer; rho_u is the two-site marginal rho2 = (Tr_3 rho + Tr_1 rho)/2 pushed down through w (x) w with the
     outer bottom legs traced, giving an a^2 x a^2 matrix on the two top legs of u.
     """
     out = []
+    T = len(dims) - 1
     for t, (a, b) in enumerate(dims):
-        r6 = rhos[t].reshape((b,) * 6)
+        top = rhos[t + 1] if t < T else rhos[T]
+        r6 = top.reshape((b,) * 6)
         rho_w = np.einsum('pqrpQr->qQ', r6)
         rho2 = 0.5 * (np.einsum('pqrPQr->pqPQ', r6) + np.einsum('pqrpQR->qrQR', r6))
         Wt = params[t][1].reshape(a, a, b)

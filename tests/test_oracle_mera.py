@@ -212,3 +212,20 @@ def test_gradient_shift_invariance():
         for k in range(2):
             W = params[t][k]
             assert np.max(np.abs(manifold.project(W, g1[t][k]) - manifold.project(W, g2[t][k]))) < 1e-11
+
+
+def test_preconditioner_rdms_match_brute_force():
+    # rho_w of layer 1 is the one-site density matrix of the 4-site ring above it; rho_u of layer 1 is the
+    # two-site density matrix, on the pair a disentangler acts on, of the state between w's and u's.
+    d = chi = 2
+    psi8, psi4, (u1, w1) = _ring_state(9, d, chi)
+    rho1 = sum(finite.rdm(psi4, [j, (j + 1) % 4, (j + 2) % 4]) for j in range(4)) / 4
+    rhos = [None, rho1]        # bottom of layer 1 (unused), top of layer 1 (in the slot of rho_s, T = 1)
+    dims = [(d, chi), (chi, chi)]
+    params = [(u1, w1), (u1, w1)]
+    rho_u, rho_w = mera.preconditioner_rdms(rhos, params, dims)[0]
+    one_site = sum(finite.rdm(psi4, [j]) for j in range(4)) / 4
+    assert np.max(np.abs(rho_w - one_site)) < 1e-14
+    mid = finite.apply_layer(psi4, u1, w1, d, chi, isometries_only=True)
+    two_site = sum(finite.rdm(mid, [2 * j + 1, (2 * j + 2) % 8]) for j in range(4)) / 4
+    assert np.max(np.abs(rho_u - two_site)) < 1e-14
