@@ -1,0 +1,227 @@
+/*
+ * mera.h — C ABI of the MI355X (gfx950) library for Riemannian optimisation of an infinite, scale-invariant
+ * binary MERA.
+ *
+ * Method: Hauru, Van Damme & Haegeman, "Riemannian optimization of isometric tensor networks",
+ * arXiv:2007.03638. Section numbers below refer to that paper.
+ *
+ * Conventions (all calls)
+ *   - Every call returns a mera_status; nothing else signals failure, and no exception crosses the ABI.
+ *     On error the outputs are unspecified and mera_last_error(ctx) holds a message.
+ *   - Matrices (mera_mat) are REAL, FP64, ROW-MAJOR n x p, in DEVICE memory of the context's GPU, and are
+ *     owned by the caller. For an isometry the rows index the bottom (incoming) legs and the columns the top
+ *     (outgoing) legs: a disentangler u is a^2 x a^2 with rows (bl, br) and columns (tl, tr); an isometry w is
+ *     a^2 x b with rows (bl, br) and column t. Leg indices are row-major (first leg slowest).
+ *   - 3-site operators are d^3 x d^3 matrices (rows = ket legs abc, columns = bra legs ABC), row-major FP64.
+ *   - All device work is ordered on the context's HIP stream. Calls that return host scalars synchronise it.
+ *   - The library owns only what its *_create calls allocate and frees it in the matching *_destroy.
+ *   - Layer geometry: T transition layers and one scale-invariant layer. Layer 1 has bottom dimension a_1 = d;
+ *     layer tau has top dimension b_tau = min(chi, a_tau^2) and a_{tau+1} = b_tau; the scale-invariant layer
+ *     has a = b = chi, so b_T must equal chi (MERA_EINVAL otherwise). Tensor arrays are indexed by layer,
+ *     0..T-1 for the transition layers and T for the scale-invariant one.
+ */
+#ifndef MERA_H
+#define MERA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MERA_OK = 0,
+  MERA_EINVAL = -1,      /* bad argument: shape mismatch, null pointer, unsupported size            */
+  MERA_ENOMEM = -2,      /* device allocation failed                                                  */
+  MERA_EHIP = -3,        /* a HIP runtime call failed                                                 */
+  MERA_ENOCONV = -4,     /* an iteration (Krylov solve, line search) did not reach its tolerance      */
+  MERA_ENONFINITE = -5,  /* a NaN or Inf appeared in an energy, a norm or an inner product            */
+  MERA_EBUSY = -6        /* the job is still running (server polling)                                 */
+} mera_status;
+
+/* Arithmetic of the bulk contractions. FP64: double-precision MFMA throughout. FP32: single-precision
+ * MFMA with single-precision accumulation, double-precision dot products, traces and Krylov scalars.
+ * BF16X3: each FP32 operand split into bf16 hi + lo parts, products hi*hi + hi*lo + lo*hi on the bf16
+ * MFMA units with FP32 accumulation. */
+typedef enum { MERA_FP64 = 0, MERA_FP32 = 1, MERA_BF16X3 = 2 } mera_prec;
+
+typedef struct { int n, p; double* data; } mera_mat;
+
+typedef struct {
+  int T;    /* number of transition layers (>= 1)                         */
+  int d;    /* physical (blocked-site) dimension, 4 for two spins per site */
+  int chi;  /* bond dimension of the scale-invariant layer                 */
+} mera_shape;
+
+typedef struct mera_ctx mera_ctx;
+typedef struct mera_warm mera_warm;
+typedef struct mera_lbfgs mera_lbfgs;
+typedef struct mera_server mera_server;
+
+/* ---- context ------------------------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`. `hip_stream` is a hipStream_t owned by the caller, or NULL for
+ * the default stream. */
+mera_status mera_ctx_create(int device, void* hip_stream, mera_ctx** out);
+void mera_ctx_destroy(mera_ctx* ctx);
+const char* mera_last_error(const mera_ctx* ctx);
+/* Release the context's cached device workspace (intermediate tensors, offset tables). */
+mera_status mera_ctx_trim(mera_ctx* ctx);
+/* Multiply-accumulate count of every contraction issued on the context since creation (algorithmic:
+ * the product of all leg dimensions of each pairwise step, no padding). */
+double mera_ctx_macs(const mera_ctx* ctx);
+
+/* Layer dimensions: a_out[0..T], b_out[0..T] (host arrays of T+1 ints). */
+mera_status mera_layer_dims(const mera_shape* shape, int* a_out, int* b_out);
+
+/* ---- model -------------------------------------------------------------------------------------------- */
+
+/* Three-site terms on blocked sites of two spins (d = 4), written to a HOST array of 64*64 doubles.
+ * Sec. 4 (cost function): TFIM local term -X X - h Z; XXZ term X X + Y Y + delta Z Z in Pauli units.
+ * Blocked site = spins (s1, s2), s1 major; hb = inter-block bond + half of each block's internal terms;
+ * h3 = (hb (x) 1 + 1 (x) hb) / 2, so that the sum of h3 over a ring is the spin Hamiltonian. */
+mera_status mera_h3_tfim(double h, double* h3_host);
+mera_status mera_h3_xxz(double delta, double* h3_host);
+
+/* ---- energy and Euclidean gradient (Sec. 4, App. B) --------------------------------------------------- */
+
+/* Krylov warm starts kept between evaluations: the scale-invariant density matrix and the operator h~ of
+ * the previous call (App. B: "the solution from the previous iteration as the initial guess"). */
+mera_status mera_warm_create(mera_ctx* ctx, const mera_shape* shape, mera_warm** out);
+void mera_warm_destroy(mera_warm* warm);
+
+typedef struct {
+  int krylov_dim;          /* Krylov subspace dimension per restart (App. B suggests 4); 0 -> 4          */
+  int max_restarts;        /* per solve; 0 -> 200                                                      */
+  double tol;              /* relative residual of both solves; 0 -> 1e-13 (FP64) or 1e-7 (FP32/BF16X3)  */
+} mera_krylov_opts;
+
+typedef struct {
+  double energy;           /* per blocked site, Tr[h_T rho_s]                                           */
+  int applications_rho;    /* superoperator applications spent on the fixed point                       */
+  int applications_htilde; /* ... on h~                                                                 */
+  double residual_rho;     /* final relative residuals                                                  */
+  double residual_htilde;
+  double macs;             /* multiply-accumulates issued by this call                                  */
+} mera_eval_info;
+
+/*
+ * mera_energy_grad — energy per blocked site and the Euclidean partial derivatives D_v of every tensor.
+ *   Sec. 4 (cost C = <MERA|H|MERA>, D_v = environment of v summed over all its occurrences), App. B (scale-
+ *   invariant density matrix as the fixed point of the descending map; derivative through the fixed point by
+ *   the deflated series h~ = sum_i <h'|A'^i, A' = A - |rho><1|, h' = h_T - e 1, solved by a Krylov method).
+ *   u[0..T], w[0..T]     tensors (device, FP64, see conventions), isometric.
+ *   h3                   device d^3 x d^3 FP64 symmetric 3-site term.
+ *   warm                 in/out warm starts, or NULL (then the solves start from 1/chi^3 and h').
+ *   energy               host double out.
+ *   Du[0..T], Dw[0..T]   caller-allocated device outputs, same shapes as u, w. The scale-invariant D is fixed
+ *                        in the gauge Tr[h~ rho_s] = 0 (terms along W S, S symmetric, are not determined).
+ *   rho_u, rho_w         optional (NULL) device outputs: the reduced density matrices on the top legs of each
+ *                        u (a^2 x a^2) and w (b x b) used by the Hilbert-space preconditioner (Sec. 4,
+ *                        eq. mera_diagonal_inner_product).
+ *   kopts, info          optional (NULL).
+ */
+mera_status mera_energy_grad(mera_ctx* ctx, const mera_shape* shape, const mera_mat* u, const mera_mat* w,
+                             const double* h3, mera_prec prec, mera_warm* warm, const mera_krylov_opts* kopts,
+                             double* energy, mera_mat* Du, mera_mat* Dw, mera_mat* rho_u, mera_mat* rho_w,
+                             mera_eval_info* info);
+
+/* Single superoperator applications, for tests and tools (App. B: <h|A raises, A|rho> lowers).
+ * layer = 0..T; in/out are device operators of the layer's bottom (a^3 x a^3) or top (b^3 x b^3) sites. */
+mera_status mera_ascend(mera_ctx* ctx, const mera_shape* shape, int layer, const mera_mat* u, const mera_mat* w,
+                        mera_prec prec, const double* h_in, double* h_out);
+mera_status mera_descend(mera_ctx* ctx, const mera_shape* shape, int layer, const mera_mat* u, const mera_mat* w,
+                         mera_prec prec, const double* rho_in, double* rho_out);
+
+/* ---- Stiefel manifold (Sec. 2) ------------------------------------------------------------------------ */
+/* All take `count` matrices (a point of the product manifold, Sec. 2.4) and act factor by factor. */
+
+/* G = D - W (W^T D + D^T W) / 2 (eq. stiefel_gradient, real case). G may alias D. */
+mera_status stiefel_project(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, mera_mat* G);
+/* Polar retraction W_out = (W + alpha X)(I + alpha^2 X^T X)^{-1/2} computed as the polar factor of
+ * Y = W + alpha X, with (Y^T Y)^{-1/2} by a coupled Newton-Schulz iteration in FP64 (retraction as defined in
+ * Sec. 2.3; the polar form is this library's choice). X_out (nullable) receives dR/dalpha at alpha, the
+ * curve tangent used in the Wolfe slope (Sec. 3). */
+mera_status stiefel_retract(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* X, double alpha,
+                            mera_mat* W_out, mera_mat* X_out);
+/* Vector transport by projection onto the tangent space at W_new. Y_out may alias Y. */
+mera_status stiefel_transport(mera_ctx* ctx, int count, const mera_mat* W_new, const mera_mat* Y, mera_mat* Y_out);
+/* Hilbert-space preconditioner (Sec. 3 eqs. preconditioner / preconditioner_solution): X = W A + W_perp B
+ * maps to W A~ + W_perp B~ with A~ f + f A~ = 2 A, B~ = B f^{-1}, f = (rho^2 + delta^2)^{1/2}; delta < 0 means
+ * delta = ||X_v||_F per factor (Sec. 4). rho: count p x p symmetric PSD matrices. */
+mera_status stiefel_precondition(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* X,
+                                 const mera_mat* rho, double delta, mera_mat* X_out);
+/* Euclidean metric summed over factors: sum_v Tr[X_v^T Y_v] (Sec. 2.2, 2.4). Host result. */
+mera_status mera_inner(mera_ctx* ctx, int count, const mera_mat* X, const mera_mat* Y, double* out);
+
+/* ---- L-BFGS (Sec. 3) ---------------------------------------------------------------------------------- */
+
+/* History of up to m pairs for a product manifold with factors of sizes n[i] x p[i]. */
+mera_status lbfgs_create(mera_ctx* ctx, int count, const int* n, const int* p, int m, mera_lbfgs** out);
+void lbfgs_destroy(mera_lbfgs* lb);
+mera_status lbfgs_reset(mera_lbfgs* lb);
+int lbfgs_size(const mera_lbfgs* lb);
+/* Two-loop recursion: dir_out = -H G with H0 = gamma P, P the preconditioner with rho (NULL: identity),
+ * gamma = <s,y>/<y,P y> of the newest pair. slope_out (host) = <G, dir_out>. If the result is not a descent
+ * direction the history is cleared and dir_out = -P G. */
+mera_status lbfgs_step(mera_ctx* ctx, mera_lbfgs* lb, const mera_mat* W, const mera_mat* G, const mera_mat* rho,
+                       mera_mat* dir_out, double* slope_out);
+/* After an accepted step W_new = R_W(d, alpha): transport the stored pairs to W_new, form
+ * s = T(alpha d), y = G_new - T(G_old), store the pair if <s,y> > 1e-12 |s||y| (accepted = 1). */
+mera_status lbfgs_push(mera_ctx* ctx, mera_lbfgs* lb, const mera_mat* W_new, const mera_mat* d, double alpha,
+                       const mera_mat* G_old, const mera_mat* G_new, int* accepted);
+
+/* ---- whole optimisation ------------------------------------------------------------------------------- */
+
+typedef struct {
+  mera_shape shape;
+  const double* h3_host;           /* d^3 x d^3 host FP64                                                   */
+  const double* const* init_host;  /* 2(T+1) host FP64 matrices: u_1, w_1, ..., u_T, w_T, u_s, w_s          */
+  mera_prec prec;                  /* contraction arithmetic before polishing                               */
+  int lbfgs_m;                     /* memory (8)                                                            */
+  int max_iter;
+  double grad_tol;                 /* stop at ||G|| <= grad_tol                                             */
+  double polish_tol;               /* FP32/BF16X3 forms switch to FP64 below this ||G|| (0: never)          */
+  int precondition;                /* 1: Hilbert-space preconditioner as H0 (Sec. 3, Sec. 4)                */
+  int max_ls_evals;                /* line-search evaluations per iteration (10)                            */
+  mera_krylov_opts krylov;
+} mera_job;
+
+typedef struct {
+  double energy;                   /* per blocked site at the returned point                                */
+  double gnorm;                    /* ||G|| of the unpreconditioned Riemannian gradient                      */
+  int iterations;
+  int evaluations;
+  int status;                      /* 0 converged, 1 iteration cap, 2 line search failed, <0 mera_status      */
+  int polish_iter;                 /* iteration at which FP64 polishing started, -1 if never                 */
+  double seconds;                  /* wall time of the run                                                  */
+  double macs;
+} mera_result;
+
+typedef struct { int iter; int evals; double energy; double gnorm; double alpha; int prec; } mera_iter_log;
+
+/* Blocking single-job optimisation (Sec. 3 L-BFGS with Wolfe / approximate-Wolfe line search on the product
+ * of Stiefel manifolds, Sec. 4 MERA cost). final_host (nullable): 2(T+1) host buffers receiving the final
+ * tensors. log (nullable): up to log_cap per-iteration records; *log_len (nullable) receives the count. */
+mera_status run_optimize(mera_ctx* ctx, const mera_job* job, mera_result* out, double* const* final_host,
+                         mera_iter_log* log, int log_cap, int* log_len);
+
+/* ---- serving: continuous batching of optimisation jobs ------------------------------------------------ */
+
+/* A server owns a host thread that admits submitted jobs while the device-memory footprint of the running
+ * jobs fits `hbm_budget` bytes and fewer than `max_slots` run, interleaves their evaluations on the device,
+ * and retires finished jobs. */
+mera_status mera_server_create(mera_ctx* ctx, size_t hbm_budget, int max_slots, mera_server** out);
+/* The job is copied (including h3 and initial tensors) before the call returns. */
+mera_status mera_server_submit(mera_server* srv, const mera_job* job, uint64_t* job_id);
+/* MERA_EBUSY while queued or running; MERA_OK with the result once finished. */
+mera_status mera_server_poll(mera_server* srv, uint64_t job_id, mera_result* out);
+/* Device bytes a job of this shape and precision needs (admission estimate). */
+size_t mera_job_footprint(const mera_shape* shape, mera_prec prec);
+void mera_server_destroy(mera_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MERA_H */

@@ -1,0 +1,108 @@
+// Internal shared definitions: error handling, device buffers, the context object.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/mera.h"
+
+namespace mera {
+
+// Errors inside the library are C++ exceptions carrying a status; the C ABI converts them.
+struct Error : std::runtime_error {
+  mera_status status;
+  Error(mera_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define MERA_HIP(call)                                                                               \
+  do {                                                                                               \
+    hipError_t e_ = (call);                                                                          \
+    if (e_ != hipSuccess)                                                                            \
+      throw ::mera::Error(MERA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_) + " at " +   \
+                                         __FILE__ + ":" + std::to_string(__LINE__));                 \
+  } while (0)
+
+#define MERA_CHECK(cond, status, msg)                            \
+  do {                                                           \
+    if (!(cond)) throw ::mera::Error((status), std::string(msg)); \
+  } while (0)
+
+// Owning device allocation.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); ptr = o.ptr; bytes = o.bytes; o.ptr = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      (void)hipGetLastError();
+      throw Error(MERA_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    }
+    bytes = n;
+  }
+  // Grow-only reallocation; contents are not preserved.
+  void ensure(size_t n) { if (n > bytes) alloc(n); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
+inline size_t elem_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
+
+struct PlanCache;  // network.h
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  double macs = 0.0;
+  // Named grow-only scratch buffers (intermediates, partial sums), reused across calls.
+  std::map<std::string, DevBuf> scratch;
+  std::unique_ptr<PlanCache> plans;
+  DevBuf red;        // reduction partials (doubles)
+  DevBuf red_host_flag;
+
+  Ctx();
+  ~Ctx();
+  void* buf(const std::string& name, size_t bytes) {
+    DevBuf& b = scratch[name];
+    b.ensure(bytes);
+    return b.ptr;
+  }
+  void sync() { MERA_HIP(hipStreamSynchronize(stream)); }
+};
+
+// Scoped device selection.
+struct DeviceGuard {
+  int prev = 0;
+  explicit DeviceGuard(int dev) {
+    MERA_HIP(hipGetDevice(&prev));
+    if (prev != dev) MERA_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+}  // namespace mera

@@ -1,0 +1,502 @@
+// Permute-fused GETT kernels for gfx950: LDS-staged, register-prefetched tile loads through offset tables,
+// MFMA inner products (f32 32x32x2, f64 16x16x4, bf16 16x16x32 for the split-bf16 form), split-K partials
+// reduced in FP64.
+#include "gett.h"
+
+#include <algorithm>
+
+namespace mera {
+
+namespace {
+
+struct Args {
+  const void* A;
+  const void* B;
+  void* C;
+  const int64_t* a_m;
+  const int64_t* a_k;
+  const int64_t* b_k;
+  const int64_t* b_n;
+  const int64_t* c_m;
+  const int64_t* c_n;
+  int64_t M, N, K;
+  int64_t kchunk;  // K range per split, a multiple of BK
+  double alpha, beta;
+  void* partial;   // splits x M x N partial sums (element type of the accumulator), or null
+};
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Lane layouts (checked on gfx950 against a host GEMM):
+//  f32 32x32x2:  A[m = lane%32][k = lane/32], B[k = lane/32][n = lane%32],
+//                acc[i] -> row 8*(i/4) + 4*(lane/32) + i%4, col lane%32
+//  f64 16x16x4:  A[m = lane%16][k = lane/16], B[k = lane/16][n = lane%16],
+//                acc[i] -> row lane/16 + 4*i, col lane%16
+//  bf16 16x16x32: A[m = lane%16][k = 8*(lane/16)+j], B[k = 8*(lane/16)+j][n = lane%16],
+//                acc[i] -> row 4*(lane/16) + i, col lane%16
+template <typename T> struct Mma;
+template <> struct Mma<float> {
+  static constexpr int MT = 32, NT = 32, KT = 2, NACC = 16;
+  typedef f32x16 acc_t;
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int i) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
+  __device__ static inline int col(int lane) { return lane & 31; }
+};
+template <> struct Mma<double> {
+  static constexpr int MT = 16, NT = 16, KT = 4, NACC = 4;
+  typedef f64x4 acc_t;
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int i) { return (lane >> 4) + 4 * i; }
+  __device__ static inline int col(int lane) { return lane & 15; }
+};
+
+// Tile loader: BMN x BK tile of an operand whose element (r, k) lives at base + off_r[r] + off_k[k].
+// KFAST: consecutive threads walk k (unit-stride leg is a K leg); else consecutive threads walk r.
+template <typename T, int BMN, int BK, bool KFAST>
+struct Loader {
+  static constexpr int PER = BMN * BK / 256;
+  static_assert(PER >= 1 && (BMN * BK) % 256 == 0, "tile too small for 256 threads");
+  static_assert(KFAST ? (256 % BK == 0) : (256 % BMN == 0), "thread mapping");
+  static constexpr int RSTEP = KFAST ? 256 / BK : 1;
+  static constexpr int KSTEP = KFAST ? 1 : 256 / BMN;
+  int64_t roff[KFAST ? PER : 1];
+  bool rval[KFAST ? PER : 1];
+  int r0, k0;
+  T reg[PER];
+
+  __device__ inline void init(const int64_t* off_r, int64_t rbase, int64_t R, int tid) {
+    if (KFAST) {
+      k0 = tid % BK;
+      r0 = tid / BK;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        int64_t r = rbase + r0 + i * RSTEP;
+        roff[i] = off_r[r];
+        rval[i] = r < R;
+      }
+    } else {
+      r0 = tid % BMN;
+      k0 = tid / BMN;
+      int64_t r = rbase + r0;
+      roff[0] = off_r[r];
+      rval[0] = r < R;
+    }
+  }
+  __device__ inline void load(const T* __restrict__ base, const int64_t* __restrict__ off_k, int64_t kt,
+                              int64_t kend) {
+    if (KFAST) {
+      int64_t k = kt + k0;
+      bool kv = k < kend;
+      int64_t ko = off_k[k];
+#pragma unroll
+      for (int i = 0; i < PER; ++i) reg[i] = (kv && rval[i]) ? base[roff[i] + ko] : T(0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        int64_t k = kt + k0 + i * KSTEP;
+        int64_t ko = off_k[k];
+        reg[i] = (k < kend && rval[0]) ? base[roff[0] + ko] : T(0);
+      }
+    }
+  }
+  // LDS tile stored k-major: lds[k * LD + r]
+  template <int LD>
+  __device__ inline void store(T* lds) const {
+    if (KFAST) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) lds[k0 * LD + r0 + i * RSTEP] = reg[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) lds[(k0 + i * KSTEP) * LD + r0] = reg[i];
+    }
+  }
+};
+
+template <typename T, int BM, int BN, int BK, bool AKF, bool BKF>
+__global__ void __launch_bounds__(256) gett_kernel(Args g) {
+  using F = Mma<T>;
+  constexpr int PAD = sizeof(T) == 4 ? 2 : 1;
+  constexpr int LDA = BM + PAD, LDB = BN + PAD;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / F::MT, FN = WN / F::NT;
+  static_assert(FM >= 1 && FN >= 1, "wave tile smaller than one MFMA block");
+  __shared__ T As[2][BK * LDA];
+  __shared__ T Bs[2][BK * LDB];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * WM;
+  const int wn = (wave & 1) * WN;
+
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const int64_t tile = blockIdx.x;
+  const int64_t m0 = (tile / tiles_n) * BM;
+  const int64_t n0 = (tile % tiles_n) * BN;
+  const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t ke = (g.K < kb + g.kchunk) ? g.K : kb + g.kchunk;
+
+  const T* __restrict__ A = static_cast<const T*>(g.A);
+  const T* __restrict__ B = static_cast<const T*>(g.B);
+
+  Loader<T, BM, BK, AKF> la;
+  Loader<T, BN, BK, BKF> lb;
+  la.init(g.a_m, m0, g.M, tid);
+  lb.init(g.b_n, n0, g.N, tid);
+
+  typename F::acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < F::NACC; ++r) acc[i][j][r] = T(0);
+
+  int buf = 0;
+  if (kb < ke) {
+    la.load(A, g.a_k, kb, ke);
+    lb.load(B, g.b_k, kb, ke);
+  }
+  for (int64_t kt = kb; kt < ke; kt += BK) {
+    la.template store<LDA>(As[buf]);
+    lb.template store<LDB>(Bs[buf]);
+    __syncthreads();
+    if (kt + BK < ke) {
+      la.load(A, g.a_k, kt + BK, ke);
+      lb.load(B, g.b_k, kt + BK, ke);
+    }
+    const T* as = As[buf];
+    const T* bs = Bs[buf];
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += F::KT) {
+      T af[FM], bf[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) af[i] = as[(ks + lane / F::MT) * LDA + wm + i * F::MT + lane % F::MT];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bf[j] = bs[(ks + lane / F::NT) * LDB + wn + j * F::NT + lane % F::NT];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = F::mma(af[i], bf[j], acc[i][j]);
+    }
+    buf ^= 1;
+  }
+
+  // epilogue
+  if (g.partial) {
+    T* P = static_cast<T*>(g.partial) + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < F::NACC; ++r) {
+          int64_t row = m0 + wm + i * F::MT + F::row(lane, r);
+          int64_t col = n0 + wn + j * F::NT + F::col(lane);
+          if (row < g.M && col < g.N) P[row * g.N + col] = acc[i][j][r];
+        }
+    return;
+  }
+  T* __restrict__ C = static_cast<T*>(g.C);
+  const T alpha = T(g.alpha), beta = T(g.beta);
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    int64_t col = n0 + wn + j * F::NT + F::col(lane);
+    int64_t cn = g.c_n[col];
+    bool cv = col < g.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < F::NACC; ++r) {
+        int64_t row = m0 + wm + i * F::MT + F::row(lane, r);
+        if (cv && row < g.M) {
+          int64_t o = g.c_m[row] + cn;
+          T v = alpha * acc[i][j][r];
+          if (g.beta != 0.0) v += beta * C[o];
+          C[o] = v;
+        }
+      }
+  }
+}
+
+// ---- split-bf16 (hi + lo) form: C ~= A_hi B_hi + A_hi B_lo + A_lo B_hi on the bf16 MFMA ------------------
+
+__device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// FP32 tiles are staged in LDS as (hi, lo) bf16 pairs, k-major with 8 consecutive k per lane fragment.
+template <int BM, int BN, int BK, bool AKF, bool BKF>
+__global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
+  static_assert(BK % 32 == 0, "bf16 MFMA consumes k in steps of 32");
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int LDA = BM + 2, LDB = BN + 2;  // in bf16x? units: stored as separate hi/lo planes, k-major
+  __shared__ __bf16 Ah[BK * LDA], Al[BK * LDA], Bh[BK * LDB], Bl[BK * LDB];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * WM;
+  const int wn = (wave & 1) * WN;
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const int64_t tile = blockIdx.x;
+  const int64_t m0 = (tile / tiles_n) * BM;
+  const int64_t n0 = (tile % tiles_n) * BN;
+  const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t ke = (g.K < kb + g.kchunk) ? g.K : kb + g.kchunk;
+  const float* __restrict__ A = static_cast<const float*>(g.A);
+  const float* __restrict__ B = static_cast<const float*>(g.B);
+
+  Loader<float, BM, BK, AKF> la;
+  Loader<float, BN, BK, BKF> lb;
+  la.init(g.a_m, m0, g.M, tid);
+  lb.init(g.b_n, n0, g.N, tid);
+
+  f32x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  if (kb < ke) {
+    la.load(A, g.a_k, kb, ke);
+    lb.load(B, g.b_k, kb, ke);
+  }
+  for (int64_t kt = kb; kt < ke; kt += BK) {
+    // split and stage
+    if (AKF) {
+#pragma unroll
+      for (int i = 0; i < la.PER; ++i) {
+        __bf16 h, l;
+        split_bf16(la.reg[i], h, l);
+        int idx = la.k0 * LDA + la.r0 + i * la.RSTEP;
+        Ah[idx] = h;
+        Al[idx] = l;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < la.PER; ++i) {
+        __bf16 h, l;
+        split_bf16(la.reg[i], h, l);
+        int idx = (la.k0 + i * la.KSTEP) * LDA + la.r0;
+        Ah[idx] = h;
+        Al[idx] = l;
+      }
+    }
+    if (BKF) {
+#pragma unroll
+      for (int i = 0; i < lb.PER; ++i) {
+        __bf16 h, l;
+        split_bf16(lb.reg[i], h, l);
+        int idx = lb.k0 * LDB + lb.r0 + i * lb.RSTEP;
+        Bh[idx] = h;
+        Bl[idx] = l;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < lb.PER; ++i) {
+        __bf16 h, l;
+        split_bf16(lb.reg[i], h, l);
+        int idx = (lb.k0 + i * lb.KSTEP) * LDB + lb.r0;
+        Bh[idx] = h;
+        Bl[idx] = l;
+      }
+    }
+    __syncthreads();
+    if (kt + BK < ke) {
+      la.load(A, g.a_k, kt + BK, ke);
+      lb.load(B, g.b_k, kt + BK, ke);
+    }
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 32) {
+      bf16x8 ah[FM], al[FM], bh[FN], bl[FN];
+      const int kq = ks + 8 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        int r = wm + i * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          ah[i][e] = Ah[(kq + e) * LDA + r];
+          al[i][e] = Al[(kq + e) * LDA + r];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        int c = wn + j * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          bh[j][e] = Bh[(kq + e) * LDB + c];
+          bl[j][e] = Bl[(kq + e) * LDB + c];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+
+  if (g.partial) {
+    float* P = static_cast<float*>(g.partial) + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+          int64_t col = n0 + wn + j * 16 + (lane & 15);
+          if (row < g.M && col < g.N) P[row * g.N + col] = acc[i][j][r];
+        }
+    return;
+  }
+  float* __restrict__ C = static_cast<float*>(g.C);
+  const float alpha = float(g.alpha), beta = float(g.beta);
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    int64_t col = n0 + wn + j * 16 + (lane & 15);
+    int64_t cn = g.c_n[col];
+    bool cv = col < g.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        if (cv && row < g.M) {
+          int64_t o = g.c_m[row] + cn;
+          float v = alpha * acc[i][j][r];
+          if (g.beta != 0.0) v += beta * C[o];
+          C[o] = v;
+        }
+      }
+  }
+}
+
+template <typename T>
+__global__ void splitk_reduce_kernel(const T* __restrict__ P, int splits, int64_t M, int64_t N,
+                                     const int64_t* __restrict__ c_m, const int64_t* __restrict__ c_n, T* C,
+                                     double alpha, double beta) {
+  const int64_t total = M * N;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < splits; ++z) s += (double)P[(int64_t)z * total + idx];
+    int64_t m = idx / N, n = idx - m * N;
+    int64_t o = c_m[m] + c_n[n];
+    double v = alpha * s;
+    if (beta != 0.0) v += beta * (double)C[o];
+    C[o] = (T)v;
+  }
+}
+
+template <typename T, int BM, int BN, int BK>
+void launch_tile(const Args& a, int splits, hipStream_t s, bool akf, bool bkf) {
+  const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  dim3 grid((unsigned)tiles, 1, (unsigned)splits), block(256);
+  if (akf && bkf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, true, true>), grid, block, 0, s, a);
+  else if (akf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, true, false>), grid, block, 0, s, a);
+  else if (bkf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, false, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, false, false>), grid, block, 0, s, a);
+}
+
+template <int BM, int BN, int BK>
+void launch_bf16x3(const Args& a, int splits, hipStream_t s, bool akf, bool bkf) {
+  const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  dim3 grid((unsigned)tiles, 1, (unsigned)splits), block(256);
+  if (akf && bkf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, true, true>), grid, block, 0, s, a);
+  else if (akf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, true, false>), grid, block, 0, s, a);
+  else if (bkf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, false, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, false, false>), grid, block, 0, s, a);
+}
+
+}  // namespace
+
+void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
+  if (t.M <= 0 || t.N <= 0) return;
+  Args a{};
+  a.A = l.A;
+  a.B = l.B;
+  a.C = l.C;
+  a.a_m = t.a_m;
+  a.a_k = t.a_k;
+  a.b_k = t.b_k;
+  a.b_n = t.b_n;
+  a.c_m = t.c_m;
+  a.c_n = t.c_n;
+  a.M = t.M;
+  a.N = t.N;
+  a.K = t.K;
+  a.alpha = l.alpha;
+  a.beta = l.beta;
+  a.partial = nullptr;
+
+  // tile shape: large tiles when both extents allow, otherwise 64-wide
+  const bool bigm = t.M >= 128, bign = t.N >= 128;
+  const int BMsel = bigm ? 128 : 64, BNsel = bign ? 128 : 64;
+  const int64_t tiles = ((t.M + BMsel - 1) / BMsel) * ((t.N + BNsel - 1) / BNsel);
+  const int BK = (l.prec == Prec::BF16X3) ? 32 : 16;
+
+  // split-K when the output grid cannot fill the chip and K is long
+  int splits = l.splits;
+  if (splits <= 0) {
+    splits = 1;
+    const int64_t target = 1024;
+    while (tiles * splits < target && t.K / (splits * 2) >= 512 && splits < 64) splits *= 2;
+  }
+  int64_t kchunk = (t.K + splits - 1) / splits;
+  kchunk = ((kchunk + BK - 1) / BK) * BK;
+  splits = (int)std::max<int64_t>(1, (t.K + kchunk - 1) / kchunk);
+  a.kchunk = kchunk;
+
+  const size_t eb = (l.prec == Prec::F64) ? 8 : 4;
+  if (splits > 1) {
+    a.partial = ctx.buf("gett.partial", (size_t)splits * t.M * t.N * eb);
+  }
+  hipStream_t s = ctx.stream;
+  if (l.prec == Prec::F64) {
+    if (bigm && bign) launch_tile<double, 128, 128, 16>(a, splits, s, t.a_kfast, t.b_kfast);
+    else if (bigm) launch_tile<double, 128, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
+    else if (bign) launch_tile<double, 64, 128, 16>(a, splits, s, t.a_kfast, t.b_kfast);
+    else launch_tile<double, 64, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
+  } else if (l.prec == Prec::F32) {
+    if (bigm && bign) launch_tile<float, 128, 128, 16>(a, splits, s, t.a_kfast, t.b_kfast);
+    else if (bigm) launch_tile<float, 128, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
+    else if (bign) launch_tile<float, 64, 128, 16>(a, splits, s, t.a_kfast, t.b_kfast);
+    else launch_tile<float, 64, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
+  } else {
+    if (bigm && bign) launch_bf16x3<128, 128, 32>(a, splits, s, t.a_kfast, t.b_kfast);
+    else if (bigm) launch_bf16x3<128, 64, 32>(a, splits, s, t.a_kfast, t.b_kfast);
+    else if (bign) launch_bf16x3<64, 128, 32>(a, splits, s, t.a_kfast, t.b_kfast);
+    else launch_bf16x3<64, 64, 32>(a, splits, s, t.a_kfast, t.b_kfast);
+  }
+  MERA_HIP(hipGetLastError());
+  if (splits > 1) {
+    const int64_t total = t.M * t.N;
+    int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    if (l.prec == Prec::F64)
+      hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3(blocks), dim3(256), 0, s,
+                         static_cast<const double*>(a.partial), splits, t.M, t.N, t.c_m, t.c_n,
+                         static_cast<double*>(l.C), l.alpha, l.beta);
+    else
+      hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(blocks), dim3(256), 0, s,
+                         static_cast<const float*>(a.partial), splits, t.M, t.N, t.c_m, t.c_n,
+                         static_cast<float*>(l.C), l.alpha, l.beta);
+    MERA_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace mera

@@ -1,0 +1,504 @@
+// Binary-MERA energy and Euclidean gradient on the GPU.
+//
+// Geometry (Sec. 4, binary form): w_j sends site j of layer tau to sites (2j, 2j+1) below; the disentanglers of
+// a layer act on (2j+1, 2j+2). A 3-site operator on (2j, 2j+1, 2j+2) rises to (j-1, j, j+1) ("L" diagram),
+// one on (2j+1, 2j+2, 2j+3) to (j, j+1, j+2) ("R" diagram); the translation average is A = (A_L + A_R)/2.
+// Tensor legs: u[bl br tl tr], w[bl br t]; operators h[abc ABC] (kets lowercase).
+//
+// Each diagram is a pairwise contraction program (network.h). The two chi^9 steps of every diagram contract
+// a 6-leg operator with the composite (u w) over two legs, then over three legs, the contraction order
+// with the smallest multiply-add count for the binary 3-site maps (2 chi^9 + O(chi^8) per diagram).
+//
+// Energy and gradient (Sec. 4; App. B):
+//   h_0 = h3, h_tau = A_tau(h_{tau-1});  rho_s = fixed point of the scale-invariant descending map;
+//   e = Tr[h_T rho_s];  h~ solves <h~|(1 - A') = <h_T - e 1| with A' = A - |rho><1|;
+//   D of the scale-invariant tensors = derivative of Tr[A_s(h~) rho_s] with h~, rho_s held fixed;
+//   D of layer tau = derivative of Tr[A_tau(h_{tau-1}) rho_tau], rho_{tau-1} = D_tau(rho_tau).
+// Each layer derivative runs one diagram forward and back (reverse accumulation with cotangent rho). Since h
+// and rho are symmetric, the closed network is invariant under exchanging ket and bra, so the bra
+// occurrences of u and w have the same environments as the ket ones: only ket environments are formed and
+// counted twice, which with the 1/2 of the position average gives weight 1.
+#include "mera.h"
+
+#include <cmath>
+#include <functional>
+
+#include "linalg.h"
+#include "network.h"
+
+namespace mera {
+
+namespace {
+
+const char* const kAscL[] = {
+    "W1[epEP] = w[xep] * w[xEP]",
+    "W3[hrHR] = w[hyr] * w[HyR]",
+    "T1[aABCgh] = h[abcABC] * u[bcgh]",
+    "T2[aAghGH] = T1[aABCgh] * u[BCGH]",
+    "UW[daegq] = u[daef] * w[fgq]",
+    "T3[AhGHdeq] = T2[aAghGH] * UW[daegq]",
+    "T4[hHeqEQ] = T3[AhGHdeq] * UW[dAEGQ]",
+    "T5[hHqQpP] = T4[hHeqEQ] * W1[epEP]",
+    "out[pqrPQR] += 0.5 * T5[hHqQpP] * W3[hrHR]",
+};
+const char* const kAscR[] = {
+    "W1[epEP] = w[xep] * w[xEP]",
+    "W3[hrHR] = w[hyr] * w[HyR]",
+    "T1[cABCef] = h[abcABC] * u[abef]",
+    "T2[cCefEF] = T1[cABCef] * u[ABEF]",
+    "UW[cdhfq] = u[cdgh] * w[fgq]",
+    "T3[CeEFdhq] = T2[cCefEF] * UW[cdhfq]",
+    "T4[eEhqHQ] = T3[CeEFdhq] * UW[CdHFQ]",
+    "T5[eEqQrR] = T4[eEhqHQ] * W3[hrHR]",
+    "out[pqrPQR] += 0.5 * T5[eEqQrR] * W1[epEP]",
+};
+const char* const kDesL[] = {
+    "W1[epEP] = w[xep] * w[xEP]",
+    "W3[hrHR] = w[hyr] * w[HyR]",
+    "UW[daegq] = u[daef] * w[fgq]",
+    "dT5[pqPQhH] = rho[pqrPQR] * W3[hrHR]",
+    "dT4[qQhHeE] = dT5[pqPQhH] * W1[epEP]",
+    "dT3[qhHedAG] = dT4[qQhHeE] * UW[dAEGQ]",
+    "dT2[hHAGag] = dT3[qhHedAG] * UW[daegq]",
+    "dT1[hAagBC] = dT2[hHAGag] * u[BCGH]",
+    "out[abcABC] += 0.5 * dT1[hAagBC] * u[bcgh]",
+};
+const char* const kDesR[] = {
+    "W1[epEP] = w[xep] * w[xEP]",
+    "W3[hrHR] = w[hyr] * w[HyR]",
+    "UW[cdhfq] = u[cdgh] * w[fgq]",
+    "dT5[qrQReE] = rho[pqrPQR] * W1[epEP]",
+    "dT4[qQeEhH] = dT5[qrQReE] * W3[hrHR]",
+    "dT3[qeEhCdF] = dT4[qQeEhH] * UW[CdHFQ]",
+    "dT2[eECFcf] = dT3[qeEhCdF] * UW[cdhfq]",
+    "dT1[eCcfAB] = dT2[eECFcf] * u[ABEF]",
+    "out[abcABC] += 0.5 * dT1[eCcfAB] * u[abef]",
+};
+// forward of the L diagram, then reverse accumulation with cotangent rho
+const char* const kGradL[] = {
+    "W1[epEP] = w[xep] * w[xEP]",
+    "W3[hrHR] = w[hyr] * w[HyR]",
+    "T1[aABCgh] = h[abcABC] * u[bcgh]",
+    "T2[aAghGH] = T1[aABCgh] * u[BCGH]",
+    "UW[daegq] = u[daef] * w[fgq]",
+    "T3[AhGHdeq] = T2[aAghGH] * UW[daegq]",
+    "T4[hHeqEQ] = T3[AhGHdeq] * UW[dAEGQ]",
+    "T5[hHqQpP] = T4[hHeqEQ] * W1[epEP]",
+    "dT5[pqPQhH] = rho[pqrPQR] * W3[hrHR]",
+    "dW3[hHrR] = T5[hHqQpP] * rho[pqrPQR]",
+    "dT4[qQhHeE] = dT5[pqPQhH] * W1[epEP]",
+    "dW1[eEpP] = T4[hHeqEQ] * dT5[pqPQhH]",
+    "dT3[qhHedAG] = dT4[qQhHeE] * UW[dAEGQ]",
+    "dUW[agqed] = T2[aAghGH] * dT3[qhHedAG]",
+    "dT2[hHAGag] = dT3[qhHedAG] * UW[daegq]",
+    "dT1[hAagBC] = dT2[hHAGag] * u[BCGH]",
+    "Du[BCGH] += T1[aABCgh] * dT2[hHAGag]",
+    "rhoout[abcABC] += 0.5 * dT1[hAagBC] * u[bcgh]",
+    "Du[daef] += dUW[agqed] * w[fgq]",
+    "Dw[fgq] += u[daef] * dUW[agqed]",
+    "Dw[xep] += dW1[eEpP] * w[xEP]",
+    "Dw[hyr] += dW3[hHrR] * w[HyR]",
+};
+const char* const kGradR[] = {
+    "W1[epEP] = w[xep] * w[xEP]",
+    "W3[hrHR] = w[hyr] * w[HyR]",
+    "T1[cABCef] = h[abcABC] * u[abef]",
+    "T2[cCefEF] = T1[cABCef] * u[ABEF]",
+    "UW[cdhfq] = u[cdgh] * w[fgq]",
+    "T3[CeEFdhq] = T2[cCefEF] * UW[cdhfq]",
+    "T4[eEhqHQ] = T3[CeEFdhq] * UW[CdHFQ]",
+    "T5[eEqQrR] = T4[eEhqHQ] * W3[hrHR]",
+    "dT5[qrQReE] = rho[pqrPQR] * W1[epEP]",
+    "dW1[eEpP] = T5[eEqQrR] * rho[pqrPQR]",
+    "dT4[qQeEhH] = dT5[qrQReE] * W3[hrHR]",
+    "dW3[hHrR] = T4[eEhqHQ] * dT5[qrQReE]",
+    "dT3[qeEhCdF] = dT4[qQeEhH] * UW[CdHFQ]",
+    "dUW[cfqhd] = T2[cCefEF] * dT3[qeEhCdF]",
+    "dT2[eECFcf] = dT3[qeEhCdF] * UW[cdhfq]",
+    "dT1[eCcfAB] = dT2[eECFcf] * u[ABEF]",
+    "Du[ABEF] += T1[cABCef] * dT2[eECFcf]",
+    "rhoout[abcABC] += 0.5 * dT1[eCcfAB] * u[abef]",
+    "Du[cdgh] += dUW[cfqhd] * w[fgq]",
+    "Dw[fgq] += u[cdgh] * dUW[cfqhd]",
+    "Dw[xep] += dW1[eEpP] * w[xEP]",
+    "Dw[hyr] += dW3[hHrR] * w[HyR]",
+};
+// reduced density matrix on the two top legs of u from the two-site marginal above (Sec. 4, rho_v)
+const char* const kRhoU[] = {
+    "Z1[epEP] = w[xep] * w[xEP]",
+    "Z3[fqFQ] = w[fyq] * w[FyQ]",
+    "R1[eEqQ] = Z1[epEP] * rho2[pqPQ]",
+    "rhou[efEF] = R1[eEqQ] * Z3[fqFQ]",
+};
+
+template <size_t N>
+std::vector<std::string> lines(const char* const (&a)[N]) {
+  return std::vector<std::string>(a, a + N);
+}
+
+struct Programs {
+  Program asc[2], des[2], grad[2], rhou;
+  Programs() {
+    const std::vector<std::string> ext = {"h", "u", "w", "rho", "out", "Du", "Dw", "rhoout", "rho2", "rhou"};
+    asc[0] = Program::parse("ascL", lines(kAscL), ext);
+    asc[1] = Program::parse("ascR", lines(kAscR), ext);
+    des[0] = Program::parse("desL", lines(kDesL), ext);
+    des[1] = Program::parse("desR", lines(kDesR), ext);
+    grad[0] = Program::parse("gradL", lines(kGradL), ext);
+    grad[1] = Program::parse("gradR", lines(kGradR), ext);
+    rhou = Program::parse("rhou", lines(kRhoU), ext);
+  }
+};
+
+const Programs& programs() {
+  static const Programs p;
+  return p;
+}
+
+LegDims legs(int a, int b) {
+  LegDims d;
+  d.fill(0);
+  for (char c : std::string("abcdefghxyABCEFGH")) d[(unsigned char)c] = a;
+  for (char c : std::string("pqrPQR")) d[(unsigned char)c] = b;
+  return d;
+}
+
+int64_t p6(int64_t x) { return x * x * x * x * x * x; }
+
+// Device element pointers of the contraction precision for one layer's tensors.
+struct LayerTensors {
+  void* u;
+  void* w;
+};
+
+}  // namespace
+
+std::vector<LayerDim> layer_dims(const mera_shape& s) {
+  MERA_CHECK(s.T >= 1 && s.d >= 2 && s.chi >= 2, MERA_EINVAL, "shape: need T >= 1, d >= 2, chi >= 2");
+  std::vector<LayerDim> out;
+  int a = s.d;
+  for (int t = 0; t < s.T; ++t) {
+    int b = (int)std::min<int64_t>((int64_t)s.chi, (int64_t)a * a);
+    out.push_back({a, b});
+    a = b;
+  }
+  MERA_CHECK(a == s.chi, MERA_EINVAL,
+             "top transition dimension " + std::to_string(a) + " != chi " + std::to_string(s.chi));
+  out.push_back({s.chi, s.chi});
+  return out;
+}
+
+namespace {
+
+void ascend_raw(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr in, VPtr out, Prec prec) {
+  fill(ctx, out, p6(L.b), 0.0);
+  const LegDims d = legs(L.a, L.b);
+  for (int s = 0; s < 2; ++s)
+    run_program(ctx, programs().asc[s], d, {{"h", in.p}, {"u", t.u}, {"w", t.w}, {"out", out.p}}, prec);
+  symmetrize(ctx, out, (int64_t)L.b * L.b * L.b);
+}
+
+void descend_raw(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr in, VPtr out, Prec prec) {
+  fill(ctx, out, p6(L.a), 0.0);
+  const LegDims d = legs(L.a, L.b);
+  for (int s = 0; s < 2; ++s)
+    run_program(ctx, programs().des[s], d, {{"rho", in.p}, {"u", t.u}, {"w", t.w}, {"out", out.p}}, prec);
+  symmetrize(ctx, out, (int64_t)L.a * L.a * L.a);
+}
+
+// D_u, D_w (+)= derivative of Tr[A(h) rho]; rhoout = D(rho). Du, Dw, rhoout are overwritten.
+void layer_grad(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr h, VPtr rho, VPtr Du, VPtr Dw, VPtr rhoout,
+                Prec prec) {
+  const int64_t a2 = (int64_t)L.a * L.a;
+  fill(ctx, Du, a2 * a2, 0.0);
+  fill(ctx, Dw, a2 * L.b, 0.0);
+  fill(ctx, rhoout, p6(L.a), 0.0);
+  const LegDims d = legs(L.a, L.b);
+  for (int s = 0; s < 2; ++s)
+    run_program(ctx, programs().grad[s], d,
+                {{"h", h.p}, {"rho", rho.p}, {"u", t.u}, {"w", t.w}, {"Du", Du.p}, {"Dw", Dw.p},
+                 {"rhoout", rhoout.p}},
+                prec);
+  symmetrize(ctx, rhoout, (int64_t)L.a * L.a * L.a);
+}
+
+struct KStat {
+  int apps = 0;
+  double res = 0.0;
+  bool converged = false;
+};
+
+// Restarted GMRES(m) for op(x) = b, starting from x (in/out). Vectors of length n in precision `prec`,
+// scalars in FP64; classical Gram-Schmidt applied twice; restart residual from the Arnoldi relation.
+KStat gmres(Ctx& ctx, const std::function<void(VPtr, VPtr)>& op, VPtr b, VPtr x, int64_t n, int m, double tol,
+            int max_restarts, Prec prec) {
+  KStat st;
+  const size_t bytes = (size_t)n * elem_bytes(prec);
+  std::vector<VPtr> V(m + 1);
+  for (int i = 0; i <= m; ++i) V[i] = VPtr{ctx.buf("krylov.v" + std::to_string(i), bytes), prec};
+  VPtr R{ctx.buf("krylov.r", bytes), prec};
+  const double bnorm = nrm2(ctx, b, n);
+  MERA_CHECK(std::isfinite(bnorm), MERA_ENONFINITE, "non-finite right-hand side in Krylov solve");
+  if (bnorm == 0.0) {
+    fill(ctx, x, n, 0.0);
+    st.converged = true;
+    return st;
+  }
+  op(x, V[0]);
+  st.apps++;
+  axpby(ctx, 1.0, b, -1.0, V[0], n);  // V0 = b - A x
+  double beta = nrm2(ctx, V[0], n);
+  MERA_CHECK(std::isfinite(beta), MERA_ENONFINITE, "non-finite residual in Krylov solve");
+  std::vector<double> H((m + 1) * m), Hr((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  for (int restart = 0; restart <= max_restarts; ++restart) {
+    st.res = beta / bnorm;
+    if (beta <= tol * bnorm) {
+      st.converged = true;
+      break;
+    }
+    if (restart == max_restarts) break;
+    scal(ctx, 1.0 / beta, V[0], n);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      op(V[j], V[j + 1]);
+      st.apps++;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i <= j; ++i) {
+          double hij = dot(ctx, V[j + 1], V[i], n);
+          H[i * m + j] += hij;
+          axpby(ctx, -hij, V[i], 1.0, V[j + 1], n);
+        }
+      double hn = nrm2(ctx, V[j + 1], n);
+      MERA_CHECK(std::isfinite(hn), MERA_ENONFINITE, "non-finite Krylov vector");
+      H[(j + 1) * m + j] = hn;
+      if (hn > 0.0) scal(ctx, 1.0 / hn, V[j + 1], n);
+      // rotated copy for the least-squares solve
+      for (int i = 0; i <= j + 1; ++i) Hr[i * m + j] = H[i * m + j];
+      for (int i = 0; i < j; ++i) {
+        double t0 = cs[i] * Hr[i * m + j] + sn[i] * Hr[(i + 1) * m + j];
+        double t1 = -sn[i] * Hr[i * m + j] + cs[i] * Hr[(i + 1) * m + j];
+        Hr[i * m + j] = t0;
+        Hr[(i + 1) * m + j] = t1;
+      }
+      double den = std::hypot(Hr[j * m + j], Hr[(j + 1) * m + j]);
+      cs[j] = den > 0 ? Hr[j * m + j] / den : 1.0;
+      sn[j] = den > 0 ? Hr[(j + 1) * m + j] / den : 0.0;
+      Hr[j * m + j] = den;
+      Hr[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      if (std::fabs(g[j + 1]) <= tol * bnorm || hn == 0.0) break;
+    }
+    // back substitution
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int l = i + 1; l < k; ++l) s -= Hr[i * m + l] * y[l];
+      y[i] = s / Hr[i * m + i];
+    }
+    for (int i = 0; i < k; ++i) axpby(ctx, y[i], V[i], 1.0, x, n);
+    // residual r = V_{0..k} (beta e1 - Hbar y)
+    std::vector<double> c(k + 1, 0.0);
+    c[0] = beta;
+    for (int i = 0; i <= k; ++i)
+      for (int l = 0; l < k; ++l) c[i] -= H[i * m + l] * y[l];
+    fill(ctx, R, n, 0.0);
+    for (int i = 0; i <= k; ++i) axpby(ctx, c[i], V[i], 1.0, R, n);
+    std::swap(V[0], R);
+    beta = nrm2(ctx, V[0], n);
+    MERA_CHECK(std::isfinite(beta), MERA_ENONFINITE, "non-finite residual in Krylov solve");
+  }
+  // keep the scratch names stable for the next call (V[0] may have been swapped with R)
+  return st;
+}
+
+}  // namespace
+
+void ascend_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, Prec prec, const double* hin,
+               double* hout) {
+  const int64_t a2 = (int64_t)L.a * L.a;
+  if (prec == Prec::F64) {
+    ascend_raw(ctx, L, {(void*)u, (void*)w}, VPtr{(void*)hin, prec}, VPtr{hout, prec}, prec);
+    return;
+  }
+  void* us = ctx.buf("op.u", a2 * a2 * 4);
+  void* ws = ctx.buf("op.w", a2 * L.b * 4);
+  void* hi = ctx.buf("op.in", p6(L.a) * 4);
+  void* ho = ctx.buf("op.out", p6(L.b) * 4);
+  copy(ctx, VPtr{us, prec}, VPtr{(void*)u, Prec::F64}, a2 * a2);
+  copy(ctx, VPtr{ws, prec}, VPtr{(void*)w, Prec::F64}, a2 * L.b);
+  copy(ctx, VPtr{hi, prec}, VPtr{(void*)hin, Prec::F64}, p6(L.a));
+  ascend_raw(ctx, L, {us, ws}, VPtr{hi, prec}, VPtr{ho, prec}, prec);
+  copy(ctx, VPtr{hout, Prec::F64}, VPtr{ho, prec}, p6(L.b));
+}
+
+void descend_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, Prec prec, const double* rin,
+                double* rout) {
+  const int64_t a2 = (int64_t)L.a * L.a;
+  if (prec == Prec::F64) {
+    descend_raw(ctx, L, {(void*)u, (void*)w}, VPtr{(void*)rin, prec}, VPtr{rout, prec}, prec);
+    return;
+  }
+  void* us = ctx.buf("op.u", a2 * a2 * 4);
+  void* ws = ctx.buf("op.w", a2 * L.b * 4);
+  void* ri = ctx.buf("op.in", p6(L.b) * 4);
+  void* ro = ctx.buf("op.out", p6(L.a) * 4);
+  copy(ctx, VPtr{us, prec}, VPtr{(void*)u, Prec::F64}, a2 * a2);
+  copy(ctx, VPtr{ws, prec}, VPtr{(void*)w, Prec::F64}, a2 * L.b);
+  copy(ctx, VPtr{ri, prec}, VPtr{(void*)rin, Prec::F64}, p6(L.b));
+  descend_raw(ctx, L, {us, ws}, VPtr{ri, prec}, VPtr{ro, prec}, prec);
+  copy(ctx, VPtr{rout, Prec::F64}, VPtr{ro, prec}, p6(L.a));
+}
+
+EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const double* h3, Prec prec, Warm* warm,
+                    const KrylovOpts& ko, const GradOut& out) {
+  const std::vector<LayerDim> dims = layer_dims(shape);
+  const int T = shape.T;
+  const int chi = shape.chi;
+  const int64_t chi3 = (int64_t)chi * chi * chi, n6 = chi3 * chi3;
+  const size_t eb = elem_bytes(prec);
+  const double macs0 = ctx.macs;
+  EvalOut res;
+  MERA_CHECK((int)pt.u.size() == T + 1 && (int)pt.w.size() == T + 1, MERA_EINVAL, "need T+1 tensors u and w");
+  MERA_CHECK((int)out.Du.size() == T + 1 && (int)out.Dw.size() == T + 1, MERA_EINVAL, "need T+1 outputs");
+
+  // tensors in contraction precision
+  std::vector<LayerTensors> lt(T + 1);
+  for (int t = 0; t <= T; ++t) {
+    const int64_t a2 = (int64_t)dims[t].a * dims[t].a;
+    if (prec == Prec::F64) {
+      lt[t] = {(void*)pt.u[t], (void*)pt.w[t]};
+    } else {
+      lt[t].u = ctx.buf("shadow.u" + std::to_string(t), a2 * a2 * 4);
+      lt[t].w = ctx.buf("shadow.w" + std::to_string(t), a2 * dims[t].b * 4);
+      copy(ctx, VPtr{lt[t].u, prec}, VPtr{(void*)pt.u[t], Prec::F64}, a2 * a2);
+      copy(ctx, VPtr{lt[t].w, prec}, VPtr{(void*)pt.w[t], Prec::F64}, a2 * dims[t].b);
+    }
+  }
+
+  // ascend the Hamiltonian through the transition layers
+  std::vector<VPtr> hs(T + 1);
+  hs[0] = VPtr{ctx.buf("hs0", p6(shape.d) * eb), prec};
+  copy(ctx, hs[0], VPtr{(void*)h3, Prec::F64}, p6(shape.d));
+  for (int t = 0; t < T; ++t) {
+    hs[t + 1] = VPtr{ctx.buf("hs" + std::to_string(t + 1), p6(dims[t].b) * eb), prec};
+    ascend_raw(ctx, dims[t], lt[t], hs[t], hs[t + 1], prec);
+  }
+
+  const LayerDim& S = dims[T];
+  const double tol = ko.tol > 0 ? ko.tol : (prec == Prec::F64 ? 1e-13 : 1e-7);
+  const int kdim = ko.dim > 0 ? ko.dim : 4;
+  const int kres = ko.max_restarts > 0 ? ko.max_restarts : 200;
+
+  // scale-invariant density matrix: x - D(x) + Tr[x] sigma = sigma, sigma = warm start with unit trace
+  VPtr rho{ctx.buf("rho_s", n6 * eb), prec};
+  VPtr sigma{ctx.buf("sigma", n6 * eb), prec};
+  VPtr tmp{ctx.buf("ktmp", n6 * eb), prec};
+  if (warm && warm->has_rho && warm->chi == chi) {
+    copy(ctx, rho, VPtr{warm->rho.ptr, Prec::F64}, n6);
+    double tr = trace(ctx, rho, chi3);
+    scal(ctx, 1.0 / tr, rho, n6);
+  } else {
+    fill(ctx, rho, n6, 0.0);
+    add_diag(ctx, rho, chi3, 1.0 / (double)chi3);
+  }
+  copy(ctx, sigma, rho, n6);
+  auto op_rho = [&](VPtr in, VPtr o) {
+    descend_raw(ctx, S, lt[T], in, o, prec);
+    axpby(ctx, 1.0, in, -1.0, o, n6);
+    axpby(ctx, trace(ctx, in, chi3), sigma, 1.0, o, n6);
+  };
+  KStat kr = gmres(ctx, op_rho, sigma, rho, n6, kdim, tol, kres, prec);
+  MERA_CHECK(kr.converged, MERA_ENOCONV,
+             "fixed-point solve did not converge (residual " + std::to_string(kr.res) + ")");
+  symmetrize(ctx, rho, chi3);
+  {
+    double tr = trace(ctx, rho, chi3);
+    MERA_CHECK(std::isfinite(tr) && tr != 0.0, MERA_ENONFINITE, "bad trace of the fixed point");
+    scal(ctx, 1.0 / tr, rho, n6);
+  }
+  res.app_rho = kr.apps;
+  res.res_rho = kr.res;
+
+  const double e = dot(ctx, hs[T], rho, n6);
+  MERA_CHECK(std::isfinite(e), MERA_ENONFINITE, "non-finite energy");
+  res.energy = e;
+
+  // h~: x - A(x) + Tr[x rho] 1 = h_T - e 1
+  VPtr hp{ctx.buf("hprime", n6 * eb), prec};
+  VPtr ht{ctx.buf("htilde", n6 * eb), prec};
+  copy(ctx, hp, hs[T], n6);
+  add_diag(ctx, hp, chi3, -e);
+  if (warm && warm->has_ht && warm->chi == chi) copy(ctx, ht, VPtr{warm->ht.ptr, Prec::F64}, n6);
+  else copy(ctx, ht, hp, n6);
+  auto op_ht = [&](VPtr in, VPtr o) {
+    ascend_raw(ctx, S, lt[T], in, o, prec);
+    axpby(ctx, 1.0, in, -1.0, o, n6);
+    add_diag(ctx, o, chi3, dot(ctx, in, rho, n6));
+  };
+  KStat kh = gmres(ctx, op_ht, hp, ht, n6, kdim, tol, kres, prec);
+  MERA_CHECK(kh.converged, MERA_ENOCONV, "h~ solve did not converge (residual " + std::to_string(kh.res) + ")");
+  symmetrize(ctx, ht, chi3);
+  add_diag(ctx, ht, chi3, -dot(ctx, ht, rho, n6));  // gauge Tr[h~ rho] = 0
+  res.app_ht = kh.apps;
+  res.res_ht = kh.res;
+
+  if (warm) {
+    warm->chi = chi;
+    warm->rho.ensure(n6 * 8);
+    warm->ht.ensure(n6 * 8);
+    copy(ctx, VPtr{warm->rho.ptr, Prec::F64}, rho, n6);
+    copy(ctx, VPtr{warm->ht.ptr, Prec::F64}, ht, n6);
+    warm->has_rho = warm->has_ht = true;
+  }
+
+  // gradients, top down; rl[t] = density matrix at the top of layer t (rl[T] = rho_s)
+  std::vector<VPtr> rl(T + 1);
+  rl[T] = rho;
+  for (int t = T; t >= 0; --t) {
+    const LayerDim& L = dims[t];
+    const int64_t a2 = (int64_t)L.a * L.a;
+    VPtr Du, Dw;
+    if (prec == Prec::F64) {
+      Du = VPtr{out.Du[t], prec};
+      Dw = VPtr{out.Dw[t], prec};
+    } else {
+      Du = VPtr{ctx.buf("Dacc.u", a2 * a2 * 4), prec};
+      Dw = VPtr{ctx.buf("Dacc.w", a2 * L.b * 4), prec};
+    }
+    const VPtr hin = (t == T) ? ht : hs[t];
+    const VPtr rtop = (t == T) ? rho : rl[t + 1];
+    // the descended matrix is the top of layer t-1; it is not needed below layer 0 or for the
+    // scale-invariant layer, whose bottom is rho_s itself
+    const bool keep = (t >= 1 && t < T);
+    VPtr rdown{ctx.buf(keep ? "rl" + std::to_string(t) : std::string("rl.discard"), p6(L.a) * eb), prec};
+    layer_grad(ctx, L, lt[t], hin, rtop, Du, Dw, rdown, prec);
+    if (keep) rl[t] = rdown;
+    if (prec != Prec::F64) {
+      copy(ctx, VPtr{out.Du[t], Prec::F64}, Du, a2 * a2);
+      copy(ctx, VPtr{out.Dw[t], Prec::F64}, Dw, a2 * L.b);
+    }
+  }
+
+  if (!out.rho_u.empty()) {
+    MERA_CHECK((int)out.rho_u.size() == T + 1 && (int)out.rho_w.size() == T + 1, MERA_EINVAL,
+               "need T+1 preconditioner outputs");
+    for (int t = 0; t <= T; ++t) {
+      const LayerDim& L = dims[t];
+      VPtr rtop = (t == T) ? rho : rl[t + 1];
+      double* r2 = static_cast<double*>(ctx.buf("rdm.rho2", (size_t)L.b * L.b * L.b * L.b * 8));
+      rho_marginals(ctx, rtop, L.b, out.rho_w[t], r2);
+      symmetrize(ctx, VPtr{out.rho_w[t], Prec::F64}, L.b);
+      run_program(ctx, programs().rhou, legs(L.a, L.b),
+                  {{"w", (void*)pt.w[t]}, {"rho2", r2}, {"rhou", out.rho_u[t]}}, Prec::F64);
+      symmetrize(ctx, VPtr{out.rho_u[t], Prec::F64}, (int64_t)L.a * L.a);
+    }
+  }
+  res.macs = ctx.macs - macs0;
+  return res;
+}
+
+}  // namespace mera

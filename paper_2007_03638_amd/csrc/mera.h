@@ -1,0 +1,57 @@
+// Binary-MERA energy and Euclidean gradient (Sec. 4 and App. B of arXiv:2007.03638).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+#include "vec.h"
+
+namespace mera {
+
+struct LayerDim {
+  int a, b;  // bottom and top leg dimension of the layer
+};
+
+// Transition layers 0..T-1 then the scale-invariant layer T (a = b = chi). Throws MERA_EINVAL if b_T != chi.
+std::vector<LayerDim> layer_dims(const mera_shape& s);
+
+// Device views of one evaluation point, all FP64 row-major (u: a^2 x a^2, w: a^2 x b).
+struct Point {
+  std::vector<const double*> u, w;
+};
+
+struct Warm {
+  int chi = 0;
+  bool has_rho = false, has_ht = false;
+  DevBuf rho, ht;  // FP64 chi^6
+};
+
+struct KrylovOpts {
+  int dim = 4;
+  int max_restarts = 200;
+  double tol = 0.0;  // 0: precision default
+};
+
+struct EvalOut {
+  double energy = 0;
+  int app_rho = 0, app_ht = 0;
+  double res_rho = 0, res_ht = 0;
+  double macs = 0;
+};
+
+// Gradient outputs (FP64 device, caller-owned), and optional preconditioner density matrices.
+struct GradOut {
+  std::vector<double*> Du, Dw;
+  std::vector<double*> rho_u, rho_w;  // may be empty
+};
+
+EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const double* h3, Prec prec, Warm* warm,
+                    const KrylovOpts& ko, const GradOut& out);
+
+// One layer map on FP64 device operators (converted internally for FP32/BF16X3).
+void ascend_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, Prec prec, const double* hin,
+               double* hout);
+void descend_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, Prec prec, const double* rin,
+                double* rout);
+
+}  // namespace mera

@@ -1,0 +1,251 @@
+// Contraction-program planner and executor (see network.h).
+#include "network.h"
+
+#include <algorithm>
+#include <cctype>
+#include <sstream>
+
+namespace mera {
+
+namespace {
+
+std::string trim(const std::string& s) {
+  size_t a = s.find_first_not_of(" \t"), b = s.find_last_not_of(" \t");
+  return a == std::string::npos ? std::string() : s.substr(a, b - a + 1);
+}
+
+// "NAME[labels]" -> (NAME, labels)
+std::pair<std::string, std::string> parse_ref(const std::string& tok) {
+  std::string t = trim(tok);
+  size_t lb = t.find('['), rb = t.find(']');
+  if (lb == std::string::npos || rb == std::string::npos || rb < lb)
+    throw Error(MERA_EINVAL, "bad tensor reference '" + t + "'");
+  return {trim(t.substr(0, lb)), t.substr(lb + 1, rb - lb - 1)};
+}
+
+int64_t roundup(int64_t x, int64_t m) { return ((x + m - 1) / m) * m; }
+
+}  // namespace
+
+int Program::id(const std::string& n) const {
+  for (size_t i = 0; i < tensors.size(); ++i)
+    if (tensors[i] == n) return (int)i;
+  return -1;
+}
+
+Program Program::parse(const std::string& name, const std::vector<std::string>& lines,
+                       const std::vector<std::string>& externals) {
+  Program p;
+  p.name = name;
+  auto get = [&](const std::string& n, const std::string& labels) {
+    int i = p.id(n);
+    if (i < 0) {
+      p.tensors.push_back(n);
+      p.layout.push_back(labels);
+      p.external.push_back(std::find(externals.begin(), externals.end(), n) != externals.end());
+      return (int)p.tensors.size() - 1;
+    }
+    if (p.layout[i].size() != labels.size())
+      throw Error(MERA_EINVAL, "rank mismatch for tensor " + n + " in program " + name);
+    return i;
+  };
+  for (const std::string& raw : lines) {
+    std::string line = trim(raw);
+    if (line.empty()) continue;
+    bool acc = false;
+    size_t eq = line.find("+=");
+    if (eq != std::string::npos) {
+      acc = true;
+    } else {
+      eq = line.find('=');
+      if (eq == std::string::npos) throw Error(MERA_EINVAL, "no '=' in '" + line + "'");
+    }
+    std::string lhs = line.substr(0, eq);
+    std::string rhs = line.substr(eq + (acc ? 2 : 1));
+    std::vector<std::string> parts;
+    std::stringstream ss(rhs);
+    std::string tok;
+    while (std::getline(ss, tok, '*')) parts.push_back(trim(tok));
+    double alpha = 1.0;
+    if (parts.size() == 3) {
+      alpha = std::stod(parts[0]);
+      parts.erase(parts.begin());
+    }
+    if (parts.size() != 2) throw Error(MERA_EINVAL, "need two operands in '" + line + "'");
+    auto c = parse_ref(lhs), a = parse_ref(parts[0]), b = parse_ref(parts[1]);
+    StepDef st;
+    st.a = get(a.first, a.second);
+    st.b = get(b.first, b.second);
+    st.c = get(c.first, c.second);
+    st.la = a.second;
+    st.lb = b.second;
+    st.lc = c.second;
+    st.alpha = alpha;
+    st.accumulate = acc;
+    p.steps.push_back(st);
+  }
+  return p;
+}
+
+namespace {
+
+// Row-major strides of a tensor whose axes carry labels `lab` with extents from `dims`.
+std::vector<int64_t> strides_of(const std::string& lab, const LegDims& dims) {
+  std::vector<int64_t> s(lab.size());
+  int64_t acc = 1;
+  for (int i = (int)lab.size() - 1; i >= 0; --i) {
+    s[i] = acc;
+    acc *= dims[(unsigned char)lab[i]];
+  }
+  return s;
+}
+
+int64_t stride_of(const std::string& lab, const std::vector<int64_t>& st, char c) {
+  size_t pos = lab.find(c);
+  return pos == std::string::npos ? 0 : st[pos];
+}
+
+// Offsets of the flattened index over `legs` (last fastest) for a tensor with labels/strides.
+void fill_table(std::vector<int64_t>& out, const std::string& legs, const LegDims& dims, const std::string& lab,
+                const std::vector<int64_t>& st, int64_t padded) {
+  int64_t total = 1;
+  for (char c : legs) total *= dims[(unsigned char)c];
+  out.assign(padded, 0);
+  std::vector<int64_t> idx(legs.size(), 0), sl(legs.size());
+  for (size_t i = 0; i < legs.size(); ++i) sl[i] = stride_of(lab, st, legs[i]);
+  int64_t off = 0;
+  for (int64_t f = 0; f < total; ++f) {
+    out[f] = off;
+    // increment multi-index (last fastest), maintain offset
+    for (int i = (int)legs.size() - 1; i >= 0; --i) {
+      idx[i]++;
+      off += sl[i];
+      if (idx[i] < dims[(unsigned char)legs[i]]) break;
+      off -= sl[i] * idx[i];
+      idx[i] = 0;
+    }
+  }
+}
+
+PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegDims& dims) {
+  const StepDef& s = prog.steps[si];
+  std::string key = prog.name + "#" + std::to_string(si);
+  std::string all = s.la + s.lb + s.lc;
+  std::sort(all.begin(), all.end());
+  all.erase(std::unique(all.begin(), all.end()), all.end());
+  for (char c : all) key += ":" + std::to_string(dims[(unsigned char)c]);
+  auto it = ctx.plans->map.find(key);
+  if (it != ctx.plans->map.end()) return *it->second;
+
+  auto has = [](const std::string& s_, char c) { return s_.find(c) != std::string::npos; };
+  std::string Ml, Nl, Kl;
+  for (char c : s.la) {
+    bool inb = has(s.lb, c), inc = has(s.lc, c);
+    if (inc && !inb) Ml += c;
+    else if (inb && !inc) Kl += c;
+    else throw Error(MERA_EINVAL, prog.name + ": leg '" + std::string(1, c) + "' of A is batch or traced");
+  }
+  for (char c : s.lb) {
+    bool ina = has(s.la, c), inc = has(s.lc, c);
+    if (inc && !ina) Nl += c;
+    else if (!(ina && !inc)) throw Error(MERA_EINVAL, prog.name + ": leg of B is batch or traced");
+  }
+  for (char c : s.lc)
+    if (!has(Ml, c) && !has(Nl, c)) throw Error(MERA_EINVAL, prog.name + ": output leg not produced");
+  if (Ml.size() + Nl.size() != s.lc.size()) throw Error(MERA_EINVAL, prog.name + ": repeated output leg");
+  for (char c : all)
+    if (dims[(unsigned char)c] <= 0) throw Error(MERA_EINVAL, prog.name + ": unset leg extent");
+
+  const bool a_kfast = !Kl.empty() && has(Kl, s.la.back());
+  const bool b_kfast = !Kl.empty() && has(Kl, s.lb.back());
+  if (!a_kfast && b_kfast) {
+    // order K legs as B stores them so B's unit-stride leg is fastest in k
+    std::string k2;
+    for (char c : s.lb)
+      if (has(Kl, c)) k2 += c;
+    Kl = k2;
+  }
+  auto ext = [&](const std::string& legs) {
+    int64_t t = 1;
+    for (char c : legs) t *= dims[(unsigned char)c];
+    return t;
+  };
+  const int64_t M = ext(Ml), N = ext(Nl), K = ext(Kl);
+  const int64_t Mp = roundup(M, 128), Np = roundup(N, 128), Kp = roundup(K, 32);
+  auto sa = strides_of(s.la, dims), sb = strides_of(s.lb, dims), sc = strides_of(s.lc, dims);
+  std::vector<int64_t> host;
+  host.reserve(2 * Mp + 2 * Np + 2 * Kp);
+  std::vector<int64_t> tmp;
+  size_t off_am, off_ak, off_bk, off_bn, off_cm, off_cn;
+  off_am = host.size(); fill_table(tmp, Ml, dims, s.la, sa, Mp); host.insert(host.end(), tmp.begin(), tmp.end());
+  off_ak = host.size(); fill_table(tmp, Kl, dims, s.la, sa, Kp); host.insert(host.end(), tmp.begin(), tmp.end());
+  off_bk = host.size(); fill_table(tmp, Kl, dims, s.lb, sb, Kp); host.insert(host.end(), tmp.begin(), tmp.end());
+  off_bn = host.size(); fill_table(tmp, Nl, dims, s.lb, sb, Np); host.insert(host.end(), tmp.begin(), tmp.end());
+  off_cm = host.size(); fill_table(tmp, Ml, dims, s.lc, sc, Mp); host.insert(host.end(), tmp.begin(), tmp.end());
+  off_cn = host.size(); fill_table(tmp, Nl, dims, s.lc, sc, Np); host.insert(host.end(), tmp.begin(), tmp.end());
+
+  auto e = std::make_unique<PlanCache::Entry>();
+  e->tables.alloc(host.size() * sizeof(int64_t));
+  MERA_HIP(hipMemcpy(e->tables.ptr, host.data(), host.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  const int64_t* base = e->tables.as<int64_t>();
+  e->t.a_m = base + off_am;
+  e->t.a_k = base + off_ak;
+  e->t.b_k = base + off_bk;
+  e->t.b_n = base + off_bn;
+  e->t.c_m = base + off_cm;
+  e->t.c_n = base + off_cn;
+  e->t.M = M;
+  e->t.N = N;
+  e->t.K = K;
+  e->t.a_kfast = a_kfast;
+  e->t.b_kfast = b_kfast;
+  e->macs = (double)M * (double)N * (double)K;
+  auto& ref = *e;
+  ctx.plans->map.emplace(key, std::move(e));
+  return ref;
+}
+
+}  // namespace
+
+void run_program(Ctx& ctx, const Program& prog, const LegDims& dims, const std::vector<void*>& ext, Prec prec) {
+  if (ext.size() != prog.tensors.size()) throw Error(MERA_EINVAL, prog.name + ": binding count");
+  const size_t eb = elem_bytes(prec);
+  std::vector<void*> ptr(prog.tensors.size(), nullptr);
+  for (size_t i = 0; i < prog.tensors.size(); ++i) {
+    if (prog.external[i]) {
+      if (!ext[i]) throw Error(MERA_EINVAL, prog.name + ": unbound tensor " + prog.tensors[i]);
+      ptr[i] = ext[i];
+    } else {
+      int64_t n = 1;
+      for (char c : prog.layout[i]) n *= dims[(unsigned char)c];
+      ptr[i] = ctx.buf("net/" + prog.tensors[i], (size_t)n * eb);
+    }
+  }
+  for (size_t si = 0; si < prog.steps.size(); ++si) {
+    const StepDef& s = prog.steps[si];
+    PlanCache::Entry& e = plan_step(ctx, prog, si, dims);
+    GettLaunch l;
+    l.A = ptr[s.a];
+    l.B = ptr[s.b];
+    l.C = ptr[s.c];
+    l.alpha = s.alpha;
+    l.beta = s.accumulate ? 1.0 : 0.0;
+    l.prec = prec;
+    l.splits = 0;
+    gett_run(ctx, e.t, l);
+    ctx.macs += e.macs;
+  }
+}
+
+void run_program(Ctx& ctx, const Program& prog, const LegDims& dims,
+                 const std::vector<std::pair<std::string, void*>>& bind, Prec prec) {
+  std::vector<void*> ext(prog.tensors.size(), nullptr);
+  for (auto& b : bind) {
+    int i = prog.id(b.first);
+    if (i < 0) continue;
+    ext[i] = b.second;
+  }
+  run_program(ctx, prog, dims, ext, prec);
+}
+
+}  // namespace mera

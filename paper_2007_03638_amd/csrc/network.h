@@ -1,0 +1,62 @@
+// Contraction programs: a tensor network written as an ordered list of pairwise contractions
+//   C[labels] (+)= alpha * A[labels] * B[labels]
+// over named tensors. Each tensor is stored dense and row-major over the leg order in which it is declared
+// (the label string of its first appearance, or of its binding for external tensors); the label strings of
+// later uses name the same axes positionally, so one buffer can appear with ket labels in one step and bra
+// labels in another. A step's legs split into M (A and C only), N (B and C only) and K (A and B only); a
+// leg in all three, or in one operand only, is rejected. Every step becomes one GETT launch whose offset
+// tables fold the stored leg order of A, B and C into the tile loads and stores.
+#pragma once
+
+#include <array>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+#include "gett.h"
+
+namespace mera {
+
+struct StepDef {
+  int a, b, c;                    // tensor ids
+  std::string la, lb, lc;         // per-use labels (positional)
+  double alpha = 1.0;
+  bool accumulate = false;        // C += ... instead of C = ...
+};
+
+struct Program {
+  std::string name;
+  std::vector<std::string> tensors;    // names
+  std::vector<bool> external;          // bound by the caller
+  std::vector<std::string> layout;     // declared storage labels
+  std::vector<StepDef> steps;
+  // Parse "C[cab] = A[ab] * B[bc]", "C[..] += 0.5 * A[..] * B[..]"; tensors whose name is in `externals`
+  // are caller-bound, all others are intermediates owned by the context.
+  static Program parse(const std::string& name, const std::vector<std::string>& lines,
+                       const std::vector<std::string>& externals);
+  int id(const std::string& n) const;
+};
+
+// Extent of every leg label for one instantiation of a program.
+using LegDims = std::array<int64_t, 128>;
+
+struct PlanCache {
+  struct Entry {
+    DevBuf tables;
+    GettTables t;
+    double macs = 0;
+  };
+  std::unordered_map<std::string, std::unique_ptr<Entry>> map;
+};
+
+// Runs `prog` with leg extents `dims`, external tensors bound to `ext` (indexed like prog.tensors; null for
+// intermediates), all tensors of element type given by `prec` (float for F32/BF16X3, double for F64).
+// Intermediates live in context scratch buffers named after the program and tensor.
+void run_program(Ctx& ctx, const Program& prog, const LegDims& dims, const std::vector<void*>& ext, Prec prec);
+
+// Same, with each external tensor bound by name.
+void run_program(Ctx& ctx, const Program& prog, const LegDims& dims,
+                 const std::vector<std::pair<std::string, void*>>& bind, Prec prec);
+
+}  // namespace mera

@@ -1,0 +1,47 @@
+// Memory-bound vector and small-matrix kernels: dot products with FP64 accumulation, axpby, conversions,
+// symmetrisation, traces, and the cyclic two-sided Jacobi eigensolver for small symmetric matrices.
+#pragma once
+
+#include "common.h"
+
+namespace mera {
+
+// Typed device pointer of either precision.
+struct VPtr {
+  void* p = nullptr;
+  Prec prec = Prec::F64;  // F64: double storage; F32/BF16X3: float storage
+  bool dbl() const { return prec == Prec::F64; }
+};
+
+double dot(Ctx& ctx, VPtr x, VPtr y, int64_t n);               // sum x*y in FP64 (syncs)
+double nrm2(Ctx& ctx, VPtr x, int64_t n);
+void axpby(Ctx& ctx, double a, VPtr x, double b, VPtr y, int64_t n);  // y = a x + b y
+void scal(Ctx& ctx, double a, VPtr x, int64_t n);
+void copy(Ctx& ctx, VPtr dst, VPtr src, int64_t n);            // with conversion
+void fill(Ctx& ctx, VPtr x, int64_t n, double v);
+// X (dim x dim, row-major) <- (X + X^T)/2
+void symmetrize(Ctx& ctx, VPtr x, int64_t dim);
+// X_ii += c
+void add_diag(Ctx& ctx, VPtr x, int64_t dim, double c);
+double trace(Ctx& ctx, VPtr x, int64_t dim);                   // syncs
+
+// Symmetric eigendecomposition of a dim x dim FP64 matrix (row-major, device) by cyclic two-sided Jacobi
+// rotations in tournament order: A = V diag(lam) V^T, eigenvectors in the columns of V. `a` is overwritten.
+// Returns the number of sweeps.
+int jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol = 1e-15, int max_sweeps = 30);
+
+// Element-wise helpers for the preconditioner (all FP64, device):
+//   M_ij <- M_ij * 2 / (f_i + f_j)
+void scale_sylvester(Ctx& ctx, double* m, const double* f, int dim);
+//   M_ij <- M_ij * s_j   (column scaling)
+void scale_cols(Ctx& ctx, double* m, const double* s, int64_t rows, int cols);
+//   f_i <- sqrt(lam_i^2 + delta^2), g_i <- 1/f_i
+void reg_spectrum(Ctx& ctx, const double* lam, double delta, double* f, double* g, int dim);
+
+// Marginals of a 3-site density matrix rho[p q r, P Q R] (b^3 x b^3, float or double):
+//   rho1[q, Q]        = sum_{p r} rho[p q r, p Q r]                       (middle site)
+//   rho2[x y, X Y]    = ( sum_r rho[x y r, X Y r] + sum_p rho[p x y, p X Y] ) / 2
+// outputs FP64 device, b x b and b^2 x b^2.
+void rho_marginals(Ctx& ctx, VPtr rho, int b, double* rho1, double* rho2);
+
+}  // namespace mera

@@ -1,0 +1,458 @@
+// Memory-bound kernels: reductions accumulate in FP64 with a wavefront shuffle tree, then per-block partials
+// are summed on the host in a fixed order (deterministic).
+#include "vec.h"
+
+#include <cmath>
+#include <unordered_map>
+
+namespace mera {
+
+namespace {
+
+constexpr int RED_BLOCKS = 1024;
+constexpr int TPB = 256;
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ inline void block_sum_store(double v, double* out) {
+  __shared__ double part[TPB / 64];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) part[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < TPB / 64; ++i) s += part[i];
+    out[blockIdx.x] = s;
+  }
+}
+
+template <typename TX, typename TY>
+__global__ void dot_kernel(const TX* __restrict__ x, const TY* __restrict__ y, int64_t n, double* out) {
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)x[i] * (double)y[i];
+  block_sum_store(s, out);
+}
+
+template <typename TX, typename TY>
+__global__ void axpby_kernel(double a, const TX* __restrict__ x, double b, TY* __restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v = a * (double)x[i];
+    if (b != 0.0) v += b * (double)y[i];
+    y[i] = (TY)v;
+  }
+}
+
+template <typename T>
+__global__ void scal_kernel(double a, T* x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (T)(a * (double)x[i]);
+}
+
+template <typename TD, typename TS>
+__global__ void copy_kernel(TD* __restrict__ d, const TS* __restrict__ s, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = (TD)s[i];
+}
+
+template <typename T>
+__global__ void fill_kernel(T* x, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (T)v;
+}
+
+// 32x32 tile pairs (I, J) with I <= J; each tile pair is symmetrised through LDS.
+template <typename T>
+__global__ void symmetrize_kernel(T* x, int64_t dim) {
+  __shared__ T a[32][33], b[32][33];
+  const int64_t ntile = (dim + 31) / 32;
+  // map blockIdx.x to (I, J) with I <= J
+  int64_t t = blockIdx.x, I = 0;
+  while (t >= ntile - I) { t -= ntile - I; ++I; }
+  const int64_t J = I + t;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int r = ty; r < 32; r += 8) {
+    int64_t i = I * 32 + r, j = J * 32 + tx;
+    a[r][tx] = (i < dim && j < dim) ? x[i * dim + j] : T(0);
+    int64_t i2 = J * 32 + r, j2 = I * 32 + tx;
+    b[r][tx] = (i2 < dim && j2 < dim) ? x[i2 * dim + j2] : T(0);
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    int64_t i = I * 32 + r, j = J * 32 + tx;
+    T v = T(0.5) * (a[r][tx] + b[tx][r]);
+    if (i < dim && j < dim) x[i * dim + j] = v;
+    int64_t i2 = J * 32 + r, j2 = I * 32 + tx;
+    T w = T(0.5) * (b[r][tx] + a[tx][r]);
+    if (i2 < dim && j2 < dim && I != J) x[i2 * dim + j2] = w;
+  }
+}
+
+template <typename T>
+__global__ void add_diag_kernel(T* x, int64_t dim, double c) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += (int64_t)gridDim.x * blockDim.x)
+    x[i * dim + i] = (T)((double)x[i * dim + i] + c);
+}
+
+template <typename T>
+__global__ void trace_kernel(const T* x, int64_t dim, double* out) {
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)x[i * dim + i];
+  block_sum_store(s, out);
+}
+
+int grid_for(int64_t n) {
+  int64_t b = (n + TPB - 1) / TPB;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+double finish_partials(Ctx& ctx, int blocks) {
+  double host[RED_BLOCKS];
+  MERA_HIP(hipMemcpyAsync(host, ctx.red.ptr, blocks * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  double s = 0.0;
+  for (int i = 0; i < blocks; ++i) s += host[i];
+  return s;
+}
+
+// ---- Jacobi --------------------------------------------------------------------------------------------
+
+// Rotation of one tournament pair (i, j) that zeroes A_ij of the 2x2 block (Golub & Van Loan's symmetric
+// Schur step); a dummy partner (-1, odd dimension) gives the identity.
+__device__ inline void rot_of(const double* a, int dim, int i, int j, double& c, double& s) {
+  if (i < 0 || j < 0) { c = 1.0; s = 0.0; return; }
+  const double aii = a[(int64_t)i * dim + i], ajj = a[(int64_t)j * dim + j], aij = a[(int64_t)i * dim + j];
+  if (aij == 0.0) { c = 1.0; s = 0.0; return; }
+  const double tau = (ajj - aii) / (2.0 * aij);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+}
+
+// One round: every index is in exactly one pair; A' = J^T A J block by block (P, Q) of 2x2 entries, reading
+// ain and writing aout; V <- V J in place. pairs: npairs x 2 ints for this round (-1 = dummy).
+__global__ void jacobi_round_kernel(const double* __restrict__ ain, double* __restrict__ aout, double* v,
+                                    const int* __restrict__ pairs, int npairs, int dim) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nblk = (int64_t)npairs * npairs;
+  if (id < nblk) {
+    const int P = (int)(id / npairs), Q = (int)(id % npairs);
+    const int i = pairs[2 * P], j = pairs[2 * P + 1], k = pairs[2 * Q], l = pairs[2 * Q + 1];
+    double cp, sp, cq, sq;
+    rot_of(ain, dim, i, j, cp, sp);
+    rot_of(ain, dim, k, l, cq, sq);
+    // entries (row in {i,j}) x (col in {k,l}); a missing index (dummy) contributes nothing
+    double aik = (i >= 0 && k >= 0) ? ain[(int64_t)i * dim + k] : 0.0;
+    double ail = (i >= 0 && l >= 0) ? ain[(int64_t)i * dim + l] : 0.0;
+    double ajk = (j >= 0 && k >= 0) ? ain[(int64_t)j * dim + k] : 0.0;
+    double ajl = (j >= 0 && l >= 0) ? ain[(int64_t)j * dim + l] : 0.0;
+    // T = J_P^T A_PQ
+    double t0k = cp * aik - sp * ajk, t0l = cp * ail - sp * ajl;
+    double t1k = sp * aik + cp * ajk, t1l = sp * ail + cp * ajl;
+    // A' = T J_Q
+    double n_ik = cq * t0k - sq * t0l, n_il = sq * t0k + cq * t0l;
+    double n_jk = cq * t1k - sq * t1l, n_jl = sq * t1k + cq * t1l;
+    if (P == Q) { n_il = 0.0; n_jk = 0.0; }
+    if (i >= 0 && k >= 0) aout[(int64_t)i * dim + k] = n_ik;
+    if (i >= 0 && l >= 0) aout[(int64_t)i * dim + l] = n_il;
+    if (j >= 0 && k >= 0) aout[(int64_t)j * dim + k] = n_jk;
+    if (j >= 0 && l >= 0) aout[(int64_t)j * dim + l] = n_jl;
+  }
+  // V <- V J: thread -> (row r, pair P)
+  const int64_t nv = (int64_t)dim * npairs;
+  if (id < nv) {
+    const int r = (int)(id / npairs), P = (int)(id % npairs);
+    const int i = pairs[2 * P], j = pairs[2 * P + 1];
+    if (i >= 0 && j >= 0) {
+      double cp, sp;
+      rot_of(ain, dim, i, j, cp, sp);
+      const double vi = v[(int64_t)r * dim + i], vj = v[(int64_t)r * dim + j];
+      v[(int64_t)r * dim + i] = cp * vi - sp * vj;
+      v[(int64_t)r * dim + j] = sp * vi + cp * vj;
+    }
+  }
+}
+
+__global__ void offdiag_kernel(const double* a, int dim, double* out) {
+  double s = 0.0;
+  const int64_t n = (int64_t)dim * dim;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = t / dim, j = t - i * dim;
+    double x = a[t];
+    if (i != j) s += x * x;
+  }
+  block_sum_store(s, out);
+}
+
+__global__ void diag_kernel(const double* a, int dim, double* lam) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < dim) lam[i] = a[(int64_t)i * dim + i];
+}
+
+__global__ void eye_kernel(double* v, int dim) {
+  const int64_t n = (int64_t)dim * dim;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = t / dim, j = t - i * dim;
+    v[t] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void scale_sylvester_kernel(double* m, const double* f, int dim) {
+  const int64_t n = (int64_t)dim * dim;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = t / dim, j = t - i * dim;
+    m[t] = m[t] * 2.0 / (f[i] + f[j]);
+  }
+}
+
+__global__ void scale_cols_kernel(double* m, const double* s, int64_t rows, int cols) {
+  const int64_t n = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    m[t] *= s[t % cols];
+}
+
+__global__ void reg_spectrum_kernel(const double* lam, double delta, double* f, double* g, int dim) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < dim) {
+    double x = sqrt(lam[i] * lam[i] + delta * delta);
+    f[i] = x;
+    g[i] = 1.0 / x;
+  }
+}
+
+template <typename T>
+__global__ void marginal2_kernel(const T* __restrict__ rho, int b, double* __restrict__ out) {
+  const int64_t b2 = (int64_t)b * b, b3 = b2 * b, n = b2 * b2;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = t / (b * b2), y = (t / b2) % b, X = (t / b) % b, Y = t % b;
+    double s = 0.0;
+    for (int r = 0; r < b; ++r) s += (double)rho[((x * b + y) * b + r) * b3 + (X * b + Y) * b + r];
+    for (int p = 0; p < b; ++p) s += (double)rho[((p * b + x) * b + y) * b3 + (p * b + X) * b + Y];
+    out[t] = 0.5 * s;
+  }
+}
+
+template <typename T>
+__global__ void marginal1_kernel(const T* __restrict__ rho, int b, double* __restrict__ out) {
+  const int64_t b3 = (int64_t)b * b * b;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < b * b) {
+    const int q = t / b, Q = t % b;
+    double s = 0.0;
+    for (int p = 0; p < b; ++p)
+      for (int r = 0; r < b; ++r) s += (double)rho[((int64_t)(p * b + q) * b + r) * b3 + (p * b + Q) * b + r];
+    out[t] = s;
+  }
+}
+
+struct JacobiSchedule {
+  int dim = 0, npairs = 0, rounds = 0;
+  DevBuf pairs;  // rounds x npairs x 2
+};
+
+}  // namespace
+
+double dot(Ctx& ctx, VPtr x, VPtr y, int64_t n) {
+  ctx.red.ensure(RED_BLOCKS * sizeof(double));
+  int blocks = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + TPB - 1) / TPB));
+  double* out = ctx.red.as<double>();
+  if (x.dbl() && y.dbl())
+    hipLaunchKernelGGL((dot_kernel<double, double>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const double*)x.p, (const double*)y.p, n, out);
+  else if (x.dbl())
+    hipLaunchKernelGGL((dot_kernel<double, float>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const double*)x.p, (const float*)y.p, n, out);
+  else if (y.dbl())
+    hipLaunchKernelGGL((dot_kernel<float, double>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const float*)x.p, (const double*)y.p, n, out);
+  else
+    hipLaunchKernelGGL((dot_kernel<float, float>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const float*)x.p, (const float*)y.p, n, out);
+  MERA_HIP(hipGetLastError());
+  return finish_partials(ctx, blocks);
+}
+
+double nrm2(Ctx& ctx, VPtr x, int64_t n) { return std::sqrt(dot(ctx, x, x, n)); }
+
+void axpby(Ctx& ctx, double a, VPtr x, double b, VPtr y, int64_t n) {
+  int g = grid_for(n);
+  if (x.dbl() && y.dbl())
+    hipLaunchKernelGGL((axpby_kernel<double, double>), dim3(g), dim3(TPB), 0, ctx.stream, a, (const double*)x.p, b,
+                       (double*)y.p, n);
+  else if (x.dbl())
+    hipLaunchKernelGGL((axpby_kernel<double, float>), dim3(g), dim3(TPB), 0, ctx.stream, a, (const double*)x.p, b,
+                       (float*)y.p, n);
+  else if (y.dbl())
+    hipLaunchKernelGGL((axpby_kernel<float, double>), dim3(g), dim3(TPB), 0, ctx.stream, a, (const float*)x.p, b,
+                       (double*)y.p, n);
+  else
+    hipLaunchKernelGGL((axpby_kernel<float, float>), dim3(g), dim3(TPB), 0, ctx.stream, a, (const float*)x.p, b,
+                       (float*)y.p, n);
+  MERA_HIP(hipGetLastError());
+}
+
+void scal(Ctx& ctx, double a, VPtr x, int64_t n) {
+  int g = grid_for(n);
+  if (x.dbl()) hipLaunchKernelGGL(scal_kernel<double>, dim3(g), dim3(TPB), 0, ctx.stream, a, (double*)x.p, n);
+  else hipLaunchKernelGGL(scal_kernel<float>, dim3(g), dim3(TPB), 0, ctx.stream, a, (float*)x.p, n);
+  MERA_HIP(hipGetLastError());
+}
+
+void copy(Ctx& ctx, VPtr d, VPtr s, int64_t n) {
+  if (n <= 0) return;
+  if (d.dbl() == s.dbl()) {
+    MERA_HIP(hipMemcpyAsync(d.p, s.p, n * (d.dbl() ? 8 : 4), hipMemcpyDeviceToDevice, ctx.stream));
+    return;
+  }
+  int g = grid_for(n);
+  if (d.dbl())
+    hipLaunchKernelGGL((copy_kernel<double, float>), dim3(g), dim3(TPB), 0, ctx.stream, (double*)d.p,
+                       (const float*)s.p, n);
+  else
+    hipLaunchKernelGGL((copy_kernel<float, double>), dim3(g), dim3(TPB), 0, ctx.stream, (float*)d.p,
+                       (const double*)s.p, n);
+  MERA_HIP(hipGetLastError());
+}
+
+void fill(Ctx& ctx, VPtr x, int64_t n, double v) {
+  int g = grid_for(n);
+  if (x.dbl()) hipLaunchKernelGGL(fill_kernel<double>, dim3(g), dim3(TPB), 0, ctx.stream, (double*)x.p, n, v);
+  else hipLaunchKernelGGL(fill_kernel<float>, dim3(g), dim3(TPB), 0, ctx.stream, (float*)x.p, n, v);
+  MERA_HIP(hipGetLastError());
+}
+
+void symmetrize(Ctx& ctx, VPtr x, int64_t dim) {
+  const int64_t nt = (dim + 31) / 32;
+  const int64_t blocks = nt * (nt + 1) / 2;
+  if (x.dbl())
+    hipLaunchKernelGGL(symmetrize_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, ctx.stream, (double*)x.p,
+                       dim);
+  else
+    hipLaunchKernelGGL(symmetrize_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, ctx.stream, (float*)x.p,
+                       dim);
+  MERA_HIP(hipGetLastError());
+}
+
+void add_diag(Ctx& ctx, VPtr x, int64_t dim, double c) {
+  int g = grid_for(dim);
+  if (x.dbl()) hipLaunchKernelGGL(add_diag_kernel<double>, dim3(g), dim3(TPB), 0, ctx.stream, (double*)x.p, dim, c);
+  else hipLaunchKernelGGL(add_diag_kernel<float>, dim3(g), dim3(TPB), 0, ctx.stream, (float*)x.p, dim, c);
+  MERA_HIP(hipGetLastError());
+}
+
+double trace(Ctx& ctx, VPtr x, int64_t dim) {
+  ctx.red.ensure(RED_BLOCKS * sizeof(double));
+  int blocks = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (dim + TPB - 1) / TPB));
+  if (x.dbl())
+    hipLaunchKernelGGL(trace_kernel<double>, dim3(blocks), dim3(TPB), 0, ctx.stream, (const double*)x.p, dim,
+                       ctx.red.as<double>());
+  else
+    hipLaunchKernelGGL(trace_kernel<float>, dim3(blocks), dim3(TPB), 0, ctx.stream, (const float*)x.p, dim,
+                       ctx.red.as<double>());
+  MERA_HIP(hipGetLastError());
+  return finish_partials(ctx, blocks);
+}
+
+int jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol, int max_sweeps) {
+  if (dim <= 0) return 0;
+  static thread_local std::unordered_map<std::string, std::unique_ptr<JacobiSchedule>> scheds;
+  const std::string key = std::to_string(ctx.device) + ":" + std::to_string(dim);
+  auto it = scheds.find(key);
+  if (it == scheds.end()) {
+    // tournament (circle) schedule over m = dim rounded up to even; index m-1 is a dummy when dim is odd
+    auto s = std::make_unique<JacobiSchedule>();
+    const int m = dim + (dim & 1);
+    s->dim = dim;
+    s->npairs = m / 2;
+    s->rounds = m - 1;
+    std::vector<int> host((size_t)s->rounds * s->npairs * 2);
+    std::vector<int> ring(m);
+    for (int i = 0; i < m; ++i) ring[i] = i;
+    for (int r = 0; r < s->rounds; ++r) {
+      for (int k = 0; k < s->npairs; ++k) {
+        int i = ring[k], j = ring[m - 1 - k];
+        host[((size_t)r * s->npairs + k) * 2] = (i < dim) ? i : -1;
+        host[((size_t)r * s->npairs + k) * 2 + 1] = (j < dim) ? j : -1;
+      }
+      // rotate all but ring[0]
+      int last = ring[m - 1];
+      for (int i = m - 1; i > 1; --i) ring[i] = ring[i - 1];
+      ring[1] = last;
+    }
+    s->pairs.alloc(host.size() * sizeof(int));
+    MERA_HIP(hipMemcpy(s->pairs.ptr, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice));
+    it = scheds.emplace(key, std::move(s)).first;
+  }
+  JacobiSchedule& s = *it->second;
+  double* b = static_cast<double*>(ctx.buf("jacobi.pingpong", (size_t)dim * dim * sizeof(double)));
+  const int g = grid_for((int64_t)dim * dim);
+  hipLaunchKernelGGL(eye_kernel, dim3(g), dim3(TPB), 0, ctx.stream, v, dim);
+  const double fro = std::sqrt(dot(ctx, VPtr{a, Prec::F64}, VPtr{a, Prec::F64}, (int64_t)dim * dim));
+  ctx.red.ensure(RED_BLOCKS * sizeof(double));
+  const int64_t work = std::max<int64_t>((int64_t)s.npairs * s.npairs, (int64_t)dim * s.npairs);
+  const int rg = (int)((work + TPB - 1) / TPB);
+  int sweeps = 0;
+  double* cur = a;
+  double* nxt = b;
+  double prev_off = INFINITY;
+  for (; sweeps < max_sweeps; ++sweeps) {
+    hipLaunchKernelGGL(offdiag_kernel, dim3(256), dim3(TPB), 0, ctx.stream, cur, dim, ctx.red.as<double>());
+    double off = std::sqrt(finish_partials(ctx, 256));
+    if (!(off > tol * fro) || dim == 1) break;
+    // rounding floor: off-diagonal mass no longer shrinks quadratically
+    if (sweeps >= 4 && off > 0.25 * prev_off && off < 1e-12 * fro) break;
+    prev_off = off;
+    for (int r = 0; r < s.rounds; ++r) {
+      hipLaunchKernelGGL(jacobi_round_kernel, dim3(rg), dim3(TPB), 0, ctx.stream, cur, nxt, v,
+                         s.pairs.as<int>() + (size_t)r * s.npairs * 2, s.npairs, dim);
+      std::swap(cur, nxt);
+    }
+    MERA_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(diag_kernel, dim3((dim + TPB - 1) / TPB), dim3(TPB), 0, ctx.stream, cur, dim, lam);
+  if (cur != a) MERA_HIP(hipMemcpyAsync(a, cur, (size_t)dim * dim * 8, hipMemcpyDeviceToDevice, ctx.stream));
+  MERA_HIP(hipGetLastError());
+  return sweeps;
+}
+
+void rho_marginals(Ctx& ctx, VPtr rho, int b, double* rho1, double* rho2) {
+  const int64_t n2 = (int64_t)b * b * b * b;
+  if (rho.dbl()) {
+    hipLaunchKernelGGL(marginal2_kernel<double>, dim3(grid_for(n2)), dim3(TPB), 0, ctx.stream,
+                       (const double*)rho.p, b, rho2);
+    hipLaunchKernelGGL(marginal1_kernel<double>, dim3((b * b + TPB - 1) / TPB), dim3(TPB), 0, ctx.stream,
+                       (const double*)rho.p, b, rho1);
+  } else {
+    hipLaunchKernelGGL(marginal2_kernel<float>, dim3(grid_for(n2)), dim3(TPB), 0, ctx.stream,
+                       (const float*)rho.p, b, rho2);
+    hipLaunchKernelGGL(marginal1_kernel<float>, dim3((b * b + TPB - 1) / TPB), dim3(TPB), 0, ctx.stream,
+                       (const float*)rho.p, b, rho1);
+  }
+  MERA_HIP(hipGetLastError());
+}
+
+void scale_sylvester(Ctx& ctx, double* m, const double* f, int dim) {
+  hipLaunchKernelGGL(scale_sylvester_kernel, dim3(grid_for((int64_t)dim * dim)), dim3(TPB), 0, ctx.stream, m, f,
+                     dim);
+  MERA_HIP(hipGetLastError());
+}
+
+void scale_cols(Ctx& ctx, double* m, const double* s, int64_t rows, int cols) {
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(grid_for(rows * cols)), dim3(TPB), 0, ctx.stream, m, s, rows, cols);
+  MERA_HIP(hipGetLastError());
+}
+
+void reg_spectrum(Ctx& ctx, const double* lam, double delta, double* f, double* g, int dim) {
+  hipLaunchKernelGGL(reg_spectrum_kernel, dim3((dim + TPB - 1) / TPB), dim3(TPB), 0, ctx.stream, lam, delta, f, g,
+                     dim);
+  MERA_HIP(hipGetLastError());
+}
+
+}  // namespace mera
