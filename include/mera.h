@@ -195,8 +195,9 @@ typedef struct {
   int evaluations;
   int status;                      /* 0 converged, 1 iteration cap, 2 line search failed, <0 mera_status      */
   int polish_iter;                 /* iteration at which FP64 polishing started, -1 if never                 */
-  double seconds;                  /* wall time of the run                                                  */
+  double seconds;                  /* wall time of the optimisation itself                                  */
   double macs;
+  double queued_seconds;           /* server only: time from submission to admission (0 for run_optimize)   */
 } mera_result;
 
 typedef struct { int iter; int evals; double energy; double gnorm; double alpha; int prec; } mera_iter_log;
@@ -209,13 +210,16 @@ mera_status run_optimize(mera_ctx* ctx, const mera_job* job, mera_result* out, d
 
 /* ---- serving: continuous batching of optimisation jobs ------------------------------------------------ */
 
-/* A server owns a host thread that admits submitted jobs while the device-memory footprint of the running
- * jobs fits `hbm_budget` bytes and fewer than `max_slots` run, interleaves their evaluations on the device,
- * and retires finished jobs. */
+/* A server owns `max_slots` host workers, each with its own HIP stream and workspace on the context's
+ * device. Submitted jobs wait in a FIFO queue; the head job is admitted when a worker is free and the summed
+ * device-memory footprint of the running jobs plus its own fits `hbm_budget` bytes; the device work of the
+ * running jobs overlaps. A job computes exactly what run_optimize computes for it alone. Destroying the server
+ * waits for running jobs and drops queued ones. */
 mera_status mera_server_create(mera_ctx* ctx, size_t hbm_budget, int max_slots, mera_server** out);
 /* The job is copied (including h3 and initial tensors) before the call returns. */
 mera_status mera_server_submit(mera_server* srv, const mera_job* job, uint64_t* job_id);
-/* MERA_EBUSY while queued or running; MERA_OK with the result once finished. */
+/* MERA_EBUSY while queued or running; MERA_OK with the result once finished (or the job's error status,
+ * with out->status set to it). Time to converged = queued_seconds + seconds. */
 mera_status mera_server_poll(mera_server* srv, uint64_t job_id, mera_result* out);
 /* Device bytes a job of this shape and precision needs (admission estimate). */
 size_t mera_job_footprint(const mera_shape* shape, mera_prec prec);

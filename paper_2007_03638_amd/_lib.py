@@ -35,7 +35,8 @@ class Job(ctypes.Structure):
 
 class Result(ctypes.Structure):
     _fields_ = [("energy", c_double), ("gnorm", c_double), ("iterations", c_int), ("evaluations", c_int),
-                ("status", c_int), ("polish_iter", c_int), ("seconds", c_double), ("macs", c_double)]
+                ("status", c_int), ("polish_iter", c_int), ("seconds", c_double), ("macs", c_double),
+                ("queued_seconds", c_double)]
 
 
 class IterLog(ctypes.Structure):

@@ -74,9 +74,12 @@ class Warm:
         ctx._check(self._lib.mera_warm_create(ctx.ptr, ctypes.byref(sh), ctypes.byref(self.ptr)), "warm_create")
 
     def __del__(self):
-        if getattr(self, "ptr", None) and self.ptr.value:
-            self._lib.mera_warm_destroy(self.ptr)
-            self.ptr = ctypes.c_void_p()
+        try:
+            if self.ptr.value:
+                self._lib.mera_warm_destroy(self.ptr)
+                self.ptr.value = None
+        except Exception:
+            pass
 
 
 class Context:
@@ -92,9 +95,12 @@ class Context:
             raise MeraError(st, "mera_ctx_create")
 
     def __del__(self):
-        if getattr(self, "ptr", None) and self.ptr.value:
-            self._lib.mera_ctx_destroy(self.ptr)
-            self.ptr = ctypes.c_void_p()
+        try:
+            if self.ptr.value:
+                self._lib.mera_ctx_destroy(self.ptr)
+                self.ptr.value = None
+        except Exception:
+            pass
 
     def _check(self, st, what):
         if st != 0:
@@ -231,7 +237,8 @@ class Context:
 
 def result_dict(res):
     return dict(energy=res.energy, gnorm=res.gnorm, iterations=res.iterations, evaluations=res.evaluations,
-                status=res.status, polish_iter=res.polish_iter, seconds=res.seconds, macs=res.macs)
+                status=res.status, polish_iter=res.polish_iter, seconds=res.seconds, macs=res.macs,
+                queued_seconds=res.queued_seconds)
 
 
 def make_job(T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, polish_tol=0.0, precondition=True,
@@ -258,9 +265,12 @@ class LBFGS:
         ctx._check(self._lib.lbfgs_create(ctx.ptr, len(shapes), n, p, m, ctypes.byref(self.ptr)), "lbfgs_create")
 
     def __del__(self):
-        if getattr(self, "ptr", None) and self.ptr.value:
-            self._lib.lbfgs_destroy(self.ptr)
-            self.ptr = ctypes.c_void_p()
+        try:
+            if self.ptr.value:
+                self._lib.lbfgs_destroy(self.ptr)
+                self.ptr.value = None
+        except Exception:
+            pass
 
     def size(self):
         return self._lib.lbfgs_size(self.ptr)
@@ -315,12 +325,15 @@ class Server:
         return result_dict(res)
 
     def close(self):
-        if getattr(self, "ptr", None) and self.ptr.value:
+        if getattr(self, "ptr", None) is not None and self.ptr.value:
             self._lib.mera_server_destroy(self.ptr)
-            self.ptr = ctypes.c_void_p()
+            self.ptr.value = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def job_footprint(T, chi, prec="fp32", d=4):

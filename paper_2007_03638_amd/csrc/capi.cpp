@@ -248,3 +248,228 @@ mera_status mera_descend(mera_ctx* ctx, const mera_shape* shape, int layer, cons
 }
 
 }  // extern "C"
+
+// ---- Stiefel manifold, L-BFGS, optimiser ---------------------------------------------------------------
+
+#include "optim.h"
+
+struct mera_lbfgs {
+  mera::Lbfgs lb;
+  int device = 0;
+};
+
+namespace mera {
+int ctx_device_of(const mera_ctx* ctx) { return ctx->c.device; }
+}  // namespace mera
+
+namespace {
+
+std::vector<MatView> views(const mera_mat* m, int count) {
+  std::vector<MatView> v;
+  for (int i = 0; i < count; ++i) v.push_back(MatView{m[i].n, m[i].p, m[i].data});
+  return v;
+}
+
+void same_shapes(const mera_mat* a, const mera_mat* b, int count, const char* what) {
+  for (int i = 0; i < count; ++i)
+    MERA_CHECK(a[i].n == b[i].n && a[i].p == b[i].p, MERA_EINVAL, std::string(what) + ": shape mismatch");
+}
+
+void check_isometry_shapes(const mera_mat* W, int count, const char* what) {
+  check_mats(W, count, what);
+  for (int i = 0; i < count; ++i)
+    MERA_CHECK(W[i].n >= W[i].p, MERA_EINVAL, std::string(what) + ": need n >= p");
+}
+
+}  // namespace
+
+extern "C" {
+
+mera_status stiefel_project(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, mera_mat* G) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(count >= 0, MERA_EINVAL, "count");
+    check_isometry_shapes(W, count, "stiefel_project W");
+    check_mats(D, count, "stiefel_project D");
+    check_mats(G, count, "stiefel_project G");
+    same_shapes(W, D, count, "stiefel_project");
+    same_shapes(W, G, count, "stiefel_project");
+    DeviceGuard g(ctx->c.device);
+    for (int i = 0; i < count; ++i)
+      stiefel_project_one(ctx->c, MatView{W[i].n, W[i].p, W[i].data}, MatView{D[i].n, D[i].p, D[i].data},
+                          MatView{G[i].n, G[i].p, G[i].data});
+    ctx->c.sync();
+  });
+}
+
+mera_status stiefel_retract(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* X, double alpha,
+                            mera_mat* W_out, mera_mat* X_out) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(count >= 0 && std::isfinite(alpha), MERA_EINVAL, "count/alpha");
+    check_isometry_shapes(W, count, "stiefel_retract W");
+    check_mats(X, count, "stiefel_retract X");
+    check_mats(W_out, count, "stiefel_retract W_out");
+    same_shapes(W, X, count, "stiefel_retract");
+    same_shapes(W, W_out, count, "stiefel_retract");
+    if (X_out) {
+      check_mats(X_out, count, "stiefel_retract X_out");
+      same_shapes(W, X_out, count, "stiefel_retract");
+    }
+    DeviceGuard g(ctx->c.device);
+    for (int i = 0; i < count; ++i) {
+      MatView xo = X_out ? MatView{X_out[i].n, X_out[i].p, X_out[i].data} : MatView{};
+      stiefel_retract_one(ctx->c, MatView{W[i].n, W[i].p, W[i].data}, MatView{X[i].n, X[i].p, X[i].data}, alpha,
+                          MatView{W_out[i].n, W_out[i].p, W_out[i].data}, X_out ? &xo : nullptr);
+    }
+    ctx->c.sync();
+  });
+}
+
+mera_status stiefel_transport(mera_ctx* ctx, int count, const mera_mat* W_new, const mera_mat* Y, mera_mat* Y_out) {
+  return stiefel_project(ctx, count, W_new, Y, Y_out);
+}
+
+mera_status stiefel_precondition(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* X,
+                                 const mera_mat* rho, double delta, mera_mat* X_out) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(count >= 0 && std::isfinite(delta), MERA_EINVAL, "count/delta");
+    check_isometry_shapes(W, count, "stiefel_precondition W");
+    check_mats(X, count, "stiefel_precondition X");
+    check_mats(rho, count, "stiefel_precondition rho");
+    check_mats(X_out, count, "stiefel_precondition X_out");
+    same_shapes(W, X, count, "stiefel_precondition");
+    same_shapes(W, X_out, count, "stiefel_precondition");
+    for (int i = 0; i < count; ++i)
+      MERA_CHECK(rho[i].n == W[i].p && rho[i].p == W[i].p, MERA_EINVAL, "rho must be p x p");
+    DeviceGuard g(ctx->c.device);
+    Metric met;
+    met.compute(ctx->c, views(rho, count));
+    for (int i = 0; i < count; ++i)
+      precondition_one(ctx->c, MatView{W[i].n, W[i].p, W[i].data}, MatView{X[i].n, X[i].p, X[i].data}, met, i,
+                       delta, MatView{X_out[i].n, X_out[i].p, X_out[i].data});
+    ctx->c.sync();
+  });
+}
+
+mera_status mera_inner(mera_ctx* ctx, int count, const mera_mat* X, const mera_mat* Y, double* out) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(out && count >= 0, MERA_EINVAL, "null output");
+    check_mats(X, count, "mera_inner X");
+    check_mats(Y, count, "mera_inner Y");
+    same_shapes(X, Y, count, "mera_inner");
+    DeviceGuard g(ctx->c.device);
+    *out = inner(ctx->c, views(X, count), views(Y, count));
+  });
+}
+
+mera_status lbfgs_create(mera_ctx* ctx, int count, const int* n, const int* p, int m, mera_lbfgs** out) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(out && n && p && count > 0 && m >= 0, MERA_EINVAL, "lbfgs_create arguments");
+    for (int i = 0; i < count; ++i) MERA_CHECK(n[i] > 0 && p[i] > 0, MERA_EINVAL, "lbfgs_create sizes");
+    DeviceGuard g(ctx->c.device);
+    auto* lb = new mera_lbfgs;
+    lb->device = ctx->c.device;
+    try {
+      lb->lb.init(ctx->c, std::vector<int>(n, n + count), std::vector<int>(p, p + count), m);
+    } catch (...) {
+      delete lb;
+      throw;
+    }
+    *out = lb;
+  });
+}
+
+void lbfgs_destroy(mera_lbfgs* lb) {
+  if (!lb) return;
+  try {
+    DeviceGuard g(lb->device);
+    delete lb;
+  } catch (...) {
+  }
+}
+
+mera_status lbfgs_reset(mera_lbfgs* lb) {
+  if (!lb) return MERA_EINVAL;
+  lb->lb.reset();
+  return MERA_OK;
+}
+
+int lbfgs_size(const mera_lbfgs* lb) { return lb ? lb->lb.size() : 0; }
+
+mera_status lbfgs_step(mera_ctx* ctx, mera_lbfgs* lb, const mera_mat* W, const mera_mat* G, const mera_mat* rho,
+                       mera_mat* dir_out, double* slope_out) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(lb && slope_out && lb->device == ctx->c.device, MERA_EINVAL, "lbfgs_step arguments");
+    const int count = lb->lb.shape.count();
+    check_mats(W, count, "lbfgs_step W");
+    check_mats(G, count, "lbfgs_step G");
+    check_mats(dir_out, count, "lbfgs_step dir_out");
+    for (int i = 0; i < count; ++i)
+      MERA_CHECK(W[i].n == lb->lb.shape.n[i] && W[i].p == lb->lb.shape.p[i], MERA_EINVAL, "lbfgs_step shape");
+    same_shapes(W, G, count, "lbfgs_step");
+    same_shapes(W, dir_out, count, "lbfgs_step");
+    DeviceGuard g(ctx->c.device);
+    Metric met;
+    if (rho) {
+      check_mats(rho, count, "lbfgs_step rho");
+      for (int i = 0; i < count; ++i)
+        MERA_CHECK(rho[i].n == W[i].p && rho[i].p == W[i].p, MERA_EINVAL, "rho must be p x p");
+      met.compute(ctx->c, views(rho, count));
+    }
+    *slope_out = lb->lb.step(ctx->c, views(W, count), views(G, count), rho ? &met : nullptr,
+                             views(dir_out, count));
+    ctx->c.sync();
+  });
+}
+
+mera_status lbfgs_push(mera_ctx* ctx, mera_lbfgs* lb, const mera_mat* W_new, const mera_mat* d, double alpha,
+                       const mera_mat* G_old, const mera_mat* G_new, int* accepted) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(lb && lb->device == ctx->c.device && std::isfinite(alpha), MERA_EINVAL, "lbfgs_push arguments");
+    const int count = lb->lb.shape.count();
+    for (const mera_mat* M : {W_new, d, G_old, G_new}) {
+      check_mats(M, count, "lbfgs_push");
+      for (int i = 0; i < count; ++i)
+        MERA_CHECK(M[i].n == lb->lb.shape.n[i] && M[i].p == lb->lb.shape.p[i], MERA_EINVAL, "lbfgs_push shape");
+    }
+    DeviceGuard g(ctx->c.device);
+    bool ok = lb->lb.push(ctx->c, views(W_new, count), views(d, count), alpha, views(G_old, count),
+                          views(G_new, count));
+    if (accepted) *accepted = ok ? 1 : 0;
+    ctx->c.sync();
+  });
+}
+
+mera_status run_optimize(mera_ctx* ctx, const mera_job* job, mera_result* out, double* const* final_host,
+                         mera_iter_log* log, int log_cap, int* log_len) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(job && out, MERA_EINVAL, "null argument");
+    MERA_CHECK(log_cap >= 0 && (log_cap == 0 || log), MERA_EINVAL, "log buffer");
+    JobSpec spec = JobSpec::from_c(*job);
+    DeviceGuard g(ctx->c.device);
+    std::vector<double*> fin;
+    if (final_host)
+      for (int i = 0; i < 2 * (spec.shape.T + 1); ++i) fin.push_back(final_host[i]);
+    OptResult r = optimize(ctx->c, spec, final_host ? &fin : nullptr, log_cap);
+    std::memset(out, 0, sizeof(*out));
+    out->energy = r.energy;
+    out->gnorm = r.gnorm;
+    out->iterations = r.iterations;
+    out->evaluations = r.evaluations;
+    out->status = r.status;
+    out->polish_iter = r.polish_iter;
+    out->seconds = r.seconds;
+    out->macs = r.macs;
+    for (size_t i = 0; i < r.log.size() && (int)i < log_cap; ++i) log[i] = r.log[i];
+    if (log_len) *log_len = (int)std::min<size_t>(r.log.size(), (size_t)log_cap);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,556 @@
+// Stiefel manifold, preconditioner, L-BFGS and the optimisation driver (see optim.h).
+#include "optim.h"
+
+#include <chrono>
+#include <cmath>
+#include <limits>
+
+#include "linalg.h"
+#include "vec.h"
+
+namespace mera {
+
+namespace {
+
+VPtr d64(const MatView& m) { return VPtr{m.data, Prec::F64}; }
+int64_t numel(const MatView& m) { return (int64_t)m.n * m.p; }
+double* tmp(Ctx& ctx, const char* name, int64_t n) {
+  return static_cast<double*>(ctx.buf(name, (size_t)n * sizeof(double)));
+}
+
+}  // namespace
+
+void Flat::init(const std::vector<int>& n_, const std::vector<int>& p_) {
+  n = n_;
+  p = p_;
+  off.assign(n.size(), 0);
+  total = 0;
+  for (size_t i = 0; i < n.size(); ++i) {
+    off[i] = total;
+    total += (int64_t)n[i] * p[i];
+  }
+  buf.alloc((size_t)std::max<int64_t>(total, 1) * sizeof(double));
+}
+
+std::vector<MatView> Flat::views() const {
+  std::vector<MatView> v;
+  for (int i = 0; i < count(); ++i) v.push_back(view(i));
+  return v;
+}
+
+double inner(Ctx& ctx, const std::vector<MatView>& X, const std::vector<MatView>& Y) {
+  double s = 0.0;
+  for (size_t i = 0; i < X.size(); ++i) s += dot(ctx, d64(X[i]), d64(Y[i]), numel(X[i]));
+  return s;
+}
+
+void stiefel_project_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& G) {
+  const int n = W.n, p = W.p;
+  double* S = tmp(ctx, "st.S", (int64_t)p * p);
+  mm(ctx, "S[pq] = W[np] * D[nq]", {{'n', n}, {'p', p}, {'q', p}}, {{"S", S}, {"W", W.data}, {"D", D.data}});
+  symmetrize(ctx, VPtr{S, Prec::F64}, p);
+  if (G.data != D.data) copy(ctx, d64(G), d64(D), (int64_t)n * p);
+  mm(ctx, "G[nq] += -1.0 * W[np] * S[pq]", {{'n', n}, {'p', p}, {'q', p}},
+     {{"G", G.data}, {"W", W.data}, {"S", S}});
+}
+
+void stiefel_retract_one(Ctx& ctx, const MatView& W, const MatView& X, double alpha, const MatView& Wout,
+                         const MatView* Xout) {
+  const int n = W.n, p = W.p;
+  const int64_t pp = (int64_t)p * p;
+  double* Y = tmp(ctx, "rt.Y", (int64_t)n * p);
+  double* M = tmp(ctx, "rt.M", pp);
+  double* Yk = tmp(ctx, "rt.Yk", pp);
+  double* Zk = tmp(ctx, "rt.Zk", pp);
+  double* Tk = tmp(ctx, "rt.T", pp);
+  double* Y2 = tmp(ctx, "rt.Y2", pp);
+  double* Z2 = tmp(ctx, "rt.Z2", pp);
+  copy(ctx, VPtr{Y, Prec::F64}, d64(W), (int64_t)n * p);
+  axpby(ctx, alpha, d64(X), 1.0, VPtr{Y, Prec::F64}, (int64_t)n * p);
+  // M = Y^T Y
+  mm(ctx, "M[pq] = Y[np] * Y2[nq]", {{'n', n}, {'p', p}, {'q', p}}, {{"M", M}, {"Y", Y}, {"Y2", Y}});
+  symmetrize(ctx, VPtr{M, Prec::F64}, p);
+  // coupled Newton-Schulz iteration (Higham, "Functions of Matrices", the coupled square-root iteration):
+  // Y_0 = M/c, Z_0 = I, T = (3I - Z Y)/2, Y <- Y T, Z <- T Z; Z -> (M/c)^{-1/2}
+  const double c = std::sqrt(dot(ctx, VPtr{M, Prec::F64}, VPtr{M, Prec::F64}, pp));
+  MERA_CHECK(std::isfinite(c) && c > 0.0, MERA_ENONFINITE, "retraction: non-finite Y^T Y");
+  copy(ctx, VPtr{Yk, Prec::F64}, VPtr{M, Prec::F64}, pp);
+  scal(ctx, 1.0 / c, VPtr{Yk, Prec::F64}, pp);
+  fill(ctx, VPtr{Zk, Prec::F64}, pp, 0.0);
+  add_diag(ctx, VPtr{Zk, Prec::F64}, p, 1.0);
+  const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', p}, {'q', p}, {'r', p}};
+  bool conv = false;
+  int tail = 0;
+  for (int it = 0; it < 100; ++it) {
+    mm(ctx, "T[pq] = -0.5 * Z[pr] * Yk[rq]", dpp, {{"T", Tk}, {"Z", Zk}, {"Yk", Yk}});
+    add_diag(ctx, VPtr{Tk, Prec::F64}, p, 1.5);
+    mm(ctx, "Y2[pq] = Yk[pr] * T[rq]", dpp, {{"Y2", Y2}, {"Yk", Yk}, {"T", Tk}});
+    mm(ctx, "Z2[pq] = T[pr] * Z[rq]", dpp, {{"Z2", Z2}, {"T", Tk}, {"Z", Zk}});
+    std::swap(Yk, Y2);
+    std::swap(Zk, Z2);
+    add_diag(ctx, VPtr{Tk, Prec::F64}, p, -1.0);
+    const double err = std::sqrt(dot(ctx, VPtr{Tk, Prec::F64}, VPtr{Tk, Prec::F64}, pp));
+    MERA_CHECK(std::isfinite(err), MERA_ENONFINITE, "retraction: Newton-Schulz diverged");
+    if (err < 1e-13) {
+      // quadratic convergence: one more step reaches rounding level
+      if (++tail >= 2) {
+        conv = true;
+        break;
+      }
+    }
+  }
+  MERA_CHECK(conv, MERA_ENOCONV, "retraction: Newton-Schulz did not converge");
+  // Z = M^{-1/2}
+  scal(ctx, 1.0 / std::sqrt(c), VPtr{Zk, Prec::F64}, pp);
+  double* Wt = tmp(ctx, "rt.W", (int64_t)n * p);
+  mm(ctx, "Wt[nq] = Y[np] * Z[pq]", {{'n', n}, {'p', p}, {'q', p}}, {{"Wt", Wt}, {"Y", Y}, {"Z", Zk}});
+  // one Newton-Schulz polar refinement: W <- W (3I - W^T W)/2
+  mm(ctx, "E[pq] = Wt[np] * Wt2[nq]", {{'n', n}, {'p', p}, {'q', p}}, {{"E", Tk}, {"Wt", Wt}, {"Wt2", Wt}});
+  scal(ctx, -0.5, VPtr{Tk, Prec::F64}, pp);
+  add_diag(ctx, VPtr{Tk, Prec::F64}, p, 1.5);
+  mm(ctx, "Wo[nq] = Wt[np] * E[pq]", {{'n', n}, {'p', p}, {'q', p}}, {{"Wo", Wout.data}, {"Wt", Wt}, {"E", Tk}});
+  if (Xout) {
+    // M = I + alpha^2 K with K = X^T X (X tangent), and M commutes with K, so
+    // dR/dalpha = X Z + (W + alpha X) dZ/dalpha = X Z - alpha Y K Z^3.
+    double* K = tmp(ctx, "rt.K", pp);
+    mm(ctx, "K[pq] = X[np] * X2[nq]", {{'n', n}, {'p', p}, {'q', p}}, {{"K", K}, {"X", X.data}, {"X2", X.data}});
+    mm(ctx, "Y2[pq] = Z[pr] * Z2[rq]", dpp, {{"Y2", Y2}, {"Z", Zk}, {"Z2", Zk}});    // Z^2
+    mm(ctx, "T[pq] = Y2[pr] * Z[rq]", dpp, {{"T", Tk}, {"Y2", Y2}, {"Z", Zk}});      // Z^3
+    mm(ctx, "Y2[pq] = K[pr] * T[rq]", dpp, {{"Y2", Y2}, {"K", K}, {"T", Tk}});       // K Z^3
+    scal(ctx, -alpha, VPtr{Y2, Prec::F64}, pp);
+    mm(ctx, "Xo[nq] = X[np] * Z[pq]", {{'n', n}, {'p', p}, {'q', p}}, {{"Xo", Xout->data}, {"X", X.data}, {"Z", Zk}});
+    mm(ctx, "Xo[nq] += Y[np] * KZ[pq]", {{'n', n}, {'p', p}, {'q', p}},
+       {{"Xo", Xout->data}, {"Y", Y}, {"KZ", Y2}});
+  }
+}
+
+void Metric::compute(Ctx& ctx, const std::vector<MatView>& rho) {
+  const size_t k = rho.size();
+  V.resize(k);
+  lam.resize(k);
+  f.resize(k);
+  g.resize(k);
+  p.assign(k, 0);
+  for (size_t i = 0; i < k; ++i) {
+    const int q = rho[i].p;
+    MERA_CHECK(rho[i].n == q, MERA_EINVAL, "metric must be square");
+    p[i] = q;
+    V[i].ensure((size_t)q * q * 8);
+    lam[i].ensure((size_t)q * 8);
+    f[i].ensure((size_t)q * 8);
+    g[i].ensure((size_t)q * 8);
+    double* a = tmp(ctx, "met.a", (int64_t)q * q);
+    copy(ctx, VPtr{a, Prec::F64}, d64(rho[i]), (int64_t)q * q);
+    symmetrize(ctx, VPtr{a, Prec::F64}, q);
+    jacobi_eigh(ctx, a, lam[i].as<double>(), V[i].as<double>(), q);
+  }
+}
+
+void precondition_one(Ctx& ctx, const MatView& W, const MatView& X, Metric& met, int i, double delta,
+                      const MatView& Xout) {
+  const int n = W.n, p = W.p;
+  MERA_CHECK(met.p[i] == p, MERA_EINVAL, "metric size does not match the tensor");
+  if (delta < 0) delta = std::sqrt(dot(ctx, d64(X), d64(X), (int64_t)n * p));
+  double* V = met.V[i].as<double>();
+  double* f = met.f[i].as<double>();
+  double* g = met.g[i].as<double>();
+  reg_spectrum(ctx, met.lam[i].as<double>(), delta, f, g, p);
+  const int64_t pp = (int64_t)p * p;
+  double* A = tmp(ctx, "pc.A", pp);
+  double* T1 = tmp(ctx, "pc.T1", pp);
+  double* Ah = tmp(ctx, "pc.Ah", pp);
+  double* Bp = tmp(ctx, "pc.B", (int64_t)n * p);
+  double* T3 = tmp(ctx, "pc.T3", (int64_t)n * p);
+  const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', p}, {'q', p}, {'r', p}};
+  const std::initializer_list<std::pair<char, int64_t>> dnp = {{'n', n}, {'p', p}, {'q', p}};
+  // A = W^T X; X = W A + (X - W A) with (X - W A) = W_perp B
+  mm(ctx, "A[pq] = W[np] * X[nq]", dnp, {{"A", A}, {"W", W.data}, {"X", X.data}});
+  copy(ctx, VPtr{Bp, Prec::F64}, d64(X), (int64_t)n * p);
+  mm(ctx, "B[nq] += -1.0 * W[np] * A[pq]", dnp, {{"B", Bp}, {"W", W.data}, {"A", A}});
+  // A~ = V [ (V^T A V)_ij 2 / (f_i + f_j) ] V^T
+  mm(ctx, "T1[pq] = V[rp] * A[rq]", dpp, {{"T1", T1}, {"V", V}, {"A", A}});
+  mm(ctx, "Ah[pq] = T1[pr] * V[rq]", dpp, {{"Ah", Ah}, {"T1", T1}, {"V", V}});
+  scale_sylvester(ctx, Ah, f, p);
+  mm(ctx, "T1[pq] = V[pr] * Ah[rq]", dpp, {{"T1", T1}, {"V", V}, {"Ah", Ah}});
+  mm(ctx, "A[pq] = T1[pr] * V[qr]", dpp, {{"A", A}, {"T1", T1}, {"V", V}});
+  // B~ part: (W_perp B) V diag(1/f) V^T
+  mm(ctx, "T3[nq] = B[np] * V[pq]", dnp, {{"T3", T3}, {"B", Bp}, {"V", V}});
+  scale_cols(ctx, T3, g, n, p);
+  mm(ctx, "Xo[nq] = T3[np] * V[qp]", dnp, {{"Xo", Xout.data}, {"T3", T3}, {"V", V}});
+  mm(ctx, "Xo[nq] += W[np] * A[pq]", dnp, {{"Xo", Xout.data}, {"W", W.data}, {"A", A}});
+}
+
+// ---- L-BFGS ------------------------------------------------------------------------------------------
+
+void Lbfgs::init(Ctx& ctx, const std::vector<int>& n, const std::vector<int>& p, int m_) {
+  (void)ctx;
+  MERA_CHECK(m_ >= 0, MERA_EINVAL, "L-BFGS memory must be >= 0");
+  m = m_;
+  shape.init(n, p);
+  S.clear();
+  Y.clear();
+  for (int i = 0; i < m; ++i) {
+    S.emplace_back((size_t)shape.total * 8);
+    Y.emplace_back((size_t)shape.total * 8);
+  }
+  r.assign(m, 0.0);
+  order.clear();
+  q.alloc((size_t)shape.total * 8);
+  z.alloc((size_t)shape.total * 8);
+  t.alloc((size_t)shape.total * 8);
+}
+
+namespace {
+
+std::vector<MatView> views_of(const Flat& shape, double* base) {
+  std::vector<MatView> v;
+  for (int i = 0; i < shape.count(); ++i) v.push_back(MatView{shape.n[i], shape.p[i], base + shape.off[i]});
+  return v;
+}
+
+void gather(Ctx& ctx, const Flat& shape, const std::vector<MatView>& src, double* dst) {
+  for (int i = 0; i < shape.count(); ++i)
+    copy(ctx, VPtr{dst + shape.off[i], Prec::F64}, d64(src[i]), (int64_t)shape.n[i] * shape.p[i]);
+}
+
+void scatter(Ctx& ctx, const Flat& shape, const double* src, const std::vector<MatView>& dst, double scale) {
+  for (int i = 0; i < shape.count(); ++i) {
+    const int64_t k = (int64_t)shape.n[i] * shape.p[i];
+    copy(ctx, d64(dst[i]), VPtr{(void*)(src + shape.off[i]), Prec::F64}, k);
+    if (scale != 1.0) scal(ctx, scale, d64(dst[i]), k);
+  }
+}
+
+void apply_precond(Ctx& ctx, const Flat& shape, const std::vector<MatView>& W, Metric* met, double* x,
+                   double* out) {
+  if (!met || met->empty()) {
+    if (out != x) copy(ctx, VPtr{out, Prec::F64}, VPtr{x, Prec::F64}, shape.total);
+    return;
+  }
+  auto xv = views_of(shape, x), ov = views_of(shape, out);
+  for (int i = 0; i < shape.count(); ++i) precondition_one(ctx, W[i], xv[i], *met, i, -1.0, ov[i]);
+}
+
+}  // namespace
+
+double Lbfgs::step(Ctx& ctx, const std::vector<MatView>& W, const std::vector<MatView>& G, Metric* met,
+                   const std::vector<MatView>& dout) {
+  const int64_t N = shape.total;
+  double* qp = q.as<double>();
+  double* zp = z.as<double>();
+  double* tp = t.as<double>();
+  VPtr Q{qp, Prec::F64}, Z{zp, Prec::F64}, Tt{tp, Prec::F64};
+  gather(ctx, shape, G, qp);
+  std::vector<double> alphas(order.size());
+  for (int k = (int)order.size() - 1; k >= 0; --k) {
+    const int sl = order[k];
+    const double a = r[sl] * dot(ctx, VPtr{S[sl].ptr, Prec::F64}, Q, N);
+    alphas[k] = a;
+    axpby(ctx, -a, VPtr{Y[sl].ptr, Prec::F64}, 1.0, Q, N);
+  }
+  apply_precond(ctx, shape, W, met, qp, zp);
+  if (!order.empty()) {
+    const int sl = order.back();
+    apply_precond(ctx, shape, W, met, Y[sl].as<double>(), tp);
+    const double gamma = dot(ctx, VPtr{S[sl].ptr, Prec::F64}, VPtr{Y[sl].ptr, Prec::F64}, N) /
+                         dot(ctx, VPtr{Y[sl].ptr, Prec::F64}, Tt, N);
+    scal(ctx, gamma, Z, N);
+  }
+  for (size_t k = 0; k < order.size(); ++k) {
+    const int sl = order[k];
+    const double b = r[sl] * dot(ctx, VPtr{Y[sl].ptr, Prec::F64}, Z, N);
+    axpby(ctx, alphas[k] - b, VPtr{S[sl].ptr, Prec::F64}, 1.0, Z, N);
+  }
+  // d = -z
+  gather(ctx, shape, G, tp);
+  double slope = -dot(ctx, Tt, Z, N);
+  if (!(slope < 0.0)) {
+    order.clear();
+    apply_precond(ctx, shape, W, met, tp, zp);
+    slope = -dot(ctx, Tt, Z, N);
+  }
+  MERA_CHECK(std::isfinite(slope), MERA_ENONFINITE, "non-finite L-BFGS direction");
+  scatter(ctx, shape, zp, dout, -1.0);
+  return slope;
+}
+
+bool Lbfgs::push(Ctx& ctx, const std::vector<MatView>& Wn, const std::vector<MatView>& d, double alpha,
+                 const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew) {
+  const int64_t N = shape.total;
+  // transport the stored pairs to the new point
+  for (int sl : order) {
+    auto sv = views_of(shape, S[sl].as<double>()), yv = views_of(shape, Y[sl].as<double>());
+    for (int i = 0; i < shape.count(); ++i) {
+      stiefel_project_one(ctx, Wn[i], sv[i], sv[i]);
+      stiefel_project_one(ctx, Wn[i], yv[i], yv[i]);
+    }
+  }
+  if (m == 0) return false;
+  // candidate slot: a free one, or the oldest
+  int slot;
+  if ((int)order.size() < m) {
+    std::vector<bool> used(m, false);
+    for (int sl : order) used[sl] = true;
+    slot = 0;
+    while (used[slot]) ++slot;
+  } else {
+    slot = order.front();
+  }
+  double* sp = q.as<double>();  // build in scratch first; the oldest pair stays valid if rejected
+  double* yp = t.as<double>();
+  auto sv = views_of(shape, sp), yv = views_of(shape, yp);
+  for (int i = 0; i < shape.count(); ++i) {
+    const int64_t k = (int64_t)shape.n[i] * shape.p[i];
+    copy(ctx, d64(sv[i]), d64(d[i]), k);
+    scal(ctx, alpha, d64(sv[i]), k);
+    stiefel_project_one(ctx, Wn[i], sv[i], sv[i]);
+    stiefel_project_one(ctx, Wn[i], Gold[i], yv[i]);
+    axpby(ctx, 1.0, d64(Gnew[i]), -1.0, d64(yv[i]), k);
+  }
+  const double sy = dot(ctx, VPtr{sp, Prec::F64}, VPtr{yp, Prec::F64}, N);
+  const double ss = dot(ctx, VPtr{sp, Prec::F64}, VPtr{sp, Prec::F64}, N);
+  const double yy = dot(ctx, VPtr{yp, Prec::F64}, VPtr{yp, Prec::F64}, N);
+  if (!(sy > 1e-12 * std::sqrt(ss * yy))) return false;
+  copy(ctx, VPtr{S[slot].ptr, Prec::F64}, VPtr{sp, Prec::F64}, N);
+  copy(ctx, VPtr{Y[slot].ptr, Prec::F64}, VPtr{yp, Prec::F64}, N);
+  r[slot] = 1.0 / sy;
+  if ((int)order.size() == m) order.erase(order.begin());
+  order.push_back(slot);
+  return true;
+}
+
+// ---- optimiser ----------------------------------------------------------------------------------------
+
+JobSpec JobSpec::from_c(const mera_job& j) {
+  JobSpec s;
+  s.shape = j.shape;
+  auto dims = layer_dims(j.shape);
+  const int d3 = j.shape.d * j.shape.d * j.shape.d;
+  MERA_CHECK(j.h3_host != nullptr, MERA_EINVAL, "job: null h3");
+  MERA_CHECK(j.init_host != nullptr, MERA_EINVAL, "job: null initial tensors");
+  s.h3.assign(j.h3_host, j.h3_host + (size_t)d3 * d3);
+  for (int t = 0; t <= j.shape.T; ++t) {
+    const int a2 = dims[t].a * dims[t].a;
+    const double* u = j.init_host[2 * t];
+    const double* w = j.init_host[2 * t + 1];
+    MERA_CHECK(u && w, MERA_EINVAL, "job: null initial tensor");
+    s.init.emplace_back(u, u + (size_t)a2 * a2);
+    s.init.emplace_back(w, w + (size_t)a2 * dims[t].b);
+  }
+  MERA_CHECK(j.prec == MERA_FP64 || j.prec == MERA_FP32 || j.prec == MERA_BF16X3, MERA_EINVAL, "job: precision");
+  s.prec = j.prec == MERA_FP64 ? Prec::F64 : (j.prec == MERA_FP32 ? Prec::F32 : Prec::BF16X3);
+  s.m = j.lbfgs_m;
+  s.max_iter = j.max_iter;
+  s.grad_tol = j.grad_tol;
+  s.polish_tol = j.polish_tol;
+  s.precondition = j.precondition != 0;
+  s.max_ls_evals = j.max_ls_evals > 0 ? j.max_ls_evals : 10;
+  if (j.krylov.krylov_dim > 0) s.krylov.dim = j.krylov.krylov_dim;
+  if (j.krylov.max_restarts > 0) s.krylov.max_restarts = j.krylov.max_restarts;
+  if (j.krylov.tol > 0) s.krylov.tol = j.krylov.tol;
+  MERA_CHECK(s.m >= 0 && s.max_iter >= 0, MERA_EINVAL, "job: negative memory or iteration cap");
+  return s;
+}
+
+void Optimizer::start(Ctx& c, const JobSpec& j, int log_cap_) {
+  ctx = &c;
+  job = j;
+  log_cap = log_cap_;
+  dims = layer_dims(job.shape);
+  std::vector<int> n, p, rp;
+  for (const LayerDim& L : dims) {
+    n.push_back(L.a * L.a);
+    p.push_back(L.a * L.a);
+    n.push_back(L.a * L.a);
+    p.push_back(L.b);
+    rp.push_back(L.a * L.a);
+    rp.push_back(L.b);
+  }
+  for (Flat* F : {&W, &G, &Wn, &Gn, &D, &Xp, &dir}) F->init(n, p);
+  rv.init(rp, rp);
+  rvn.init(rp, rp);
+  hist.init(c, n, p, job.m);
+  const size_t h3n = job.h3.size();
+  h3dev.alloc(h3n * 8);
+  MERA_HIP(hipMemcpyAsync(h3dev.ptr, job.h3.data(), h3n * 8, hipMemcpyHostToDevice, c.stream));
+  for (int i = 0; i < W.count(); ++i)
+    MERA_HIP(hipMemcpyAsync(W.view(i).data, job.init[i].data(), job.init[i].size() * 8, hipMemcpyHostToDevice,
+                            c.stream));
+  prec = job.prec;
+  macs0 = c.macs;
+  iter = 0;
+  evals = 0;
+  done = false;
+  started = true;
+  result = OptResult();
+  f = evaluate(W, G, rv);
+  if (job.precondition) met.compute(c, rv.views());
+}
+
+double Optimizer::evaluate(const Flat& X, Flat& Gout, Flat& rvout) {
+  Point pt;
+  GradOut go;
+  for (int t = 0; t < (int)dims.size(); ++t) {
+    pt.u.push_back(X.view(2 * t).data);
+    pt.w.push_back(X.view(2 * t + 1).data);
+    go.Du.push_back(D.view(2 * t).data);
+    go.Dw.push_back(D.view(2 * t + 1).data);
+    if (job.precondition) {
+      go.rho_u.push_back(rvout.view(2 * t).data);
+      go.rho_w.push_back(rvout.view(2 * t + 1).data);
+    }
+  }
+  EvalOut r = energy_grad(*ctx, job.shape, pt, h3dev.as<double>(), prec, &warm, job.krylov, go);
+  evals++;
+  for (int i = 0; i < X.count(); ++i) stiefel_project_one(*ctx, X.view(i), D.view(i), Gout.view(i));
+  return r.energy;
+}
+
+bool Optimizer::advance() {
+  if (done) return true;
+  Ctx& c = *ctx;
+  gnorm = std::sqrt(inner(c, G.views(), G.views()));
+  MERA_CHECK(std::isfinite(gnorm), MERA_ENONFINITE, "non-finite gradient norm");
+  if ((int)result.log.size() < log_cap)
+    result.log.push_back(mera_iter_log{iter, evals, f, gnorm, last_alpha, (int)prec});
+  if (gnorm <= job.grad_tol) {
+    status = 0;
+    done = true;
+    return true;
+  }
+  if (iter >= job.max_iter) {
+    status = 1;
+    done = true;
+    return true;
+  }
+  // precision switch: below the polishing threshold the contractions move to FP64 and the point is re-evaluated
+  if (prec != Prec::F64 && job.polish_tol > 0 && gnorm < job.polish_tol) {
+    prec = Prec::F64;
+    polish_iter = iter;
+    f = evaluate(W, G, rv);
+    if (job.precondition) met.compute(c, rv.views());
+    return false;  // the iteration restarts from the re-evaluated point
+  }
+  Metric* mp = job.precondition ? &met : nullptr;
+  const auto Wv = W.views();
+  double slope = hist.step(c, Wv, G.views(), mp, dir.views());
+
+  double f_trial = 0.0;
+  auto phi = [&](double alpha, double& fa, double& dfa) {
+    for (int i = 0; i < W.count(); ++i) {
+      MatView xo = Xp.view(i);
+      stiefel_retract_one(c, W.view(i), dir.view(i), alpha, Wn.view(i), &xo);
+    }
+    fa = evaluate(Wn, Gn, rvn);
+    dfa = inner(c, Gn.views(), Xp.views());
+    f_trial = fa;
+  };
+  // Wolfe / approximate-Wolfe line search (same rules as the reference optimiser of the tests)
+  auto line_search = [&](double f0, double df0, double& alpha_out) {
+    const double c1 = 1e-4, c2 = 0.9, eps = 1e-6;
+    const double epsk = eps * std::fabs(f0);
+    double lo_a = 0.0, lo_df = df0;
+    double hi_a = std::numeric_limits<double>::infinity();
+    double hi_df = std::numeric_limits<double>::quiet_NaN();
+    bool has_hi_df = false;
+    double alpha = 1.0;
+    for (int k = 1; k <= job.max_ls_evals; ++k) {
+      double fa, dfa;
+      phi(alpha, fa, dfa);
+      if (!(std::isfinite(fa) && std::isfinite(dfa))) {
+        hi_a = alpha;
+        hi_df = std::numeric_limits<double>::infinity();
+        has_hi_df = true;
+      } else {
+        const bool wolfe = fa <= f0 + c1 * alpha * df0 && dfa >= c2 * df0;
+        const bool approx = (2.0 * c1 - 1.0) * df0 >= dfa && dfa >= c2 * df0 && fa <= f0 + epsk;
+        if (wolfe || approx) {
+          alpha_out = alpha;
+          return true;
+        }
+        if (dfa >= 0.0 || fa > f0 + epsk) {
+          hi_a = alpha;
+          hi_df = dfa;
+          has_hi_df = true;
+        } else {
+          lo_a = alpha;
+          lo_df = dfa;
+        }
+      }
+      if (std::isinf(hi_a)) {
+        alpha = 2.0 * alpha;
+        continue;
+      }
+      const double width = hi_a - lo_a;
+      double trial = std::numeric_limits<double>::quiet_NaN();
+      if (has_hi_df && std::isfinite(hi_df) && hi_df >= 0.0 && hi_df > lo_df)
+        trial = (lo_a * hi_df - hi_a * lo_df) / (hi_df - lo_df);
+      if (!(lo_a + 0.1 * width <= trial && trial <= hi_a - 0.1 * width)) trial = lo_a + 0.5 * width;
+      alpha = trial;
+    }
+    return false;
+  };
+  double alpha = 0.0;
+  bool ok = line_search(f, slope, alpha);
+  if (!ok && hist.size() > 0) {
+    hist.reset();
+    slope = hist.step(c, Wv, G.views(), mp, dir.views());
+    ok = line_search(f, slope, alpha);
+  }
+  if (!ok) {
+    status = 2;
+    done = true;
+    return true;
+  }
+  // Wn, Gn, rvn hold the accepted (last evaluated) point
+  hist.push(c, Wn.views(), dir.views(), alpha, G.views(), Gn.views());
+  std::swap(W.buf, Wn.buf);
+  std::swap(G.buf, Gn.buf);
+  std::swap(rv.buf, rvn.buf);
+  f = f_trial;
+  last_alpha = alpha;
+  iter++;
+  if (job.precondition) met.compute(c, rv.views());
+  return false;
+}
+
+void Optimizer::finish(std::vector<double*>* final_host) {
+  Ctx& c = *ctx;
+  if (final_host && !final_host->empty()) {
+    MERA_CHECK((int)final_host->size() == W.count(), MERA_EINVAL, "final tensor count");
+    for (int i = 0; i < W.count(); ++i)
+      if ((*final_host)[i])
+        MERA_HIP(hipMemcpyAsync((*final_host)[i], W.view(i).data, (size_t)numel(W.view(i)) * 8,
+                                hipMemcpyDeviceToHost, c.stream));
+  }
+  c.sync();
+  result.energy = f;
+  result.gnorm = std::sqrt(inner(c, G.views(), G.views()));
+  result.iterations = iter;
+  result.evaluations = evals;
+  result.status = status;
+  result.polish_iter = polish_iter;
+  result.macs = c.macs - macs0;
+}
+
+size_t Optimizer::device_bytes() const {
+  size_t b = 0;
+  for (const Flat* F : {&W, &G, &Wn, &Gn, &D, &Xp, &dir, &rv, &rvn}) b += F->buf.bytes;
+  b += warm.rho.bytes + warm.ht.bytes + h3dev.bytes;
+  for (auto& x : hist.S) b += x.bytes;
+  for (auto& x : hist.Y) b += x.bytes;
+  return b;
+}
+
+OptResult optimize(Ctx& ctx, const JobSpec& job, std::vector<double*>* final_host, int log_cap) {
+  const auto t0 = std::chrono::steady_clock::now();
+  Optimizer opt;
+  opt.start(ctx, job, log_cap);
+  while (!opt.advance()) {
+  }
+  opt.finish(final_host);
+  opt.result.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return opt.result;
+}
+
+}  // namespace mera

@@ -1,0 +1,120 @@
+// Stiefel-manifold operations, Hilbert-space preconditioner, L-BFGS and the optimisation driver
+// (Sec. 2 and Sec. 3 of arXiv:2007.03638). All arithmetic here is FP64 on the device; host code only
+// handles scalars (inner products, line-search decisions).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+#include "mera.h"
+
+namespace mera {
+
+struct MatView {
+  int n = 0, p = 0;
+  double* data = nullptr;
+};
+
+// Points and tangent vectors of a product of Stiefel manifolds, stored as one flat FP64 device buffer.
+struct Flat {
+  std::vector<int> n, p;
+  std::vector<int64_t> off;
+  int64_t total = 0;
+  DevBuf buf;
+  Flat() = default;
+  Flat(const std::vector<int>& n_, const std::vector<int>& p_) { init(n_, p_); }
+  void init(const std::vector<int>& n_, const std::vector<int>& p_);
+  int count() const { return (int)n.size(); }
+  double* ptr() const { return buf.as<double>(); }
+  MatView view(int i) const { return MatView{n[i], p[i], buf.as<double>() + off[i]}; }
+  std::vector<MatView> views() const;
+};
+
+// G = D - W sym(W^T D)                                      (eq. stiefel_gradient, real case)
+void stiefel_project_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& G);
+// W_out = polar(W + alpha X), X_out = dW_out/dalpha (nullable)
+void stiefel_retract_one(Ctx& ctx, const MatView& W, const MatView& X, double alpha, const MatView& Wout,
+                         const MatView* Xout);
+
+// Eigendecompositions of the preconditioner metrics rho_v (one per factor).
+struct Metric {
+  std::vector<DevBuf> V, lam, f, g;
+  std::vector<int> p;
+  void compute(Ctx& ctx, const std::vector<MatView>& rho);
+  bool empty() const { return p.empty(); }
+};
+// X_out = preconditioned X for factor i (Sec. 3 eqs. preconditioner / preconditioner_solution); delta < 0
+// takes delta = ||X||_F (Sec. 4). X_out may alias X.
+void precondition_one(Ctx& ctx, const MatView& W, const MatView& X, Metric& met, int i, double delta,
+                      const MatView& Xout);
+
+struct Lbfgs {
+  int m = 8;
+  Flat shape;                    // factor sizes
+  std::vector<DevBuf> S, Y;      // ring slots, each `total` doubles
+  std::vector<double> r;         // 1 / <s_i, y_i>
+  std::vector<int> order;        // slot indices, oldest first
+  DevBuf q, z, t;
+  void init(Ctx& ctx, const std::vector<int>& n, const std::vector<int>& p, int m);
+  void reset() { order.clear(); }
+  int size() const { return (int)order.size(); }
+  // two-loop recursion; returns slope <G, d>
+  double step(Ctx& ctx, const std::vector<MatView>& W, const std::vector<MatView>& G, Metric* met,
+              const std::vector<MatView>& dout);
+  bool push(Ctx& ctx, const std::vector<MatView>& Wn, const std::vector<MatView>& d, double alpha,
+            const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew);
+};
+
+double inner(Ctx& ctx, const std::vector<MatView>& X, const std::vector<MatView>& Y);
+
+struct OptResult {
+  double energy = 0, gnorm = 0, seconds = 0, macs = 0;
+  int iterations = 0, evaluations = 0, status = 0, polish_iter = -1;
+  std::vector<mera_iter_log> log;
+};
+
+struct JobSpec {
+  mera_shape shape{};
+  std::vector<double> h3;                  // d^3 x d^3 host
+  std::vector<std::vector<double>> init;   // 2(T+1) host matrices
+  Prec prec = Prec::F64;
+  int m = 8, max_iter = 100, max_ls_evals = 10;
+  double grad_tol = 1e-10, polish_tol = 0.0;
+  bool precondition = true;
+  KrylovOpts krylov;
+  static JobSpec from_c(const mera_job& j);
+};
+
+// Whole optimisation of one job on `ctx` (blocking). Final tensors copied to `final_host` if non-empty.
+OptResult optimize(Ctx& ctx, const JobSpec& job, std::vector<double*>* final_host, int log_cap);
+
+// Resumable optimiser state machine used by the server: each call to advance() runs one iteration
+// (its evaluations and Stiefel steps) and returns true once the job has finished.
+struct Optimizer {
+  Ctx* ctx = nullptr;
+  JobSpec job;
+  std::vector<LayerDim> dims;
+  Flat W, G, Wn, Gn, D, Xp, dir, rv, rvn;
+  DevBuf h3dev;
+  Warm warm;
+  Lbfgs hist;
+  Metric met;
+  Prec prec = Prec::F64;
+  double f = 0, gnorm = 0, last_alpha = 0;
+  int iter = 0, evals = 0, status = -1, polish_iter = -1;
+  bool done = false, started = false;
+  double macs0 = 0;
+  OptResult result;
+  int log_cap = 0;
+
+  void start(Ctx& c, const JobSpec& j, int log_cap_ = 0);
+  bool advance();                       // one iteration
+  void finish(std::vector<double*>* final_host);
+  size_t device_bytes() const;
+
+ private:
+  double evaluate(const Flat& X, Flat& Gout, Flat& rvout);   // energy; fills G = P(D) and metrics
+  void precond_all(const std::vector<MatView>& W, const Flat& X, Flat& out);
+};
+
+}  // namespace mera

@@ -1,0 +1,67 @@
+"""run_optimize (FP64 and FP32 with polishing) against the oracle's optimiser and energy (through the C ABI)."""
+import numpy as np
+import pytest
+
+from gpu_helpers import require_gpu
+from oracle import mera as om
+from oracle import model, optim
+from paper_2007_03638_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    from paper_2007_03638_amd import api
+    return api.Context(0)
+
+
+def _init(seed, chi, T):
+    dims = om.layer_dims(chi, T)
+    return [m for pair in inputs.mera_init(seed, dims) for m in pair]
+
+
+@pytest.mark.parametrize("precondition", [True, False])
+def test_fp64_trajectory_matches_oracle(ctx, precondition):
+    chi, T, iters = 4, 2, 8
+    W0 = _init(0, chi, T)
+    h3 = model.tfim_h3(1.0)
+    prob = optim.Problem(h3, chi, T)
+    log = []
+    _, f_ref, g_ref, info = optim.optimize(W0, prob, m=8, max_iter=iters, use_precond=precondition, log=log)
+    got = ctx.run_optimize(2, 4, h3, W0, prec="fp64", m=8, max_iter=iters, grad_tol=0.0,
+                           precondition=precondition, log_cap=64, want_final=True)
+    print("gpu", [(r["iter"], r["evals"], r["energy"]) for r in got["log"]], flush=True)
+    print("ref", [(r["iter"], r["evals"], r["energy"]) for r in log], flush=True)
+    assert len(got["log"]) >= len(log)
+    for a, b in zip(got["log"], log):
+        assert a["evals"] == b["evals"]
+        assert abs(a["energy"] - b["energy"]) <= 1e-10 * abs(b["energy"])
+        assert abs(a["gnorm"] - b["gnorm"]) <= 1e-7 * b["gnorm"]
+    assert abs(got["energy"] - f_ref) <= 1e-10 * abs(f_ref)
+    # the oracle re-evaluates the returned point
+    W = got["final"]
+    params = [(W[2 * i], W[2 * i + 1]) for i in range(T + 1)]
+    for w in W:
+        assert np.max(np.abs(w.T @ w - np.eye(w.shape[1]))) < 1e-13
+    assert abs(om.energy_only(params, h3, chi, T) - got["energy"]) <= 1e-12 * abs(got["energy"])
+
+
+def test_fp32_with_fp64_polish(ctx):
+    chi, T = 4, 2
+    W0 = _init(3, chi, T)
+    h3 = model.tfim_h3(1.0)
+    got = ctx.run_optimize(2, 4, h3, W0, prec="fp32", m=8, max_iter=40, grad_tol=1e-9, polish_tol=2e-2,
+                           log_cap=64, want_final=True)
+    print({k: got[k] for k in ("energy", "gnorm", "iterations", "evaluations", "status", "polish_iter")},
+          flush=True)
+    assert got["polish_iter"] >= 0
+    W = got["final"]
+    params = [(W[2 * i], W[2 * i + 1]) for i in range(T + 1)]
+    e_ref = om.energy_only(params, h3, chi, T)
+    # after the switch the evaluations are FP64: the returned energy matches the oracle to 1e-10
+    assert abs(e_ref - got["energy"]) <= 1e-10 * abs(e_ref)
+    energies = [r["energy"] for r in got["log"]]
+    assert energies[-1] < energies[0]
+    assert got["energy"] / 2 > model.tfim_exact_energy_per_spin(1.0)
