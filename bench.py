@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark: energy+gradient evaluations per second of the infinite binary MERA optimisation on one MI355X.
+
+Workload (default): TFIM h = 1 with two spins per blocked site (d = 4, 3-site term), chi = 24, three transition
+layers plus the scale-invariant layer, Haar-random initial tensors (seed 2), FP32 MFMA contractions with FP64
+retraction / density-matrix normalisation / L-BFGS scalars, Hilbert-space preconditioner, L-BFGS memory 8,
+warm-started Krylov solves (dimension 4). One step = one L-BFGS iteration of the library's optimiser
+(mera_opt_step): its energy+gradient evaluation(s), projection, preconditioned two-loop, line search,
+polar retraction and transport. value = evaluations / second over the timed steps.
+
+Prints ONE JSON line. `--serve` instead runs a serving stream through the continuous-batching server and reports
+p50/p99 time-to-converged and jobs/s.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MERA energy+gradient evals/s at chi=24 (TFLOP/s, % peak); job p50/p99 latency"
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--chi", type=int, default=24)
+    ap.add_argument("--T", type=int, default=3)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-chi", type=int, default=14)
+    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--jobs", type=int, default=16)
+    ap.add_argument("--serve-iters", type=int, default=30)
+    return ap.parse_args()
+
+
+def cpu_baseline(sample_chi, gpu_flops_per_eval):
+    """Times the FP64 oracle's scale-invariant ascending map at a smaller bond dimension on the host cores and
+    converts its flop rate to evaluations/s of the benchmark workload (same algorithmic flop count per eval)."""
+    from oracle import mera as om
+    from paper_2007_03638_amd import inputs
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    chi = sample_chi
+    (u, w), = inputs.mera_init(0, [(chi, chi)])
+    h = inputs.symmetric_operator(1, chi ** 3)
+    om.ascend(h, u, w, chi, chi)  # warm BLAS
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        om.ascend(h, u, w, chi, chi)
+        reps += 1
+        if time.perf_counter() - t0 > 10.0:
+            break
+    dt = time.perf_counter() - t0
+    # two diagrams, each 2 chi^9 + 3 chi^8 + 2 chi^6 + 2 chi^5 multiply-adds in a pairwise order
+    macs = 2 * (2 * chi ** 9 + 3 * chi ** 8 + 2 * chi ** 6 + 2 * chi ** 5)
+    rate = 2.0 * macs * reps / dt
+    return dict(value=rate / gpu_flops_per_eval, unit="evals/s", cores=threads, kind="oracle",
+                sample=f"oracle FP64 ascending superoperator at chi={chi} ({reps} applications in {dt:.1f} s, "
+                       f"{rate / 1e9:.1f} GFLOP/s), scaled by the algorithmic flops of one chi=24 evaluation "
+                       f"({gpu_flops_per_eval:.3e})")
+
+
+def run_eval_bench(a):
+    import torch
+    from paper_2007_03638_amd import api, inputs
+
+    ctx = api.Context(0)
+    dims = api.layer_dims(a.T, a.chi)
+    init = [m for pair in inputs.mera_init(a.seed, dims) for m in pair]
+    h3 = api.h3_tfim(1.0)
+    opt = ctx.optimizer(T=a.T, chi=a.chi, h3=h3, init=init, prec=a.prec, m=8, max_iter=10 ** 6, grad_tol=0.0,
+                        polish_tol=0.0, precondition=True, max_ls_evals=10)
+    state = None
+    for _ in range(a.warmup):
+        _, state = opt.step()
+    # state after the untimed part (with no warmup: the initial evaluation done at creation)
+    s0 = state if state is not None else {"evaluations": 1, "macs": ctx.macs()}
+    ctx.profile(True)
+    ctx.kernel_stats()  # clear
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        _, state = opt.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = ctx.kernel_stats()
+    ctx.profile(False)
+    dt = t1 - t0
+    evals = state["evaluations"] - s0["evaluations"]
+    macs = state["macs"] - s0["macs"]
+    flops = 2.0 * macs
+    top = stats[0]
+    achieved = top["flops"] / top["seconds"] / 1e12
+    gemm_time = sum(s["seconds"] for s in stats)
+    peak = PEAK_TFLOPS[a.prec]
+    out = {
+        "metric": METRIC,
+        "value": evals / dt,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1000.0 * dt / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3 (f32 accumulate)"}[a.prec],
+        "data": "synthetic",
+        "config": {"workload": f"infinite binary MERA, TFIM h=1 (d=4, 3-site term), chi={a.chi}, T={a.T} + "
+                               f"scale-invariant layer, {a.prec} contractions, FP64 manifold/L-BFGS, "
+                               f"preconditioned L-BFGS m=8, seed {a.seed}",
+                   "chi": a.chi, "T": a.T, "prec": a.prec, "evaluations": evals},
+        "tflops": flops / dt / 1e12,
+        "pct_peak": 100.0 * flops / dt / 1e12 / peak,
+        "energy": state["energy"],
+        "gnorm": state["gnorm"],
+        "contraction_time_fraction": gemm_time / dt,
+        "roofline": {"bound": "mfma", "kernel": top["kernel"], "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "launches": top["launches"], "avg_launch_ms": 1000.0 * top["seconds"] / top["launches"]},
+        "kernels": [{"kernel": s["kernel"], "launches": s["launches"], "ms": 1000.0 * s["seconds"],
+                     "tflops": s["flops"] / s["seconds"] / 1e12} for s in stats[:6]],
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(a.cpu_sample_chi, flops / max(evals, 1))
+    return out
+
+
+def run_serve_bench(a):
+    """Serving stream: Poisson arrivals (mean gap 2 s, seed 3), TFIM h ~ U[0.5, 1.5] or XXZ delta ~ U[-0.5, 1.5]
+    (50/50), chi from {8, 12, 16, 20}, FP32 contractions with FP64 polishing, stop at |G| <= 1e-7 or the
+    iteration cap."""
+    from paper_2007_03638_amd import api, inputs
+    rng = np.random.default_rng(3)
+    ctx = api.Context(0)
+    srv = api.Server(ctx, hbm_budget=200 << 30, max_slots=8)
+    jobs = []
+    t_arr = 0.0
+    for k in range(a.jobs):
+        t_arr += rng.exponential(2.0)
+        chi = int(rng.choice([8, 12, 16, 20]))
+        if rng.random() < 0.5:
+            h3 = api.h3_tfim(rng.uniform(0.5, 1.5))
+        else:
+            h3 = api.h3_xxz(rng.uniform(-0.5, 1.5))
+        dims = api.layer_dims(3, chi)
+        init = [m for pair in inputs.mera_init(1000 + k, dims) for m in pair]
+        jobs.append((t_arr, dict(T=3, chi=chi, h3=h3, init=init, prec="fp32", m=8, max_iter=a.serve_iters,
+                                 grad_tol=1e-7, polish_tol=1e-5)))
+    t0 = time.perf_counter()
+    ids, arrivals = [], []
+    pending = list(jobs)
+    results = {}
+    while pending or len(results) < len(ids):
+        now = time.perf_counter() - t0
+        while pending and pending[0][0] <= now:
+            arr, spec = pending.pop(0)
+            ids.append(srv.submit(**spec))
+            arrivals.append(arr)
+        for i in ids:
+            if i not in results:
+                r = srv.poll(i)
+                if r is not None:
+                    results[i] = (time.perf_counter() - t0, r)
+        time.sleep(0.005)
+    makespan = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([results[i][1]["queued_seconds"] + results[i][1]["seconds"] for i in ids])
+    conv = sum(1 for i in ids if results[i][1]["status"] == 0)
+    return {
+        "metric": METRIC,
+        "value": float(np.percentile(lat, 50)),
+        "unit": "s (p50 time-to-converged)",
+        "n_gpus": 1, "steps": a.jobs, "warmup": 0,
+        "ms_per_step": 1000.0 * makespan / a.jobs,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serving stream of {a.jobs} jobs, Poisson arrivals mean gap 2 s (seed 3), TFIM/XXZ "
+                               f"50/50, chi in {{8,12,16,20}}, T=3, FP32 + FP64 polish below 1e-5, "
+                               f"stop at |G|<=1e-7 or {a.serve_iters} iterations"},
+        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+        "jobs_per_s": a.jobs / makespan, "converged": conv, "makespan_s": makespan,
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (this build runs on a single "
+              f"MI355X; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    out = run_serve_bench(a) if a.serve else run_eval_bench(a)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

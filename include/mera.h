@@ -72,6 +72,18 @@ mera_status mera_ctx_trim(mera_ctx* ctx);
  * the product of all leg dimensions of each pairwise step, no padding). */
 double mera_ctx_macs(const mera_ctx* ctx);
 
+/* Kernel timing: with profiling on, every contraction launch is bracketed by HIP events on the context
+ * stream. mera_ctx_kernel_stats synchronises, aggregates the recorded launches by kernel variant into
+ * out[0..cap) (largest total time first), clears the records and returns the number of variants (<0: error). */
+typedef struct {
+  char kernel[80];   /* kernel variant: precision, tile, operand load order, split-K */
+  int launches;
+  double seconds;    /* summed launch durations (event to event)                      */
+  double flops;      /* summed algorithmic flops, 2 x M x N x K per launch            */
+} mera_kernel_stat;
+mera_status mera_ctx_profile(mera_ctx* ctx, int enable);
+int mera_ctx_kernel_stats(mera_ctx* ctx, mera_kernel_stat* out, int cap);
+
 /* Layer dimensions: a_out[0..T], b_out[0..T] (host arrays of T+1 ints). */
 mera_status mera_layer_dims(const mera_shape* shape, int* a_out, int* b_out);
 
@@ -201,6 +213,17 @@ typedef struct {
 } mera_result;
 
 typedef struct { int iter; int evals; double energy; double gnorm; double alpha; int prec; } mera_iter_log;
+
+/* Step-wise optimisation: the same algorithm as run_optimize, one iteration per mera_opt_step call.
+ * mera_opt_create copies the job, allocates the state on the context's device and evaluates the initial
+ * point. mera_opt_step runs one iteration (its line-search evaluations and Stiefel steps); *done becomes 1
+ * when the job has converged, hit its iteration cap or failed; `state` (nullable) receives the current
+ * energy, ||G||, iteration and evaluation counts. mera_opt_final copies the current tensors to host buffers. */
+typedef struct mera_opt mera_opt;
+mera_status mera_opt_create(mera_ctx* ctx, const mera_job* job, mera_opt** out);
+mera_status mera_opt_step(mera_ctx* ctx, mera_opt* opt, int* done, mera_result* state);
+mera_status mera_opt_final(mera_ctx* ctx, mera_opt* opt, double* const* final_host);
+void mera_opt_destroy(mera_opt* opt);
 
 /* Blocking single-job optimisation (Sec. 3 L-BFGS with Wolfe / approximate-Wolfe line search on the product
  * of Stiefel manifolds, Sec. 4 MERA cost). final_host (nullable): 2(T+1) host buffers receiving the final

@@ -44,6 +44,10 @@ class IterLog(ctypes.Structure):
                 ("prec", c_int)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_char * 80), ("launches", c_int), ("seconds", c_double), ("flops", c_double)]
+
+
 MAT_P = ctypes.POINTER(MeraMat)
 
 # name -> (restype, argtypes)
@@ -78,6 +82,12 @@ SIGNATURES = {
     "run_optimize": (c_int, [c_void_p, ctypes.POINTER(Job), ctypes.POINTER(Result),
                              ctypes.POINTER(ctypes.POINTER(c_double)), ctypes.POINTER(IterLog), c_int,
                              ctypes.POINTER(c_int)]),
+    "mera_ctx_profile": (c_int, [c_void_p, c_int]),
+    "mera_ctx_kernel_stats": (c_int, [c_void_p, ctypes.POINTER(KernelStat), c_int]),
+    "mera_opt_create": (c_int, [c_void_p, ctypes.POINTER(Job), ctypes.POINTER(c_void_p)]),
+    "mera_opt_step": (c_int, [c_void_p, c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(Result)]),
+    "mera_opt_final": (c_int, [c_void_p, c_void_p, ctypes.POINTER(ctypes.POINTER(c_double))]),
+    "mera_opt_destroy": (None, [c_void_p]),
     "mera_server_create": (c_int, [c_void_p, c_size_t, c_int, ctypes.POINTER(c_void_p)]),
     "mera_server_submit": (c_int, [c_void_p, ctypes.POINTER(Job), ctypes.POINTER(c_uint64)]),
     "mera_server_poll": (c_int, [c_void_p, c_uint64, ctypes.POINTER(Result)]),

@@ -112,6 +112,20 @@ class Context:
     def trim(self):
         self._check(self._lib.mera_ctx_trim(self.ptr), "mera_ctx_trim")
 
+    def profile(self, enable=True):
+        self._check(self._lib.mera_ctx_profile(self.ptr, 1 if enable else 0), "mera_ctx_profile")
+
+    def kernel_stats(self, cap=64):
+        arr = (L.KernelStat * cap)()
+        n = self._lib.mera_ctx_kernel_stats(self.ptr, arr, cap)
+        if n < 0:
+            self._check(n, "mera_ctx_kernel_stats")
+        return [dict(kernel=arr[i].kernel.decode(), launches=arr[i].launches, seconds=arr[i].seconds,
+                     flops=arr[i].flops) for i in range(min(n, cap))]
+
+    def optimizer(self, **job_kwargs):
+        return Optimizer(self, **job_kwargs)
+
     def _dev(self, x):
         return torch.as_tensor(x, dtype=torch.float64).to(self.device).contiguous()
 
@@ -253,6 +267,41 @@ def make_job(T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, p
                 max_iter, grad_tol, polish_tol, 1 if precondition else 0, max_ls_evals,
                 L.KrylovOpts(kr.get("dim", 0), kr.get("max_restarts", 0), kr.get("tol", 0.0)))
     return job, (h3c, mats, ptrs)
+
+
+class Optimizer:
+    """Step-wise optimisation (mera_opt_*): one L-BFGS iteration per step()."""
+
+    def __init__(self, ctx, **job_kwargs):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        self.shapes = [np.asarray(x).shape for x in job_kwargs["init"]]
+        job, keep = make_job(**job_kwargs)
+        self.ptr = ctypes.c_void_p()
+        ctx._check(self._lib.mera_opt_create(ctx.ptr, ctypes.byref(job), ctypes.byref(self.ptr)), "mera_opt_create")
+        del keep
+
+    def step(self):
+        done = ctypes.c_int()
+        res = L.Result()
+        self.ctx._check(self._lib.mera_opt_step(self.ctx.ptr, self.ptr, ctypes.byref(done), ctypes.byref(res)),
+                        "mera_opt_step")
+        return bool(done.value), result_dict(res)
+
+    def final(self):
+        outs = [np.zeros(s) for s in self.shapes]
+        arr = (ctypes.POINTER(ctypes.c_double) * len(outs))(
+            *[o.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for o in outs])
+        self.ctx._check(self._lib.mera_opt_final(self.ctx.ptr, self.ptr, arr), "mera_opt_final")
+        return outs
+
+    def __del__(self):
+        try:
+            if self.ptr.value:
+                self._lib.mera_opt_destroy(self.ptr)
+                self.ptr.value = None
+        except Exception:
+            pass
 
 
 class LBFGS:

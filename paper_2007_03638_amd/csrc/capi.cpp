@@ -11,7 +11,13 @@
 namespace mera {
 
 Ctx::Ctx() : plans(new PlanCache) {}
-Ctx::~Ctx() {}
+Ctx::~Ctx() {
+  for (auto& r : records) {
+    event_pool.push_back(r.start);
+    event_pool.push_back(r.stop);
+  }
+  for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+}
 
 }  // namespace mera
 
@@ -470,6 +476,125 @@ mera_status run_optimize(mera_ctx* ctx, const mera_job* job, mera_result* out, d
     for (size_t i = 0; i < r.log.size() && (int)i < log_cap; ++i) log[i] = r.log[i];
     if (log_len) *log_len = (int)std::min<size_t>(r.log.size(), (size_t)log_cap);
   });
+}
+
+}  // extern "C"
+
+// ---- profiling and step-wise optimisation ----------------------------------------------------------------
+
+#include <algorithm>
+#include <chrono>
+
+struct mera_opt {
+  mera::Optimizer o;
+  int device = 0;
+  mera_ctx* owner = nullptr;
+};
+
+extern "C" {
+
+mera_status mera_ctx_profile(mera_ctx* ctx, int enable) {
+  if (!ctx) return MERA_EINVAL;
+  ctx->c.profiling = enable != 0;
+  return MERA_OK;
+}
+
+int mera_ctx_kernel_stats(mera_ctx* ctx, mera_kernel_stat* out, int cap) {
+  if (!ctx || cap < 0 || (cap > 0 && !out)) return MERA_EINVAL;
+  try {
+    DeviceGuard g(ctx->c.device);
+    ctx->c.sync();
+    struct Agg {
+      int n = 0;
+      double s = 0, f = 0;
+    };
+    std::map<std::string, Agg> agg;
+    for (auto& r : ctx->c.records) {
+      float ms = 0.f;
+      MERA_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+      Agg& a = agg[r.kernel];
+      a.n++;
+      a.s += ms * 1e-3;
+      a.f += r.flops;
+      ctx->c.event_pool.push_back(r.start);
+      ctx->c.event_pool.push_back(r.stop);
+    }
+    ctx->c.records.clear();
+    std::vector<std::pair<std::string, Agg>> v(agg.begin(), agg.end());
+    std::sort(v.begin(), v.end(), [](auto& a, auto& b) { return a.second.s > b.second.s; });
+    for (int i = 0; i < (int)v.size() && i < cap; ++i) {
+      std::memset(&out[i], 0, sizeof(out[i]));
+      std::strncpy(out[i].kernel, v[i].first.c_str(), sizeof(out[i].kernel) - 1);
+      out[i].launches = v[i].second.n;
+      out[i].seconds = v[i].second.s;
+      out[i].flops = v[i].second.f;
+    }
+    return (int)v.size();
+  } catch (const Error& e) {
+    ctx->c.last_error = e.what();
+    return e.status;
+  }
+}
+
+mera_status mera_opt_create(mera_ctx* ctx, const mera_job* job, mera_opt** out) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(job && out, MERA_EINVAL, "null argument");
+    JobSpec spec = JobSpec::from_c(*job);
+    DeviceGuard g(ctx->c.device);
+    auto* o = new mera_opt;
+    o->device = ctx->c.device;
+    o->owner = ctx;
+    try {
+      o->o.start(ctx->c, spec, 0);
+    } catch (...) {
+      delete o;
+      throw;
+    }
+    *out = o;
+  });
+}
+
+mera_status mera_opt_step(mera_ctx* ctx, mera_opt* opt, int* done, mera_result* state) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(opt && opt->owner == ctx, MERA_EINVAL, "optimiser belongs to another context");
+    DeviceGuard g(ctx->c.device);
+    const bool d = opt->o.advance();
+    if (done) *done = d ? 1 : 0;
+    if (state) {
+      std::memset(state, 0, sizeof(*state));
+      state->energy = opt->o.f;
+      state->gnorm = opt->o.gnorm;
+      state->iterations = opt->o.iter;
+      state->evaluations = opt->o.evals;
+      state->status = d ? opt->o.status : -1;
+      state->polish_iter = opt->o.polish_iter;
+      state->macs = ctx->c.macs - opt->o.macs0;
+    }
+  });
+}
+
+mera_status mera_opt_final(mera_ctx* ctx, mera_opt* opt, double* const* final_host) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(opt && opt->owner == ctx && final_host, MERA_EINVAL, "mera_opt_final arguments");
+    DeviceGuard g(ctx->c.device);
+    for (int i = 0; i < opt->o.W.count(); ++i) {
+      MatView v = opt->o.W.view(i);
+      MERA_HIP(hipMemcpyAsync(final_host[i], v.data, (size_t)v.n * v.p * 8, hipMemcpyDeviceToHost, ctx->c.stream));
+    }
+    ctx->c.sync();
+  });
+}
+
+void mera_opt_destroy(mera_opt* opt) {
+  if (!opt) return;
+  try {
+    DeviceGuard g(opt->device);
+    delete opt;
+  } catch (...) {
+  }
 }
 
 }  // extern "C"

@@ -74,6 +74,13 @@ inline size_t elem_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
 struct PlanCache;  // network.h
 
+// Per-launch timing of contraction kernels with HIP events on the context stream (profiling mode).
+struct LaunchRecord {
+  std::string kernel;
+  hipEvent_t start, stop;
+  double flops;
+};
+
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -83,7 +90,19 @@ struct Ctx {
   std::map<std::string, DevBuf> scratch;
   std::unique_ptr<PlanCache> plans;
   DevBuf red;        // reduction partials (doubles)
-  DevBuf red_host_flag;
+  bool profiling = false;
+  std::vector<LaunchRecord> records;
+  std::vector<hipEvent_t> event_pool;
+  hipEvent_t take_event() {
+    if (!event_pool.empty()) {
+      hipEvent_t e = event_pool.back();
+      event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    MERA_HIP(hipEventCreate(&e));
+    return e;
+  }
 
   Ctx();
   ~Ctx();

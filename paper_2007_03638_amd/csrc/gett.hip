@@ -58,64 +58,64 @@ template <> struct Mma<double> {
 };
 
 // Tile loader: BMN x BK tile of an operand whose element (r, k) lives at base + off_r[r] + off_k[k].
-// KFAST: consecutive threads walk k (unit-stride leg is a K leg); else consecutive threads walk r.
+// KFAST: consecutive threads walk k (the operand's unit-stride leg is a K leg); each thread then owns one k
+// and PER rows. Otherwise consecutive threads walk r in groups of 64; each thread owns NR rows and NK k's.
+// Row offsets are read once per tile row; k offsets for the next tile are fetched one tile ahead (fetch_k),
+// so the data loads of a tile never wait on a table lookup. Loads are unconditional (tables are padded with
+// offset 0, which addresses a valid element) and masked afterwards, keeping the loads in one batch.
 template <typename T, int BMN, int BK, bool KFAST>
 struct Loader {
   static constexpr int PER = BMN * BK / 256;
   static_assert(PER >= 1 && (BMN * BK) % 256 == 0, "tile too small for 256 threads");
-  static_assert(KFAST ? (256 % BK == 0) : (256 % BMN == 0), "thread mapping");
-  static constexpr int RSTEP = KFAST ? 256 / BK : 1;
-  static constexpr int KSTEP = KFAST ? 1 : 256 / BMN;
-  int64_t roff[KFAST ? PER : 1];
-  bool rval[KFAST ? PER : 1];
+  static_assert(KFAST ? (256 % BK == 0) : (BMN % 64 == 0), "thread mapping");
+  static constexpr int NR = KFAST ? PER : BMN / 64;   // rows per thread
+  static constexpr int NK = KFAST ? 1 : PER / NR;     // k's per thread
+  static constexpr int RSTEP = KFAST ? 256 / BK : 64;
+  static constexpr int KSTEP = KFAST ? 1 : 4;         // 256 threads / 64 rows per group
+  static_assert(KFAST || NK * KSTEP == BK, "k coverage");
+  int64_t roff[NR];
+  bool rval[NR];
+  int64_t koff[NK];
   int r0, k0;
   T reg[PER];
+  bool okm[PER];  // element in range; applied when staging so the mask does not wait on the loads
 
   __device__ inline void init(const int64_t* off_r, int64_t rbase, int64_t R, int tid) {
     if (KFAST) {
       k0 = tid % BK;
       r0 = tid / BK;
-#pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        int64_t r = rbase + r0 + i * RSTEP;
-        roff[i] = off_r[r];
-        rval[i] = r < R;
-      }
     } else {
-      r0 = tid % BMN;
-      k0 = tid / BMN;
-      int64_t r = rbase + r0;
-      roff[0] = off_r[r];
-      rval[0] = r < R;
+      r0 = tid % 64;
+      k0 = tid / 64;
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      int64_t r = rbase + r0 + i * RSTEP;
+      roff[i] = off_r[r];
+      rval[i] = r < R;
     }
   }
-  __device__ inline void load(const T* __restrict__ base, const int64_t* __restrict__ off_k, int64_t kt,
-                              int64_t kend) {
-    if (KFAST) {
-      int64_t k = kt + k0;
-      bool kv = k < kend;
-      int64_t ko = off_k[k];
+  // k offsets of tile kt (kt < padded K)
+  __device__ inline void fetch_k(const int64_t* __restrict__ off_k, int64_t kt) {
 #pragma unroll
-      for (int i = 0; i < PER; ++i) reg[i] = (kv && rval[i]) ? base[roff[i] + ko] : T(0);
-    } else {
+    for (int j = 0; j < NK; ++j) koff[j] = off_k[kt + k0 + j * KSTEP];
+  }
+  // element (i): row index i % NR, k index i / NR
+  __device__ inline void load(const T* __restrict__ base, int64_t kt, int64_t kend) {
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        int64_t k = kt + k0 + i * KSTEP;
-        int64_t ko = off_k[k];
-        reg[i] = (k < kend && rval[0]) ? base[roff[0] + ko] : T(0);
-      }
-    }
+    for (int i = 0; i < PER; ++i) reg[i] = base[roff[i % NR] + koff[i / NR]];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) okm[i] = rval[i % NR] && (kt + k0 + (i / NR) * KSTEP < kend);
+  }
+  __device__ inline T value(int i) const { return okm[i] ? reg[i] : T(0); }
+  __device__ inline int lds_index(int i, int LD) const {
+    return (k0 + (i / NR) * KSTEP) * LD + r0 + (i % NR) * RSTEP;
   }
   // LDS tile stored k-major: lds[k * LD + r]
   template <int LD>
   __device__ inline void store(T* lds) const {
-    if (KFAST) {
 #pragma unroll
-      for (int i = 0; i < PER; ++i) lds[k0 * LD + r0 + i * RSTEP] = reg[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < PER; ++i) lds[(k0 + i * KSTEP) * LD + r0] = reg[i];
-    }
+    for (int i = 0; i < PER; ++i) lds[lds_index(i, LD)] = value(i);
   }
 };
 
@@ -161,16 +161,26 @@ __global__ void __launch_bounds__(256) gett_kernel(Args g) {
 
   int buf = 0;
   if (kb < ke) {
-    la.load(A, g.a_k, kb, ke);
-    lb.load(B, g.b_k, kb, ke);
+    la.fetch_k(g.a_k, kb);
+    lb.fetch_k(g.b_k, kb);
+    la.load(A, kb, ke);
+    lb.load(B, kb, ke);
+    if (kb + BK < ke) {
+      la.fetch_k(g.a_k, kb + BK);
+      lb.fetch_k(g.b_k, kb + BK);
+    }
   }
   for (int64_t kt = kb; kt < ke; kt += BK) {
     la.template store<LDA>(As[buf]);
     lb.template store<LDB>(Bs[buf]);
     __syncthreads();
     if (kt + BK < ke) {
-      la.load(A, g.a_k, kt + BK, ke);
-      lb.load(B, g.b_k, kt + BK, ke);
+      la.load(A, kt + BK, ke);
+      lb.load(B, kt + BK, ke);
+      if (kt + 2 * BK < ke) {
+        la.fetch_k(g.a_k, kt + 2 * BK);
+        lb.fetch_k(g.b_k, kt + 2 * BK);
+      }
     }
     const T* as = As[buf];
     const T* bs = Bs[buf];
@@ -206,23 +216,41 @@ __global__ void __launch_bounds__(256) gett_kernel(Args g) {
   }
   T* __restrict__ C = static_cast<T*>(g.C);
   const T alpha = T(g.alpha), beta = T(g.beta);
+  // table lookups first (padded: always in range), then the masked stores
+  int64_t cn[FN];
+  bool cv[FN];
 #pragma unroll
   for (int j = 0; j < FN; ++j) {
-    int64_t col = n0 + wn + j * F::NT + F::col(lane);
-    int64_t cn = g.c_n[col];
-    bool cv = col < g.N;
+    const int64_t col = n0 + wn + j * F::NT + F::col(lane);
+    cn[j] = g.c_n[col];
+    cv[j] = col < g.N;
+  }
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < FM; ++i) {
+    int64_t cm[F::NACC];
+    bool rv[F::NACC];
 #pragma unroll
-      for (int r = 0; r < F::NACC; ++r) {
-        int64_t row = m0 + wm + i * F::MT + F::row(lane, r);
-        if (cv && row < g.M) {
-          int64_t o = g.c_m[row] + cn;
-          T v = alpha * acc[i][j][r];
-          if (g.beta != 0.0) v += beta * C[o];
-          C[o] = v;
-        }
-      }
+    for (int r = 0; r < F::NACC; ++r) {
+      const int64_t row = m0 + wm + i * F::MT + F::row(lane, r);
+      cm[r] = g.c_m[row];
+      rv[r] = row < g.M;
+    }
+    if (g.beta != 0.0) {
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < F::NACC; ++r)
+          if (cv[j] && rv[r]) {
+            const int64_t o = cm[r] + cn[j];
+            C[o] = alpha * acc[i][j][r] + beta * C[o];
+          }
+    } else {
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < F::NACC; ++r)
+          if (cv[j] && rv[r]) C[cm[r] + cn[j]] = alpha * acc[i][j][r];
+    }
   }
 }
 
@@ -268,53 +296,41 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
     for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   if (kb < ke) {
-    la.load(A, g.a_k, kb, ke);
-    lb.load(B, g.b_k, kb, ke);
+    la.fetch_k(g.a_k, kb);
+    lb.fetch_k(g.b_k, kb);
+    la.load(A, kb, ke);
+    lb.load(B, kb, ke);
+    if (kb + BK < ke) {
+      la.fetch_k(g.a_k, kb + BK);
+      lb.fetch_k(g.b_k, kb + BK);
+    }
   }
   for (int64_t kt = kb; kt < ke; kt += BK) {
     // split and stage
-    if (AKF) {
 #pragma unroll
-      for (int i = 0; i < la.PER; ++i) {
-        __bf16 h, l;
-        split_bf16(la.reg[i], h, l);
-        int idx = la.k0 * LDA + la.r0 + i * la.RSTEP;
-        Ah[idx] = h;
-        Al[idx] = l;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < la.PER; ++i) {
-        __bf16 h, l;
-        split_bf16(la.reg[i], h, l);
-        int idx = (la.k0 + i * la.KSTEP) * LDA + la.r0;
-        Ah[idx] = h;
-        Al[idx] = l;
-      }
+    for (int i = 0; i < la.PER; ++i) {
+      __bf16 h, l;
+      split_bf16(la.value(i), h, l);
+      const int idx = la.lds_index(i, LDA);
+      Ah[idx] = h;
+      Al[idx] = l;
     }
-    if (BKF) {
 #pragma unroll
-      for (int i = 0; i < lb.PER; ++i) {
-        __bf16 h, l;
-        split_bf16(lb.reg[i], h, l);
-        int idx = lb.k0 * LDB + lb.r0 + i * lb.RSTEP;
-        Bh[idx] = h;
-        Bl[idx] = l;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < lb.PER; ++i) {
-        __bf16 h, l;
-        split_bf16(lb.reg[i], h, l);
-        int idx = (lb.k0 + i * lb.KSTEP) * LDB + lb.r0;
-        Bh[idx] = h;
-        Bl[idx] = l;
-      }
+    for (int i = 0; i < lb.PER; ++i) {
+      __bf16 h, l;
+      split_bf16(lb.value(i), h, l);
+      const int idx = lb.lds_index(i, LDB);
+      Bh[idx] = h;
+      Bl[idx] = l;
     }
     __syncthreads();
     if (kt + BK < ke) {
-      la.load(A, g.a_k, kt + BK, ke);
-      lb.load(B, g.b_k, kt + BK, ke);
+      la.load(A, kt + BK, ke);
+      lb.load(B, kt + BK, ke);
+      if (kt + 2 * BK < ke) {
+        la.fetch_k(g.a_k, kt + 2 * BK);
+        lb.fetch_k(g.b_k, kt + 2 * BK);
+      }
     }
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 32) {
@@ -467,6 +483,16 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
     a.partial = ctx.buf("gett.partial", (size_t)splits * t.M * t.N * eb);
   }
   hipStream_t s = ctx.stream;
+  LaunchRecord rec;
+  if (ctx.profiling) {
+    rec.kernel = std::string("gett<") + (l.prec == Prec::F64 ? "f64" : (l.prec == Prec::F32 ? "f32" : "bf16x3")) +
+                 "," + std::to_string(BMsel) + "x" + std::to_string(BNsel) + (t.a_kfast ? ",Ak" : ",Am") +
+                 (t.b_kfast ? ",Bk" : ",Bn") + (splits > 1 ? ",splitk" : "") + ">";
+    rec.flops = 2.0 * (double)t.M * (double)t.N * (double)t.K;
+    rec.start = ctx.take_event();
+    rec.stop = ctx.take_event();
+    MERA_HIP(hipEventRecord(rec.start, s));
+  }
   if (l.prec == Prec::F64) {
     if (bigm && bign) launch_tile<double, 128, 128, 16>(a, splits, s, t.a_kfast, t.b_kfast);
     else if (bigm) launch_tile<double, 128, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
@@ -484,6 +510,10 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
     else launch_bf16x3<64, 64, 32>(a, splits, s, t.a_kfast, t.b_kfast);
   }
   MERA_HIP(hipGetLastError());
+  if (ctx.profiling) {
+    MERA_HIP(hipEventRecord(rec.stop, s));
+    ctx.records.push_back(rec);
+  }
   if (splits > 1) {
     const int64_t total = t.M * t.N;
     int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);

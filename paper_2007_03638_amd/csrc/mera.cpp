@@ -30,14 +30,18 @@ namespace mera {
 
 namespace {
 
+// Leg orders of the intermediates are chosen so that in every chi^9 step each operand is read along a
+// unit-stride run: an operand read along M (or N) has its M (N) legs innermost, and when both operands are
+// read along K their K legs appear in the same order in both (UWb is the bra composite stored in the order
+// the descending step needs).
 const char* const kAscL[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
     "T1[aABCgh] = h[abcABC] * u[bcgh]",
-    "T2[aAghGH] = T1[aABCgh] * u[BCGH]",
+    "T2[aghHAG] = T1[aABCgh] * u[BCGH]",
     "UW[daegq] = u[daef] * w[fgq]",
-    "T3[AhGHdeq] = T2[aAghGH] * UW[daegq]",
-    "T4[hHeqEQ] = T3[AhGHdeq] * UW[dAEGQ]",
+    "T3[hHAGdeq] = T2[aghHAG] * UW[daegq]",
+    "T4[hHeqEQ] = T3[hHAGdeq] * UW[dAEGQ]",
     "T5[hHqQpP] = T4[hHeqEQ] * W1[epEP]",
     "out[pqrPQR] += 0.5 * T5[hHqQpP] * W3[hrHR]",
 };
@@ -45,10 +49,10 @@ const char* const kAscR[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
     "T1[cABCef] = h[abcABC] * u[abef]",
-    "T2[cCefEF] = T1[cABCef] * u[ABEF]",
+    "T2[cfeECF] = T1[cABCef] * u[ABEF]",
     "UW[cdhfq] = u[cdgh] * w[fgq]",
-    "T3[CeEFdhq] = T2[cCefEF] * UW[cdhfq]",
-    "T4[eEhqHQ] = T3[CeEFdhq] * UW[CdHFQ]",
+    "T3[eECFdhq] = T2[cfeECF] * UW[cdhfq]",
+    "T4[eEhqHQ] = T3[eECFdhq] * UW[CdHFQ]",
     "T5[eEqQrR] = T4[eEhqHQ] * W3[hrHR]",
     "out[pqrPQR] += 0.5 * T5[eEqQrR] * W1[epEP]",
 };
@@ -56,9 +60,10 @@ const char* const kDesL[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
     "UW[daegq] = u[daef] * w[fgq]",
+    "UWb[dAGEQ] = u[dAEF] * w[FGQ]",
     "dT5[pqPQhH] = rho[pqrPQR] * W3[hrHR]",
-    "dT4[qQhHeE] = dT5[pqPQhH] * W1[epEP]",
-    "dT3[qhHedAG] = dT4[qQhHeE] * UW[dAEGQ]",
+    "dT4[qhHeEQ] = dT5[pqPQhH] * W1[epEP]",
+    "dT3[qhHedAG] = dT4[qhHeEQ] * UWb[dAGEQ]",
     "dT2[hHAGag] = dT3[qhHedAG] * UW[daegq]",
     "dT1[hAagBC] = dT2[hHAGag] * u[BCGH]",
     "out[abcABC] += 0.5 * dT1[hAagBC] * u[bcgh]",
@@ -67,10 +72,11 @@ const char* const kDesR[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
     "UW[cdhfq] = u[cdgh] * w[fgq]",
+    "UWb[dCFHQ] = u[CdGH] * w[FGQ]",
     "dT5[qrQReE] = rho[pqrPQR] * W1[epEP]",
-    "dT4[qQeEhH] = dT5[qrQReE] * W3[hrHR]",
-    "dT3[qeEhCdF] = dT4[qQeEhH] * UW[CdHFQ]",
-    "dT2[eECFcf] = dT3[qeEhCdF] * UW[cdhfq]",
+    "dT4[qeEhHQ] = dT5[qrQReE] * W3[hrHR]",
+    "dT3[qeEhdCF] = dT4[qeEhHQ] * UWb[dCFHQ]",
+    "dT2[eECFcf] = dT3[qeEhdCF] * UW[cdhfq]",
     "dT1[eCcfAB] = dT2[eECFcf] * u[ABEF]",
     "out[abcABC] += 0.5 * dT1[eCcfAB] * u[abef]",
 };
@@ -79,17 +85,18 @@ const char* const kGradL[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
     "T1[aABCgh] = h[abcABC] * u[bcgh]",
-    "T2[aAghGH] = T1[aABCgh] * u[BCGH]",
+    "T2[aghHAG] = T1[aABCgh] * u[BCGH]",
     "UW[daegq] = u[daef] * w[fgq]",
-    "T3[AhGHdeq] = T2[aAghGH] * UW[daegq]",
-    "T4[hHeqEQ] = T3[AhGHdeq] * UW[dAEGQ]",
+    "UWb[dAGEQ] = u[dAEF] * w[FGQ]",
+    "T3[hHAGdeq] = T2[aghHAG] * UW[daegq]",
+    "T4[hHeqEQ] = T3[hHAGdeq] * UW[dAEGQ]",
     "T5[hHqQpP] = T4[hHeqEQ] * W1[epEP]",
     "dT5[pqPQhH] = rho[pqrPQR] * W3[hrHR]",
     "dW3[hHrR] = T5[hHqQpP] * rho[pqrPQR]",
-    "dT4[qQhHeE] = dT5[pqPQhH] * W1[epEP]",
+    "dT4[qhHeEQ] = dT5[pqPQhH] * W1[epEP]",
     "dW1[eEpP] = T4[hHeqEQ] * dT5[pqPQhH]",
-    "dT3[qhHedAG] = dT4[qQhHeE] * UW[dAEGQ]",
-    "dUW[agqed] = T2[aAghGH] * dT3[qhHedAG]",
+    "dT3[qhHedAG] = dT4[qhHeEQ] * UWb[dAGEQ]",
+    "dUW[agqed] = T2[aghHAG] * dT3[qhHedAG]",
     "dT2[hHAGag] = dT3[qhHedAG] * UW[daegq]",
     "dT1[hAagBC] = dT2[hHAGag] * u[BCGH]",
     "Du[BCGH] += T1[aABCgh] * dT2[hHAGag]",
@@ -103,18 +110,19 @@ const char* const kGradR[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
     "T1[cABCef] = h[abcABC] * u[abef]",
-    "T2[cCefEF] = T1[cABCef] * u[ABEF]",
+    "T2[cfeECF] = T1[cABCef] * u[ABEF]",
     "UW[cdhfq] = u[cdgh] * w[fgq]",
-    "T3[CeEFdhq] = T2[cCefEF] * UW[cdhfq]",
-    "T4[eEhqHQ] = T3[CeEFdhq] * UW[CdHFQ]",
+    "UWb[dCFHQ] = u[CdGH] * w[FGQ]",
+    "T3[eECFdhq] = T2[cfeECF] * UW[cdhfq]",
+    "T4[eEhqHQ] = T3[eECFdhq] * UW[CdHFQ]",
     "T5[eEqQrR] = T4[eEhqHQ] * W3[hrHR]",
     "dT5[qrQReE] = rho[pqrPQR] * W1[epEP]",
     "dW1[eEpP] = T5[eEqQrR] * rho[pqrPQR]",
-    "dT4[qQeEhH] = dT5[qrQReE] * W3[hrHR]",
+    "dT4[qeEhHQ] = dT5[qrQReE] * W3[hrHR]",
     "dW3[hHrR] = T4[eEhqHQ] * dT5[qrQReE]",
-    "dT3[qeEhCdF] = dT4[qQeEhH] * UW[CdHFQ]",
-    "dUW[cfqhd] = T2[cCefEF] * dT3[qeEhCdF]",
-    "dT2[eECFcf] = dT3[qeEhCdF] * UW[cdhfq]",
+    "dT3[qeEhdCF] = dT4[qeEhHQ] * UWb[dCFHQ]",
+    "dUW[cfqhd] = T2[cfeECF] * dT3[qeEhdCF]",
+    "dT2[eECFcf] = dT3[qeEhdCF] * UW[cdhfq]",
     "dT1[eCcfAB] = dT2[eECFcf] * u[ABEF]",
     "Du[ABEF] += T1[cABCef] * dT2[eECFcf]",
     "rhoout[abcABC] += 0.5 * dT1[eCcfAB] * u[abef]",
