@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--jobs", type=int, default=16)
     ap.add_argument("--serve-iters", type=int, default=30)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference dispatch for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -74,11 +76,32 @@ def cpu_baseline(sample_chi, gpu_flops_per_eval):
                        f"({gpu_flops_per_eval:.3e})")
 
 
+def counter_traffic(kernel_variant):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary, or None when the
+    kernel source changed since the counters were taken or the summary covers another variant."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gett_f32_chi24_counters.md")
+    src = os.path.join(ROOT, "paper_2007_03638_amd", "csrc", "gett.hip")
+    if not os.path.exists(path) or kernel_variant != "gett<f32,128x128,Am,Bn>":
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    fields = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith("|"))
+    if fields.get("gett_source_sha256_prefix", "").strip() != sha:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def run_eval_bench(a):
     import torch
     from paper_2007_03638_amd import api, inputs
 
     ctx = api.Context(0)
+    if a.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     dims = api.layer_dims(a.T, a.chi)
     init = [m for pair in inputs.mera_init(a.seed, dims) for m in pair]
     h3 = api.h3_tfim(1.0)
@@ -88,7 +111,7 @@ def run_eval_bench(a):
     for _ in range(a.warmup):
         _, state = opt.step()
     # state after the untimed part (with no warmup: the initial evaluation done at creation)
-    s0 = state if state is not None else {"evaluations": 1, "macs": ctx.macs()}
+    s0 = state if state is not None else {"evaluations": 1, "macs": ctx.macs(), "krylov_applications": 0}
     ctx.profile(True)
     ctx.kernel_stats()  # clear
     torch.cuda.synchronize()
@@ -130,8 +153,10 @@ def run_eval_bench(a):
         "gnorm": state["gnorm"],
         "contraction_time_fraction": gemm_time / dt,
         "roofline": {"bound": "mfma", "kernel": top["kernel"], "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": counter_traffic(top["kernel"]),
+                     "algorithmic_bytes": top["bytes"] / top["launches"],
                      "launches": top["launches"], "avg_launch_ms": 1000.0 * top["seconds"] / top["launches"]},
+        "krylov_applications_per_eval": (state["krylov_applications"] - s0.get("krylov_applications", 0)) / max(evals, 1),
         "kernels": [{"kernel": s["kernel"], "launches": s["launches"], "ms": 1000.0 * s["seconds"],
                      "tflops": s["flops"] / s["seconds"] / 1e12} for s in stats[:6]],
     }

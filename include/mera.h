@@ -80,6 +80,7 @@ typedef struct {
   int launches;
   double seconds;    /* summed launch durations (event to event)                      */
   double flops;      /* summed algorithmic flops, 2 x M x N x K per launch            */
+  double bytes;      /* summed algorithmic bytes: A, B and C each moved once          */
 } mera_kernel_stat;
 mera_status mera_ctx_profile(mera_ctx* ctx, int enable);
 int mera_ctx_kernel_stats(mera_ctx* ctx, mera_kernel_stat* out, int cap);
@@ -210,6 +211,7 @@ typedef struct {
   double seconds;                  /* wall time of the optimisation itself                                  */
   double macs;
   double queued_seconds;           /* server only: time from submission to admission (0 for run_optimize)   */
+  int krylov_applications;         /* superoperator applications spent in the two Krylov solves, all evals  */
 } mera_result;
 
 typedef struct { int iter; int evals; double energy; double gnorm; double alpha; int prec; } mera_iter_log;

@@ -36,7 +36,7 @@ class Job(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("energy", c_double), ("gnorm", c_double), ("iterations", c_int), ("evaluations", c_int),
                 ("status", c_int), ("polish_iter", c_int), ("seconds", c_double), ("macs", c_double),
-                ("queued_seconds", c_double)]
+                ("queued_seconds", c_double), ("krylov_applications", c_int)]
 
 
 class IterLog(ctypes.Structure):
@@ -45,7 +45,8 @@ class IterLog(ctypes.Structure):
 
 
 class KernelStat(ctypes.Structure):
-    _fields_ = [("kernel", ctypes.c_char * 80), ("launches", c_int), ("seconds", c_double), ("flops", c_double)]
+    _fields_ = [("kernel", ctypes.c_char * 80), ("launches", c_int), ("seconds", c_double), ("flops", c_double),
+                ("bytes", c_double)]
 
 
 MAT_P = ctypes.POINTER(MeraMat)

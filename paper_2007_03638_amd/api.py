@@ -121,7 +121,7 @@ class Context:
         if n < 0:
             self._check(n, "mera_ctx_kernel_stats")
         return [dict(kernel=arr[i].kernel.decode(), launches=arr[i].launches, seconds=arr[i].seconds,
-                     flops=arr[i].flops) for i in range(min(n, cap))]
+                     flops=arr[i].flops, bytes=arr[i].bytes) for i in range(min(n, cap))]
 
     def optimizer(self, **job_kwargs):
         return Optimizer(self, **job_kwargs)
@@ -252,7 +252,7 @@ class Context:
 def result_dict(res):
     return dict(energy=res.energy, gnorm=res.gnorm, iterations=res.iterations, evaluations=res.evaluations,
                 status=res.status, polish_iter=res.polish_iter, seconds=res.seconds, macs=res.macs,
-                queued_seconds=res.queued_seconds)
+                queued_seconds=res.queued_seconds, krylov_applications=res.krylov_applications)
 
 
 def make_job(T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, polish_tol=0.0, precondition=True,

@@ -473,6 +473,7 @@ mera_status run_optimize(mera_ctx* ctx, const mera_job* job, mera_result* out, d
     out->polish_iter = r.polish_iter;
     out->seconds = r.seconds;
     out->macs = r.macs;
+    out->krylov_applications = r.krylov_apps;
     for (size_t i = 0; i < r.log.size() && (int)i < log_cap; ++i) log[i] = r.log[i];
     if (log_len) *log_len = (int)std::min<size_t>(r.log.size(), (size_t)log_cap);
   });
@@ -506,7 +507,7 @@ int mera_ctx_kernel_stats(mera_ctx* ctx, mera_kernel_stat* out, int cap) {
     ctx->c.sync();
     struct Agg {
       int n = 0;
-      double s = 0, f = 0;
+      double s = 0, f = 0, b = 0;
     };
     std::map<std::string, Agg> agg;
     for (auto& r : ctx->c.records) {
@@ -516,6 +517,7 @@ int mera_ctx_kernel_stats(mera_ctx* ctx, mera_kernel_stat* out, int cap) {
       a.n++;
       a.s += ms * 1e-3;
       a.f += r.flops;
+      a.b += r.bytes;
       ctx->c.event_pool.push_back(r.start);
       ctx->c.event_pool.push_back(r.stop);
     }
@@ -528,6 +530,7 @@ int mera_ctx_kernel_stats(mera_ctx* ctx, mera_kernel_stat* out, int cap) {
       out[i].launches = v[i].second.n;
       out[i].seconds = v[i].second.s;
       out[i].flops = v[i].second.f;
+      out[i].bytes = v[i].second.b;
     }
     return (int)v.size();
   } catch (const Error& e) {
@@ -571,6 +574,7 @@ mera_status mera_opt_step(mera_ctx* ctx, mera_opt* opt, int* done, mera_result* 
       state->status = d ? opt->o.status : -1;
       state->polish_iter = opt->o.polish_iter;
       state->macs = ctx->c.macs - opt->o.macs0;
+      state->krylov_applications = opt->o.krylov_apps;
     }
   });
 }

@@ -79,6 +79,7 @@ struct LaunchRecord {
   std::string kernel;
   hipEvent_t start, stop;
   double flops;
+  double bytes;  // algorithmic: each operand and the result read or written once
 };
 
 struct Ctx {

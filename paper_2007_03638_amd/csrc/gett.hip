@@ -119,6 +119,14 @@ struct Loader {
   }
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on XCD b % 8). Remap so that each
+// XCD processes a contiguous range of logical tiles: consecutive tiles share an A panel, which then stays in
+// that XCD's L2 instead of being fetched by all eight. The tail (ntiles % 8 tiles) keeps the identity map.
+__device__ inline int64_t xcd_tile(int64_t b, int64_t ntiles) {
+  const int64_t full = ntiles / 8;
+  return (b < full * 8) ? (b % 8) * full + b / 8 : b;
+}
+
 template <typename T, int BM, int BN, int BK, bool AKF, bool BKF>
 __global__ void __launch_bounds__(256) gett_kernel(Args g) {
   using F = Mma<T>;
@@ -137,7 +145,7 @@ __global__ void __launch_bounds__(256) gett_kernel(Args g) {
   const int wn = (wave & 1) * WN;
 
   const int64_t tiles_n = (g.N + BN - 1) / BN;
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t m0 = (tile / tiles_n) * BM;
   const int64_t n0 = (tile % tiles_n) * BN;
   const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
@@ -276,7 +284,7 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
   const int wm = (wave >> 1) * WM;
   const int wn = (wave & 1) * WN;
   const int64_t tiles_n = (g.N + BN - 1) / BN;
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t m0 = (tile / tiles_n) * BM;
   const int64_t n0 = (tile % tiles_n) * BN;
   const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
@@ -464,7 +472,7 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
   const bool bigm = t.M >= 128, bign = t.N >= 128;
   const int BMsel = bigm ? 128 : 64, BNsel = bign ? 128 : 64;
   const int64_t tiles = ((t.M + BMsel - 1) / BMsel) * ((t.N + BNsel - 1) / BNsel);
-  const int BK = (l.prec == Prec::BF16X3) ? 32 : 16;
+  const int BK = 32;  // k-chunks stay multiples of every tile depth in use
 
   // split-K when the output grid cannot fill the chip and K is long
   int splits = l.splits;
@@ -489,6 +497,7 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
                  "," + std::to_string(BMsel) + "x" + std::to_string(BNsel) + (t.a_kfast ? ",Ak" : ",Am") +
                  (t.b_kfast ? ",Bk" : ",Bn") + (splits > 1 ? ",splitk" : "") + ">";
     rec.flops = 2.0 * (double)t.M * (double)t.N * (double)t.K;
+    rec.bytes = (double)eb * ((double)t.M * t.K + (double)t.K * t.N + (double)t.M * t.N * (l.beta != 0.0 ? 2 : 1));
     rec.start = ctx.take_event();
     rec.stop = ctx.take_event();
     MERA_HIP(hipEventRecord(rec.start, s));

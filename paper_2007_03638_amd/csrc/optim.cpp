@@ -402,6 +402,7 @@ double Optimizer::evaluate(const Flat& X, Flat& Gout, Flat& rvout) {
   }
   EvalOut r = energy_grad(*ctx, job.shape, pt, h3dev.as<double>(), prec, &warm, job.krylov, go);
   evals++;
+  krylov_apps += r.app_rho + r.app_ht;
   for (int i = 0; i < X.count(); ++i) stiefel_project_one(*ctx, X.view(i), D.view(i), Gout.view(i));
   return r.energy;
 }
@@ -530,6 +531,7 @@ void Optimizer::finish(std::vector<double*>* final_host) {
   result.evaluations = evals;
   result.status = status;
   result.polish_iter = polish_iter;
+  result.krylov_apps = krylov_apps;
   result.macs = c.macs - macs0;
 }
 

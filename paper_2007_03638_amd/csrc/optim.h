@@ -69,7 +69,7 @@ double inner(Ctx& ctx, const std::vector<MatView>& X, const std::vector<MatView>
 
 struct OptResult {
   double energy = 0, gnorm = 0, seconds = 0, macs = 0;
-  int iterations = 0, evaluations = 0, status = 0, polish_iter = -1;
+  int iterations = 0, evaluations = 0, status = 0, polish_iter = -1, krylov_apps = 0;
   std::vector<mera_iter_log> log;
 };
 
@@ -101,7 +101,7 @@ struct Optimizer {
   Metric met;
   Prec prec = Prec::F64;
   double f = 0, gnorm = 0, last_alpha = 0;
-  int iter = 0, evals = 0, status = -1, polish_iter = -1;
+  int iter = 0, evals = 0, status = -1, polish_iter = -1, krylov_apps = 0;
   bool done = false, started = false;
   double macs0 = 0;
   OptResult result;

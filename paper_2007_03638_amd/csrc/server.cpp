@@ -99,6 +99,7 @@ struct Server {
         res.status = r.status;
         res.polish_iter = r.polish_iter;
         res.macs = r.macs;
+        res.krylov_applications = r.krylov_apps;
       } catch (const Error& e) {
         err = e.status;
         res.status = e.status;
