@@ -201,6 +201,10 @@ def run_serve_bench(a):
                 r = srv.poll(i)
                 if r is not None:
                     results[i] = (time.perf_counter() - t0, r)
+                    print(f"[serve] job {i} done at {results[i][0]:.1f} s: status {r['status']} "
+                          f"iters {r['iterations']} |G| {r['gnorm']:.2e} latency "
+                          f"{r['queued_seconds'] + r['seconds']:.1f} s ({len(results)}/{len(jobs)})",
+                          file=sys.stderr, flush=True)
         time.sleep(0.005)
     makespan = time.perf_counter() - t0
     srv.close()

@@ -85,6 +85,11 @@ typedef struct {
 mera_status mera_ctx_profile(mera_ctx* ctx, int enable);
 int mera_ctx_kernel_stats(mera_ctx* ctx, mera_kernel_stat* out, int cap);
 
+/* Memory bound for the two largest intermediates of a layer program (7-leg tensors of a^6 b elements): when one
+ * would exceed `bytes`, the program runs in chunks of a spectator leg so that each chunked intermediate stays
+ * within bytes/2 (default 32 GiB; results are unchanged up to rounding order). */
+mera_status mera_ctx_set_intermediate_limit(mera_ctx* ctx, size_t bytes);
+
 /* Layer dimensions: a_out[0..T], b_out[0..T] (host arrays of T+1 ints). */
 mera_status mera_layer_dims(const mera_shape* shape, int* a_out, int* b_out);
 

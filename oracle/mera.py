@@ -81,6 +81,34 @@ def descend_one(net, rho, u, w, a, b):
     return _ein(spec, rho.reshape((b,) * 6), *_operands(u, w, a, b)).reshape(a ** 3, a ** 3)
 
 
+def ascend_element(side, h, u, w, a, b, idx):
+    """One element A_L(h) or A_R(h) at (p, q, r, P, Q, R) = idx, with the isometries' top legs fixed.
+
+    The same networks as `ascend_one`, contracted in a fixed order that keeps every intermediate at most a^6, so
+    single outputs can be sampled at large bond dimension (cost ~a^8 per element).
+    """
+    U = u.reshape(a, a, a, a)
+    Wt = w.reshape(a, a, b)
+    p, q, r, P, Q, R = idx
+    h6 = h.reshape((a,) * 6)
+    X1 = np.einsum('xe,xE->eE', Wt[:, :, p], Wt[:, :, P], optimize=True)
+    X3 = np.einsum('hy,Hy->hH', Wt[:, :, r], Wt[:, :, R], optimize=True)
+    if side == 'L':
+        K = np.einsum('daeg,eE->dagE', np.einsum('daef,fg->daeg', U, Wt[:, :, q]), X1, optimize=True)
+        Kb = np.einsum('dAEF,FG->dAEG', U, Wt[:, :, Q], optimize=True)
+        T = np.einsum('abcABC,bcgh->aABCgh', h6, U, optimize=True)
+        T = np.einsum('aABCgh,hH->aABCgH', T, X3, optimize=True)
+        T = np.einsum('aABCgH,BCGH->aAgG', T, U, optimize=True)
+        T = np.einsum('aAgG,dagE->AGdE', T, K, optimize=True)
+        return float(np.einsum('AGdE,dAEG->', T, Kb, optimize=True))
+    Rr = np.einsum('cdgH,CdGH->cgCG', np.einsum('cdgh,hH->cdgH', U, X3), U, optimize=True)
+    K = np.einsum('abeg,eE->abEg', np.einsum('abef,fg->abeg', U, Wt[:, :, q]), X1, optimize=True)
+    Kb = np.einsum('ABEF,FG->ABEG', U, Wt[:, :, Q], optimize=True)
+    T = np.einsum('abcABC,cgCG->abABgG', h6, Rr, optimize=True)
+    T = np.einsum('abABgG,abEg->ABGE', T, K, optimize=True)
+    return float(np.einsum('ABGE,ABEG->', T, Kb, optimize=True))
+
+
 def ascend(h, u, w, a, b):
     """Ascending superoperator A = (A_L + A_R)/2 of one layer (App. B notation: <h| A)."""
     return 0.5 * (ascend_one(_NET_L, h, u, w, a, b) + ascend_one(_NET_R, h, u, w, a, b))

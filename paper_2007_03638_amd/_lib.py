@@ -58,6 +58,7 @@ SIGNATURES = {
     "mera_last_error": (ctypes.c_char_p, [c_void_p]),
     "mera_ctx_trim": (c_int, [c_void_p]),
     "mera_ctx_macs": (c_double, [c_void_p]),
+    "mera_ctx_set_intermediate_limit": (c_int, [c_void_p, c_size_t]),
     "mera_layer_dims": (c_int, [ctypes.POINTER(MeraShape), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "mera_h3_tfim": (c_int, [c_double, ctypes.POINTER(c_double)]),
     "mera_h3_xxz": (c_int, [c_double, ctypes.POINTER(c_double)]),

@@ -112,6 +112,9 @@ class Context:
     def trim(self):
         self._check(self._lib.mera_ctx_trim(self.ptr), "mera_ctx_trim")
 
+    def set_intermediate_limit(self, nbytes):
+        self._check(self._lib.mera_ctx_set_intermediate_limit(self.ptr, int(nbytes)), "mera_ctx_set_intermediate_limit")
+
     def profile(self, enable=True):
         self._check(self._lib.mera_ctx_profile(self.ptr, 1 if enable else 0), "mera_ctx_profile")
 

@@ -3,7 +3,7 @@
 #include <cstring>
 
 #include "common.h"
-#include "mera.h"
+#include "mera_eval.h"
 #include "model.h"
 #include "network.h"
 
@@ -123,6 +123,12 @@ mera_status mera_ctx_trim(mera_ctx* ctx) {
 }
 
 double mera_ctx_macs(const mera_ctx* ctx) { return ctx ? ctx->c.macs : 0.0; }
+
+mera_status mera_ctx_set_intermediate_limit(mera_ctx* ctx, size_t bytes) {
+  if (!ctx || bytes == 0) return MERA_EINVAL;
+  ctx->c.inter_limit = bytes;
+  return MERA_OK;
+}
 
 mera_status mera_layer_dims(const mera_shape* shape, int* a_out, int* b_out) {
   if (!shape || !a_out || !b_out) return MERA_EINVAL;

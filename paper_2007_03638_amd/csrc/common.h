@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mera.h"
+#include "mera.h"  // include/mera.h (on the include path)
 
 namespace mera {
 
@@ -91,6 +91,7 @@ struct Ctx {
   std::map<std::string, DevBuf> scratch;
   std::unique_ptr<PlanCache> plans;
   DevBuf red;        // reduction partials (doubles)
+  size_t inter_limit = (size_t)32 << 30;  // largest 7-leg intermediate built in one piece (bytes)
   bool profiling = false;
   std::vector<LaunchRecord> records;
   std::vector<hipEvent_t> event_pool;

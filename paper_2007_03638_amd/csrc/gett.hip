@@ -468,8 +468,9 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
   a.beta = l.beta;
   a.partial = nullptr;
 
-  // tile shape: large tiles when both extents allow, otherwise 64-wide
-  const bool bigm = t.M >= 128, bign = t.N >= 128;
+  // tile shape: large tiles when both extents allow, otherwise 64-wide. FP64 uses at most 128 x 64: the 128 x 128
+  // FP64 tile needs more than 256 registers per lane, leaving one wave per SIMD.
+  const bool bigm = t.M >= 128, bign = t.N >= 128 && l.prec != Prec::F64;
   const int BMsel = bigm ? 128 : 64, BNsel = bign ? 128 : 64;
   const int64_t tiles = ((t.M + BMsel - 1) / BMsel) * ((t.N + BNsel - 1) / BNsel);
   const int BK = 32;  // k-chunks stay multiples of every tile depth in use
@@ -503,9 +504,7 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
     MERA_HIP(hipEventRecord(rec.start, s));
   }
   if (l.prec == Prec::F64) {
-    if (bigm && bign) launch_tile<double, 128, 128, 16>(a, splits, s, t.a_kfast, t.b_kfast);
-    else if (bigm) launch_tile<double, 128, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
-    else if (bign) launch_tile<double, 64, 128, 16>(a, splits, s, t.a_kfast, t.b_kfast);
+    if (bigm) launch_tile<double, 128, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
     else launch_tile<double, 64, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
   } else if (l.prec == Prec::F32) {
     if (bigm && bign) launch_tile<float, 128, 128, 16>(a, splits, s, t.a_kfast, t.b_kfast);

@@ -18,7 +18,7 @@
 // and rho are symmetric, the closed network is invariant under exchanging ket and bra, so the bra
 // occurrences of u and w have the same environments as the ket ones: only ket environments are formed and
 // counted twice, which with the 1/2 of the position average gives weight 1.
-#include "mera.h"
+#include "mera_eval.h"
 
 #include <cmath>
 #include <functional>
@@ -34,101 +34,117 @@ namespace {
 // unit-stride run: an operand read along M (or N) has its M (N) legs innermost, and when both operands are
 // read along K their K legs appear in the same order in both (UWb is the bra composite stored in the order
 // the descending step needs).
+// The steps between "@loop" and "@end" may run in chunks of a spectator leg (h for the L diagram, e for the R
+// diagram: neither is contracted by a chi^9 step) to bound the two 7-leg intermediates at large chi.
 const char* const kAscL[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
+    "UW[daegq] = u[daef] * w[fgq]",
+    "@loop h",
     "T1[aABCgh] = h[abcABC] * u[bcgh]",
     "T2[aghHAG] = T1[aABCgh] * u[BCGH]",
-    "UW[daegq] = u[daef] * w[fgq]",
     "T3[hHAGdeq] = T2[aghHAG] * UW[daegq]",
     "T4[hHeqEQ] = T3[hHAGdeq] * UW[dAEGQ]",
     "T5[hHqQpP] = T4[hHeqEQ] * W1[epEP]",
     "out[pqrPQR] += 0.5 * T5[hHqQpP] * W3[hrHR]",
+    "@end",
 };
 const char* const kAscR[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
+    "UW[cdhfq] = u[cdgh] * w[fgq]",
+    "@loop e",
     "T1[cABCef] = h[abcABC] * u[abef]",
     "T2[cfeECF] = T1[cABCef] * u[ABEF]",
-    "UW[cdhfq] = u[cdgh] * w[fgq]",
     "T3[eECFdhq] = T2[cfeECF] * UW[cdhfq]",
     "T4[eEhqHQ] = T3[eECFdhq] * UW[CdHFQ]",
     "T5[eEqQrR] = T4[eEhqHQ] * W3[hrHR]",
     "out[pqrPQR] += 0.5 * T5[eEqQrR] * W1[epEP]",
+    "@end",
 };
 const char* const kDesL[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
     "UW[daegq] = u[daef] * w[fgq]",
     "UWb[dAGEQ] = u[dAEF] * w[FGQ]",
+    "@loop h",
     "dT5[pqPQhH] = rho[pqrPQR] * W3[hrHR]",
     "dT4[qhHeEQ] = dT5[pqPQhH] * W1[epEP]",
     "dT3[qhHedAG] = dT4[qhHeEQ] * UWb[dAGEQ]",
     "dT2[hHAGag] = dT3[qhHedAG] * UW[daegq]",
     "dT1[hAagBC] = dT2[hHAGag] * u[BCGH]",
     "out[abcABC] += 0.5 * dT1[hAagBC] * u[bcgh]",
+    "@end",
 };
 const char* const kDesR[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
     "UW[cdhfq] = u[cdgh] * w[fgq]",
     "UWb[dCFHQ] = u[CdGH] * w[FGQ]",
+    "@loop e",
     "dT5[qrQReE] = rho[pqrPQR] * W1[epEP]",
     "dT4[qeEhHQ] = dT5[qrQReE] * W3[hrHR]",
     "dT3[qeEhdCF] = dT4[qeEhHQ] * UWb[dCFHQ]",
     "dT2[eECFcf] = dT3[qeEhdCF] * UW[cdhfq]",
     "dT1[eCcfAB] = dT2[eECFcf] * u[ABEF]",
     "out[abcABC] += 0.5 * dT1[eCcfAB] * u[abef]",
+    "@end",
 };
 // forward of the L diagram, then reverse accumulation with cotangent rho
 const char* const kGradL[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
-    "T1[aABCgh] = h[abcABC] * u[bcgh]",
-    "T2[aghHAG] = T1[aABCgh] * u[BCGH]",
     "UW[daegq] = u[daef] * w[fgq]",
     "UWb[dAGEQ] = u[dAEF] * w[FGQ]",
+    "@zero dW1 dUW",
+    "@loop h",
+    "T1[aABCgh] = h[abcABC] * u[bcgh]",
+    "T2[aghHAG] = T1[aABCgh] * u[BCGH]",
     "T3[hHAGdeq] = T2[aghHAG] * UW[daegq]",
     "T4[hHeqEQ] = T3[hHAGdeq] * UW[dAEGQ]",
     "T5[hHqQpP] = T4[hHeqEQ] * W1[epEP]",
     "dT5[pqPQhH] = rho[pqrPQR] * W3[hrHR]",
     "dW3[hHrR] = T5[hHqQpP] * rho[pqrPQR]",
     "dT4[qhHeEQ] = dT5[pqPQhH] * W1[epEP]",
-    "dW1[eEpP] = T4[hHeqEQ] * dT5[pqPQhH]",
+    "dW1[eEpP] += T4[hHeqEQ] * dT5[pqPQhH]",
     "dT3[qhHedAG] = dT4[qhHeEQ] * UWb[dAGEQ]",
-    "dUW[agqed] = T2[aghHAG] * dT3[qhHedAG]",
+    "dUW[agqed] += T2[aghHAG] * dT3[qhHedAG]",
     "dT2[hHAGag] = dT3[qhHedAG] * UW[daegq]",
     "dT1[hAagBC] = dT2[hHAGag] * u[BCGH]",
     "Du[BCGH] += T1[aABCgh] * dT2[hHAGag]",
     "rhoout[abcABC] += 0.5 * dT1[hAagBC] * u[bcgh]",
+    "Dw[hyr] += dW3[hHrR] * w[HyR]",
+    "@end",
     "Du[daef] += dUW[agqed] * w[fgq]",
     "Dw[fgq] += u[daef] * dUW[agqed]",
     "Dw[xep] += dW1[eEpP] * w[xEP]",
-    "Dw[hyr] += dW3[hHrR] * w[HyR]",
 };
 const char* const kGradR[] = {
     "W1[epEP] = w[xep] * w[xEP]",
     "W3[hrHR] = w[hyr] * w[HyR]",
-    "T1[cABCef] = h[abcABC] * u[abef]",
-    "T2[cfeECF] = T1[cABCef] * u[ABEF]",
     "UW[cdhfq] = u[cdgh] * w[fgq]",
     "UWb[dCFHQ] = u[CdGH] * w[FGQ]",
+    "@zero dW3 dUW",
+    "@loop e",
+    "T1[cABCef] = h[abcABC] * u[abef]",
+    "T2[cfeECF] = T1[cABCef] * u[ABEF]",
     "T3[eECFdhq] = T2[cfeECF] * UW[cdhfq]",
     "T4[eEhqHQ] = T3[eECFdhq] * UW[CdHFQ]",
     "T5[eEqQrR] = T4[eEhqHQ] * W3[hrHR]",
     "dT5[qrQReE] = rho[pqrPQR] * W1[epEP]",
     "dW1[eEpP] = T5[eEqQrR] * rho[pqrPQR]",
     "dT4[qeEhHQ] = dT5[qrQReE] * W3[hrHR]",
-    "dW3[hHrR] = T4[eEhqHQ] * dT5[qrQReE]",
+    "dW3[hHrR] += T4[eEhqHQ] * dT5[qrQReE]",
     "dT3[qeEhdCF] = dT4[qeEhHQ] * UWb[dCFHQ]",
-    "dUW[cfqhd] = T2[cfeECF] * dT3[qeEhdCF]",
+    "dUW[cfqhd] += T2[cfeECF] * dT3[qeEhdCF]",
     "dT2[eECFcf] = dT3[qeEhdCF] * UW[cdhfq]",
     "dT1[eCcfAB] = dT2[eECFcf] * u[ABEF]",
     "Du[ABEF] += T1[cABCef] * dT2[eECFcf]",
     "rhoout[abcABC] += 0.5 * dT1[eCcfAB] * u[abef]",
+    "Dw[xep] += dW1[eEpP] * w[xEP]",
+    "@end",
     "Du[cdgh] += dUW[cfqhd] * w[fgq]",
     "Dw[fgq] += u[cdgh] * dUW[cfqhd]",
-    "Dw[xep] += dW1[eEpP] * w[xEP]",
     "Dw[hyr] += dW3[hHrR] * w[HyR]",
 };
 // reduced density matrix on the two top legs of u from the two-site marginal above (Sec. 4, rho_v)
@@ -173,6 +189,18 @@ LegDims legs(int a, int b) {
 
 int64_t p6(int64_t x) { return x * x * x * x * x * x; }
 
+// Chunk of the loop leg for the 7-leg intermediates (a^6 b elements each): whole when they fit the context's
+// limit, else the largest divisor of a keeping each chunked one within half of it.
+int64_t loop_chunk(const Ctx& ctx, const LayerDim& L, size_t eb) {
+  const double full = (double)p6(L.a) * L.b * eb;
+  const double lim = (double)ctx.inter_limit;
+  if (full <= lim) return 0;
+  const double per = full / L.a;
+  for (int64_t c = L.a; c >= 1; --c)
+    if (L.a % c == 0 && per * c <= 0.5 * lim) return c;
+  return 1;
+}
+
 // Device element pointers of the contraction precision for one layer's tensors.
 struct LayerTensors {
   void* u;
@@ -201,16 +229,18 @@ namespace {
 void ascend_raw(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr in, VPtr out, Prec prec) {
   fill(ctx, out, p6(L.b), 0.0);
   const LegDims d = legs(L.a, L.b);
+  const int64_t ch = loop_chunk(ctx, L, elem_bytes(prec));
   for (int s = 0; s < 2; ++s)
-    run_program(ctx, programs().asc[s], d, {{"h", in.p}, {"u", t.u}, {"w", t.w}, {"out", out.p}}, prec);
+    run_program(ctx, programs().asc[s], d, {{"h", in.p}, {"u", t.u}, {"w", t.w}, {"out", out.p}}, prec, ch);
   symmetrize(ctx, out, (int64_t)L.b * L.b * L.b);
 }
 
 void descend_raw(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr in, VPtr out, Prec prec) {
   fill(ctx, out, p6(L.a), 0.0);
   const LegDims d = legs(L.a, L.b);
+  const int64_t ch = loop_chunk(ctx, L, elem_bytes(prec));
   for (int s = 0; s < 2; ++s)
-    run_program(ctx, programs().des[s], d, {{"rho", in.p}, {"u", t.u}, {"w", t.w}, {"out", out.p}}, prec);
+    run_program(ctx, programs().des[s], d, {{"rho", in.p}, {"u", t.u}, {"w", t.w}, {"out", out.p}}, prec, ch);
   symmetrize(ctx, out, (int64_t)L.a * L.a * L.a);
 }
 
@@ -222,11 +252,12 @@ void layer_grad(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr h, VPtr rho, V
   fill(ctx, Dw, a2 * L.b, 0.0);
   fill(ctx, rhoout, p6(L.a), 0.0);
   const LegDims d = legs(L.a, L.b);
+  const int64_t ch = loop_chunk(ctx, L, elem_bytes(prec));
   for (int s = 0; s < 2; ++s)
     run_program(ctx, programs().grad[s], d,
                 {{"h", h.p}, {"rho", rho.p}, {"u", t.u}, {"w", t.w}, {"Du", Du.p}, {"Dw", Dw.p},
                  {"rhoout", rhoout.p}},
-                prec);
+                prec, ch);
   symmetrize(ctx, rhoout, (int64_t)L.a * L.a * L.a);
 }
 

@@ -1,6 +1,8 @@
 // Contraction-program planner and executor (see network.h).
 #include "network.h"
 
+#include "vec.h"
+
 #include <algorithm>
 #include <cctype>
 #include <sstream>
@@ -49,9 +51,28 @@ Program Program::parse(const std::string& name, const std::vector<std::string>& 
       throw Error(MERA_EINVAL, "rank mismatch for tensor " + n + " in program " + name);
     return i;
   };
+  std::vector<std::string> zero_names;
   for (const std::string& raw : lines) {
     std::string line = trim(raw);
     if (line.empty()) continue;
+    if (line.rfind("@loop", 0) == 0) {
+      std::string leg = trim(line.substr(5));
+      if (leg.size() != 1 || p.loop_begin >= 0) throw Error(MERA_EINVAL, "bad @loop in program " + name);
+      p.slice_leg = leg[0];
+      p.loop_begin = (int)p.steps.size();
+      continue;
+    }
+    if (line == "@end") {
+      if (p.loop_begin < 0 || p.loop_end >= 0) throw Error(MERA_EINVAL, "bad @end in program " + name);
+      p.loop_end = (int)p.steps.size();
+      continue;
+    }
+    if (line.rfind("@zero", 0) == 0) {
+      std::stringstream zs(line.substr(5));
+      std::string t;
+      while (zs >> t) zero_names.push_back(t);
+      continue;
+    }
     bool acc = false;
     size_t eq = line.find("+=");
     if (eq != std::string::npos) {
@@ -83,6 +104,15 @@ Program Program::parse(const std::string& name, const std::vector<std::string>& 
     st.alpha = alpha;
     st.accumulate = acc;
     p.steps.push_back(st);
+  }
+  if (p.loop_begin >= 0 && p.loop_end < 0) throw Error(MERA_EINVAL, "unterminated @loop in program " + name);
+  p.produced_at.assign(p.tensors.size(), -1);
+  for (size_t si = 0; si < p.steps.size(); ++si)
+    if (p.produced_at[p.steps[si].c] < 0 && !p.external[p.steps[si].c]) p.produced_at[p.steps[si].c] = (int)si;
+  for (const std::string& z : zero_names) {
+    int i = p.id(z);
+    if (i < 0 || p.external[i]) throw Error(MERA_EINVAL, "bad @zero tensor " + z + " in program " + name);
+    p.zero_before.push_back(i);
   }
   return p;
 }
@@ -127,13 +157,20 @@ void fill_table(std::vector<int64_t>& out, const std::string& legs, const LegDim
   }
 }
 
-PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegDims& dims) {
+// `dims` gives the index ranges of the step; sdims[0..2] give the extents used for the storage strides of A, B
+// and C (they differ from `dims` only in the loop leg of a full-extent tensor addressed chunk by chunk).
+PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegDims& dims,
+                            const LegDims* const sdims[3]) {
   const StepDef& s = prog.steps[si];
   std::string key = prog.name + "#" + std::to_string(si);
   std::string all = s.la + s.lb + s.lc;
   std::sort(all.begin(), all.end());
   all.erase(std::unique(all.begin(), all.end()), all.end());
   for (char c : all) key += ":" + std::to_string(dims[(unsigned char)c]);
+  if (prog.slice_leg) {
+    const unsigned char L = (unsigned char)prog.slice_leg;
+    for (int o = 0; o < 3; ++o) key += "/" + std::to_string((*sdims[o])[L]);
+  }
   auto it = ctx.plans->map.find(key);
   if (it != ctx.plans->map.end()) return *it->second;
 
@@ -172,7 +209,7 @@ PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegD
   };
   const int64_t M = ext(Ml), N = ext(Nl), K = ext(Kl);
   const int64_t Mp = roundup(M, 128), Np = roundup(N, 128), Kp = roundup(K, 32);
-  auto sa = strides_of(s.la, dims), sb = strides_of(s.lb, dims), sc = strides_of(s.lc, dims);
+  auto sa = strides_of(s.la, *sdims[0]), sb = strides_of(s.lb, *sdims[1]), sc = strides_of(s.lc, *sdims[2]);
   std::vector<int64_t> host;
   host.reserve(2 * Mp + 2 * Np + 2 * Kp);
   std::vector<int64_t> tmp;
@@ -207,45 +244,88 @@ PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegD
 
 }  // namespace
 
-void run_program(Ctx& ctx, const Program& prog, const LegDims& dims, const std::vector<void*>& ext, Prec prec) {
+void run_program(Ctx& ctx, const Program& prog, const LegDims& dims, const std::vector<void*>& ext, Prec prec,
+                 int64_t chunk) {
   if (ext.size() != prog.tensors.size()) throw Error(MERA_EINVAL, prog.name + ": binding count");
   const size_t eb = elem_bytes(prec);
+  const unsigned char L = (unsigned char)prog.slice_leg;
+  const bool sliced = prog.slice_leg && chunk > 0 && chunk < dims[L];
+  if (sliced && dims[L] % chunk != 0) throw Error(MERA_EINVAL, prog.name + ": chunk must divide the loop leg");
+  LegDims cdims = dims;
+  if (sliced) cdims[L] = chunk;
+  auto in_loop = [&](int si) { return sliced && si >= prog.loop_begin && si < prog.loop_end; };
+  // a tensor is "inner" when the loop creates it; inner tensors are allocated with one chunk of the leg
+  auto inner = [&](int t) {
+    return sliced && prog.produced_at[t] >= prog.loop_begin && prog.produced_at[t] < prog.loop_end;
+  };
   std::vector<void*> ptr(prog.tensors.size(), nullptr);
   for (size_t i = 0; i < prog.tensors.size(); ++i) {
     if (prog.external[i]) {
       if (!ext[i]) throw Error(MERA_EINVAL, prog.name + ": unbound tensor " + prog.tensors[i]);
       ptr[i] = ext[i];
     } else {
+      const LegDims& d = inner((int)i) ? cdims : dims;
       int64_t n = 1;
-      for (char c : prog.layout[i]) n *= dims[(unsigned char)c];
+      for (char c : prog.layout[i]) n *= d[(unsigned char)c];
       ptr[i] = ctx.buf("net/" + prog.tensors[i], (size_t)n * eb);
     }
   }
-  for (size_t si = 0; si < prog.steps.size(); ++si) {
+  auto launch = [&](size_t si, const LegDims& idims, int64_t c0) {
     const StepDef& s = prog.steps[si];
-    PlanCache::Entry& e = plan_step(ctx, prog, si, dims);
+    const int ids[3] = {s.a, s.b, s.c};
+    const std::string* labs[3] = {&s.la, &s.lb, &s.lc};
+    const LegDims* sd[3];
+    void* p[3];
+    for (int o = 0; o < 3; ++o) {
+      const bool full = !in_loop((int)si) || !inner(ids[o]);
+      sd[o] = full ? &dims : &cdims;
+      p[o] = ptr[ids[o]];
+      const size_t pos = labs[o]->find((char)L);
+      if (in_loop((int)si) && full && pos != std::string::npos) {
+        // full-extent tensor addressed at this chunk of the loop leg
+        int64_t stride = 1;
+        for (size_t j = pos + 1; j < labs[o]->size(); ++j) stride *= dims[(unsigned char)(*labs[o])[j]];
+        p[o] = static_cast<char*>(p[o]) + (size_t)(c0 * stride) * eb;
+      }
+    }
+    PlanCache::Entry& e = plan_step(ctx, prog, si, idims, sd);
     GettLaunch l;
-    l.A = ptr[s.a];
-    l.B = ptr[s.b];
-    l.C = ptr[s.c];
+    l.A = p[0];
+    l.B = p[1];
+    l.C = p[2];
     l.alpha = s.alpha;
     l.beta = s.accumulate ? 1.0 : 0.0;
     l.prec = prec;
     l.splits = 0;
     gett_run(ctx, e.t, l);
     ctx.macs += e.macs;
+  };
+  const int lb = prog.loop_begin >= 0 ? prog.loop_begin : 0;
+  const int le = prog.loop_end >= 0 ? prog.loop_end : 0;
+  for (int si = 0; si < lb; ++si) launch(si, dims, 0);
+  for (int t : prog.zero_before) {
+    int64_t n = 1;
+    for (char c : prog.layout[t]) n *= dims[(unsigned char)c];
+    fill(ctx, VPtr{ptr[t], prec}, n, 0.0);
   }
+  if (sliced) {
+    for (int64_t c0 = 0; c0 < dims[L]; c0 += chunk)
+      for (int si = lb; si < le; ++si) launch(si, cdims, c0);
+  } else {
+    for (int si = lb; si < le; ++si) launch(si, dims, 0);
+  }
+  for (size_t si = le; si < prog.steps.size(); ++si) launch(si, dims, 0);
 }
 
 void run_program(Ctx& ctx, const Program& prog, const LegDims& dims,
-                 const std::vector<std::pair<std::string, void*>>& bind, Prec prec) {
+                 const std::vector<std::pair<std::string, void*>>& bind, Prec prec, int64_t chunk) {
   std::vector<void*> ext(prog.tensors.size(), nullptr);
   for (auto& b : bind) {
     int i = prog.id(b.first);
     if (i < 0) continue;
     ext[i] = b.second;
   }
-  run_program(ctx, prog, dims, ext, prec);
+  run_program(ctx, prog, dims, ext, prec, chunk);
 }
 
 }  // namespace mera

@@ -25,12 +25,21 @@ struct StepDef {
   bool accumulate = false;        // C += ... instead of C = ...
 };
 
+// Slicing: the steps between the lines "@loop <leg>" and "@end" may run in chunks of that leg (to bound the
+// size of the intermediates they create). Inside the loop, tensors created in the loop hold one chunk of the leg;
+// tensors created before the loop or bound by the caller keep their full extent and are addressed at the
+// chunk's offset. Steps in the loop that write a tensor without the leg accumulate over chunks ("+="), and the
+// internal accumulators listed on an "@zero <names>" line are cleared before the loop.
 struct Program {
   std::string name;
   std::vector<std::string> tensors;    // names
   std::vector<bool> external;          // bound by the caller
   std::vector<std::string> layout;     // declared storage labels
   std::vector<StepDef> steps;
+  char slice_leg = 0;
+  int loop_begin = -1, loop_end = -1;  // step range [begin, end) of the loop
+  std::vector<int> zero_before;        // tensor ids cleared before the loop
+  std::vector<int> produced_at;        // step index that first writes each tensor (-1: external)
   // Parse "C[cab] = A[ab] * B[bc]", "C[..] += 0.5 * A[..] * B[..]"; tensors whose name is in `externals`
   // are caller-bound, all others are intermediates owned by the context.
   static Program parse(const std::string& name, const std::vector<std::string>& lines,
@@ -52,11 +61,13 @@ struct PlanCache {
 
 // Runs `prog` with leg extents `dims`, external tensors bound to `ext` (indexed like prog.tensors; null for
 // intermediates), all tensors of element type given by `prec` (float for F32/BF16X3, double for F64).
-// Intermediates live in context scratch buffers named after the program and tensor.
-void run_program(Ctx& ctx, const Program& prog, const LegDims& dims, const std::vector<void*>& ext, Prec prec);
+// Intermediates live in context scratch buffers named after the tensor. `chunk` > 0 runs the program's loop
+// in chunks of that many values of the loop leg (it must divide the leg's extent); 0 runs it in one piece.
+void run_program(Ctx& ctx, const Program& prog, const LegDims& dims, const std::vector<void*>& ext, Prec prec,
+                 int64_t chunk = 0);
 
 // Same, with each external tensor bound by name.
 void run_program(Ctx& ctx, const Program& prog, const LegDims& dims,
-                 const std::vector<std::pair<std::string, void*>>& bind, Prec prec);
+                 const std::vector<std::pair<std::string, void*>>& bind, Prec prec, int64_t chunk = 0);
 
 }  // namespace mera

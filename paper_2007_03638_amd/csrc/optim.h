@@ -6,7 +6,7 @@
 #include <vector>
 
 #include "common.h"
-#include "mera.h"
+#include "mera_eval.h"
 
 namespace mera {
 

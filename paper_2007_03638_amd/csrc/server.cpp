@@ -10,7 +10,7 @@
 #include <thread>
 
 #include "common.h"
-#include "mera.h"
+#include "mera_eval.h"
 #include "network.h"
 #include "optim.h"
 

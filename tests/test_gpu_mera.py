@@ -76,3 +76,29 @@ def test_energy_grad_reduced_precision(ctx, prec, etol, gtol):
     for t in range(T + 1):
         assert rel(to_np(got["Du"][t]), ref["grads"][t][0]) < gtol
         assert rel(to_np(got["Dw"][t]), ref["grads"][t][1]) < gtol
+
+
+@pytest.mark.parametrize("T,chi,d,limit", [(2, 4, 4, 1), (2, 6, 3, 1_500_000)])
+def test_sliced_programs_match(ctx, T, chi, d, limit):
+    """Chunked execution of the layer programs (forced by a small intermediate limit: chunks of 1 leg value, and
+    of 2 of 6) matches the oracle."""
+    dims = om.layer_dims(chi, T, d)
+    params = inputs.mera_init(2, dims)
+    h3 = model.tfim_h3(1.0) if d == 4 else inputs.symmetric_operator(9, d ** 3)
+    ref = om.evaluate(params, h3, chi, T, d=d)
+    a, b = dims[T]
+    h = inputs.symmetric_operator(3, a ** 3)
+    rho = inputs.density_matrix(4, b ** 3)
+    try:
+        ctx.set_intermediate_limit(limit)
+        got = ctx.energy_grad(T, chi, [p[0] for p in params], [p[1] for p in params], h3, prec="fp64", d=d)
+        asc = to_np(ctx.ascend(T, chi, T, params[T][0], params[T][1], h, d=d))
+        des = to_np(ctx.descend(T, chi, T, params[T][0], params[T][1], rho, d=d))
+    finally:
+        ctx.set_intermediate_limit(32 << 30)
+    assert abs(got["energy"] - ref["energy"]) <= 1e-12 * abs(ref["energy"])
+    for t in range(T + 1):
+        assert rel(to_np(got["Du"][t]), ref["grads"][t][0]) < 1e-10
+        assert rel(to_np(got["Dw"][t]), ref["grads"][t][1]) < 1e-10
+    assert rel(asc, om.ascend(h, params[T][0], params[T][1], a, b)) < 1e-13
+    assert rel(des, om.descend(rho, params[T][0], params[T][1], a, b)) < 1e-13
