@@ -269,14 +269,18 @@ __device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-// FP32 tiles are staged in LDS as (hi, lo) bf16 pairs, k-major with 8 consecutive k per lane fragment.
+// FP32 tiles are split into bf16 hi and lo planes when staged in LDS. Each plane is stored row-major with k
+// contiguous (row pitch BK + 8 bf16 = 80 bytes), so a lane's 8-element MFMA fragment is one 16-byte LDS read.
 template <int BM, int BN, int BK, bool AKF, bool BKF>
 __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
-  static_assert(BK % 32 == 0, "bf16 MFMA consumes k in steps of 32");
+  static_assert(BK == 32, "one bf16 MFMA step per tile");
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int LDA = BM + 2, LDB = BN + 2;  // in bf16x? units: stored as separate hi/lo planes, k-major
-  __shared__ __bf16 Ah[BK * LDA], Al[BK * LDA], Bh[BK * LDB], Bl[BK * LDB];
+  constexpr int LDK = BK + 8;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[BM * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[BN * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[BN * LDK];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -313,23 +317,23 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
       lb.fetch_k(g.b_k, kb + BK);
     }
   }
+  const int kq = 8 * (lane >> 4);
   for (int64_t kt = kb; kt < ke; kt += BK) {
-    // split and stage
 #pragma unroll
     for (int i = 0; i < la.PER; ++i) {
       __bf16 h, l;
       split_bf16(la.value(i), h, l);
-      const int idx = la.lds_index(i, LDA);
-      Ah[idx] = h;
-      Al[idx] = l;
+      const int r = la.r0 + (i % la.NR) * la.RSTEP, k = la.k0 + (i / la.NR) * la.KSTEP;
+      Ah[r * LDK + k] = h;
+      Al[r * LDK + k] = l;
     }
 #pragma unroll
     for (int i = 0; i < lb.PER; ++i) {
       __bf16 h, l;
       split_bf16(lb.value(i), h, l);
-      const int idx = lb.lds_index(i, LDB);
-      Bh[idx] = h;
-      Bl[idx] = l;
+      const int r = lb.r0 + (i % lb.NR) * lb.RSTEP, k = lb.k0 + (i / lb.NR) * lb.KSTEP;
+      Bh[r * LDK + k] = h;
+      Bl[r * LDK + k] = l;
     }
     __syncthreads();
     if (kt + BK < ke) {
@@ -340,36 +344,24 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
         lb.fetch_k(g.b_k, kt + 2 * BK);
       }
     }
+    bf16x8 bh[FN], bl[FN];
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += 32) {
-      bf16x8 ah[FM], al[FM], bh[FN], bl[FN];
-      const int kq = ks + 8 * (lane >> 4);
+    for (int j = 0; j < FN; ++j) {
+      const int c = (wn + j * 16 + (lane & 15)) * LDK + kq;
+      bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[c]);
+      bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[c]);
+    }
 #pragma unroll
-      for (int i = 0; i < FM; ++i) {
-        int r = wm + i * 16 + (lane & 15);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          ah[i][e] = Ah[(kq + e) * LDA + r];
-          al[i][e] = Al[(kq + e) * LDA + r];
-        }
-      }
+    for (int i = 0; i < FM; ++i) {
+      const int r = (wm + i * 16 + (lane & 15)) * LDK + kq;
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&Ah[r]);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(&Al[r]);
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        int c = wn + j * 16 + (lane & 15);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          bh[j][e] = Bh[(kq + e) * LDB + c];
-          bl[j][e] = Bl[(kq + e) * LDB + c];
-        }
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
       }
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
     }
     __syncthreads();
   }
@@ -390,23 +382,34 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
   }
   float* __restrict__ C = static_cast<float*>(g.C);
   const float alpha = float(g.alpha), beta = float(g.beta);
+  int64_t cn[FN];
+  bool cv[FN];
 #pragma unroll
   for (int j = 0; j < FN; ++j) {
-    int64_t col = n0 + wn + j * 16 + (lane & 15);
-    int64_t cn = g.c_n[col];
-    bool cv = col < g.N;
+    const int64_t col = n0 + wn + j * 16 + (lane & 15);
+    cn[j] = g.c_n[col];
+    cv[j] = col < g.N;
+  }
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < FM; ++i) {
+    int64_t cm[4];
+    bool rv[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
-        if (cv && row < g.M) {
-          int64_t o = g.c_m[row] + cn;
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+      cm[r] = g.c_m[row];
+      rv[r] = row < g.M;
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (cv[j] && rv[r]) {
+          const int64_t o = cm[r] + cn[j];
           float v = alpha * acc[i][j][r];
           if (g.beta != 0.0) v += beta * C[o];
           C[o] = v;
         }
-      }
   }
 }
 
