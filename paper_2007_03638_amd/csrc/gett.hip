@@ -4,6 +4,7 @@
 #include "gett.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace mera {
 
@@ -100,22 +101,27 @@ struct Loader {
 #pragma unroll
     for (int j = 0; j < NK; ++j) koff[j] = off_k[kt + k0 + j * KSTEP];
   }
-  // element (i): row index i % NR, k index i / NR
+  // element (i): row index i % NR, k index i / NR. MASK = false on interior tiles, where every row and k
+  // is in range and no mask is formed.
+  template <bool MASK>
   __device__ inline void load(const T* __restrict__ base, int64_t kt, int64_t kend) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) reg[i] = base[roff[i % NR] + koff[i / NR]];
+    if (MASK) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) okm[i] = rval[i % NR] && (kt + k0 + (i / NR) * KSTEP < kend);
+      for (int i = 0; i < PER; ++i) okm[i] = rval[i % NR] && (kt + k0 + (i / NR) * KSTEP < kend);
+    }
   }
-  __device__ inline T value(int i) const { return okm[i] ? reg[i] : T(0); }
+  template <bool MASK>
+  __device__ inline T value(int i) const { return MASK ? (okm[i] ? reg[i] : T(0)) : reg[i]; }
   __device__ inline int lds_index(int i, int LD) const {
     return (k0 + (i / NR) * KSTEP) * LD + r0 + (i % NR) * RSTEP;
   }
   // LDS tile stored k-major: lds[k * LD + r]
-  template <int LD>
+  template <int LD, bool MASK>
   __device__ inline void store(T* lds) const {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) lds[lds_index(i, LD)] = value(i);
+    for (int i = 0; i < PER; ++i) lds[lds_index(i, LD)] = value<MASK>(i);
   }
 };
 
@@ -167,45 +173,52 @@ __global__ void __launch_bounds__(256) gett_kernel(Args g) {
 #pragma unroll
       for (int r = 0; r < F::NACC; ++r) acc[i][j][r] = T(0);
 
-  int buf = 0;
-  if (kb < ke) {
-    la.fetch_k(g.a_k, kb);
-    lb.fetch_k(g.b_k, kb);
-    la.load(A, kb, ke);
-    lb.load(B, kb, ke);
-    if (kb + BK < ke) {
-      la.fetch_k(g.a_k, kb + BK);
-      lb.fetch_k(g.b_k, kb + BK);
-    }
-  }
-  for (int64_t kt = kb; kt < ke; kt += BK) {
-    la.template store<LDA>(As[buf]);
-    lb.template store<LDB>(Bs[buf]);
-    __syncthreads();
-    if (kt + BK < ke) {
-      la.load(A, kt + BK, ke);
-      lb.load(B, kt + BK, ke);
-      if (kt + 2 * BK < ke) {
-        la.fetch_k(g.a_k, kt + 2 * BK);
-        lb.fetch_k(g.b_k, kt + 2 * BK);
+  auto kloop = [&](auto mask_tag) {
+    constexpr bool MASK = decltype(mask_tag)::value;
+    int buf = 0;
+    if (kb < ke) {
+      la.fetch_k(g.a_k, kb);
+      lb.fetch_k(g.b_k, kb);
+      la.template load<MASK>(A, kb, ke);
+      lb.template load<MASK>(B, kb, ke);
+      if (kb + BK < ke) {
+        la.fetch_k(g.a_k, kb + BK);
+        lb.fetch_k(g.b_k, kb + BK);
       }
     }
-    const T* as = As[buf];
-    const T* bs = Bs[buf];
+    for (int64_t kt = kb; kt < ke; kt += BK) {
+      la.template store<LDA, MASK>(As[buf]);
+      lb.template store<LDB, MASK>(Bs[buf]);
+      __syncthreads();
+      if (kt + BK < ke) {
+        la.template load<MASK>(A, kt + BK, ke);
+        lb.template load<MASK>(B, kt + BK, ke);
+        if (kt + 2 * BK < ke) {
+          la.fetch_k(g.a_k, kt + 2 * BK);
+          lb.fetch_k(g.b_k, kt + 2 * BK);
+        }
+      }
+      const T* as = As[buf];
+      const T* bs = Bs[buf];
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += F::KT) {
-      T af[FM], bf[FN];
+      for (int ks = 0; ks < BK; ks += F::KT) {
+        T af[FM], bf[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = as[(ks + lane / F::MT) * LDA + wm + i * F::MT + lane % F::MT];
+        for (int i = 0; i < FM; ++i) af[i] = as[(ks + lane / F::MT) * LDA + wm + i * F::MT + lane % F::MT];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = bs[(ks + lane / F::NT) * LDB + wn + j * F::NT + lane % F::NT];
+        for (int j = 0; j < FN; ++j) bf[j] = bs[(ks + lane / F::NT) * LDB + wn + j * F::NT + lane % F::NT];
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = F::mma(af[i], bf[j], acc[i][j]);
+          for (int j = 0; j < FN; ++j) acc[i][j] = F::mma(af[i], bf[j], acc[i][j]);
+      }
+      buf ^= 1;
     }
-    buf ^= 1;
-  }
+  };
+  // interior tiles (all rows, columns and k in range) skip the range masks
+  const bool interior = (m0 + BM <= g.M) && (n0 + BN <= g.N) && ((ke - kb) % BK == 0);
+  if (interior) kloop(std::false_type{});
+  else kloop(std::true_type{});
 
   // epilogue
   if (g.partial) {
@@ -310,8 +323,8 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
   if (kb < ke) {
     la.fetch_k(g.a_k, kb);
     lb.fetch_k(g.b_k, kb);
-    la.load(A, kb, ke);
-    lb.load(B, kb, ke);
+    la.template load<true>(A, kb, ke);
+    lb.template load<true>(B, kb, ke);
     if (kb + BK < ke) {
       la.fetch_k(g.a_k, kb + BK);
       lb.fetch_k(g.b_k, kb + BK);
@@ -322,7 +335,7 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
 #pragma unroll
     for (int i = 0; i < la.PER; ++i) {
       __bf16 h, l;
-      split_bf16(la.value(i), h, l);
+      split_bf16(la.template value<true>(i), h, l);
       const int r = la.r0 + (i % la.NR) * la.RSTEP, k = la.k0 + (i / la.NR) * la.KSTEP;
       Ah[r * LDK + k] = h;
       Al[r * LDK + k] = l;
@@ -330,15 +343,15 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
 #pragma unroll
     for (int i = 0; i < lb.PER; ++i) {
       __bf16 h, l;
-      split_bf16(lb.value(i), h, l);
+      split_bf16(lb.template value<true>(i), h, l);
       const int r = lb.r0 + (i % lb.NR) * lb.RSTEP, k = lb.k0 + (i / lb.NR) * lb.KSTEP;
       Bh[r * LDK + k] = h;
       Bl[r * LDK + k] = l;
     }
     __syncthreads();
     if (kt + BK < ke) {
-      la.load(A, kt + BK, ke);
-      lb.load(B, kt + BK, ke);
+      la.template load<true>(A, kt + BK, ke);
+      lb.template load<true>(B, kt + BK, ke);
       if (kt + 2 * BK < ke) {
         la.fetch_k(g.a_k, kt + 2 * BK);
         lb.fetch_k(g.b_k, kt + 2 * BK);
