@@ -243,9 +243,28 @@ mera_status run_optimize(mera_ctx* ctx, const mera_job* job, mera_result* out, d
 /* A server owns `max_slots` host workers, each with its own HIP stream and workspace on the context's
  * device. Submitted jobs wait in a FIFO queue; the head job is admitted when a worker is free and the summed
  * device-memory footprint of the running jobs plus its own fits `hbm_budget` bytes; the device work of the
- * running jobs overlaps. A job computes exactly what run_optimize computes for it alone. Destroying the server
- * waits for running jobs and drops queued ones. */
+ * running jobs overlaps. Contraction programs (ascending / descending maps, gradient networks) that
+ * concurrent jobs reach at the same extents are run as one sequence of grouped MFMA launches (up to 8 jobs per
+ * launch), and a sequence seen before on the same buffers is replayed from a captured HIP graph. A job
+ * computes exactly what run_optimize computes for it alone (same kernels, tiles and reduction order).
+ * Destroying the server waits for running jobs and drops queued ones. The server also holds the offset
+ * tables of every contraction shape it has run (shared by its workers) until it is destroyed. */
 mera_status mera_server_create(mera_ctx* ctx, size_t hbm_budget, int max_slots, mera_server** out);
+/* Batching options, before the first submit (MERA_EBUSY afterwards): group_launches != 0 groups the same
+ * program across jobs (default on); graph_capture != 0 replays repeated sequences from HIP graphs (default
+ * on); max_wait_us bounds how long a job waits for others of its shape to reach the same program (default
+ * 2000). With both off every job launches its own kernels on its own stream. */
+mera_status mera_server_configure(mera_server* srv, int group_launches, int graph_capture, double max_wait_us);
+typedef struct {
+  int64_t batches;          /* program runs (grouped or not) */
+  int64_t grouped_batches;  /* runs that carried more than one job */
+  int64_t bindings;         /* job-programs executed (sum of group sizes) */
+  int64_t graph_launches;   /* runs replayed from a captured graph */
+  int64_t graph_captures;   /* graphs captured */
+  int64_t eager_runs;       /* runs launched kernel by kernel */
+} mera_server_stats;
+/* Counters since creation. */
+mera_status mera_server_get_stats(mera_server* srv, mera_server_stats* out);
 /* The job is copied (including h3 and initial tensors) before the call returns. */
 mera_status mera_server_submit(mera_server* srv, const mera_job* job, uint64_t* job_id);
 /* MERA_EBUSY while queued or running; MERA_OK with the result once finished (or the job's error status,

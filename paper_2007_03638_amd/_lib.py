@@ -39,6 +39,12 @@ class Result(ctypes.Structure):
                 ("queued_seconds", c_double), ("krylov_applications", c_int)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_int64), ("grouped_batches", ctypes.c_int64), ("bindings", ctypes.c_int64),
+                ("graph_launches", ctypes.c_int64), ("graph_captures", ctypes.c_int64),
+                ("eager_runs", ctypes.c_int64)]
+
+
 class IterLog(ctypes.Structure):
     _fields_ = [("iter", c_int), ("evals", c_int), ("energy", c_double), ("gnorm", c_double), ("alpha", c_double),
                 ("prec", c_int)]
@@ -91,6 +97,8 @@ SIGNATURES = {
     "mera_opt_final": (c_int, [c_void_p, c_void_p, ctypes.POINTER(ctypes.POINTER(c_double))]),
     "mera_opt_destroy": (None, [c_void_p]),
     "mera_server_create": (c_int, [c_void_p, c_size_t, c_int, ctypes.POINTER(c_void_p)]),
+    "mera_server_configure": (c_int, [c_void_p, c_int, c_int, c_double]),
+    "mera_server_get_stats": (c_int, [c_void_p, ctypes.POINTER(ServerStats)]),
     "mera_server_submit": (c_int, [c_void_p, ctypes.POINTER(Job), ctypes.POINTER(c_uint64)]),
     "mera_server_poll": (c_int, [c_void_p, c_uint64, ctypes.POINTER(Result)]),
     "mera_job_footprint": (c_size_t, [ctypes.POINTER(MeraShape), c_int]),

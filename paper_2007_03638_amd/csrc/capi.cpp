@@ -118,6 +118,7 @@ mera_status mera_ctx_trim(mera_ctx* ctx) {
     DeviceGuard g(ctx->c.device);
     ctx->c.sync();
     ctx->c.scratch.clear();
+    std::lock_guard<std::mutex> lock(ctx->c.plans->mu);
     ctx->c.plans->map.clear();
   });
 }

@@ -73,6 +73,7 @@ enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 inline size_t elem_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
 struct PlanCache;  // network.h
+struct Batcher;    // network.h
 
 // Per-launch timing of contraction kernels with HIP events on the context stream (profiling mode).
 struct LaunchRecord {
@@ -89,7 +90,8 @@ struct Ctx {
   double macs = 0.0;
   // Named grow-only scratch buffers (intermediates, partial sums), reused across calls.
   std::map<std::string, DevBuf> scratch;
-  std::unique_ptr<PlanCache> plans;
+  std::shared_ptr<PlanCache> plans;  // may be shared by the contexts of one server
+  Batcher* batcher = nullptr;        // non-null: contraction programs go through the server's batcher
   DevBuf red;        // reduction partials (doubles)
   size_t inter_limit = (size_t)32 << 30;  // largest 7-leg intermediate built in one piece (bytes)
   bool profiling = false;

@@ -25,16 +25,24 @@ struct GettTables {
   bool b_kfast = false;  // B's unit-stride leg is a K leg, else an N leg
 };
 
+// Largest number of operand sets in one grouped launch.
+constexpr int kGettMaxGroup = 8;
+
 struct GettLaunch {
-  const void* A = nullptr;
-  const void* B = nullptr;
-  void* C = nullptr;
+  // `groups` independent operand sets (A[g], B[g], C[g]) contracted with the same tables in one launch; set g
+  // computes exactly what a launch of that set alone computes.
+  int groups = 1;
+  const void* A[kGettMaxGroup] = {};
+  const void* B[kGettMaxGroup] = {};
+  void* C[kGettMaxGroup] = {};
   double alpha = 1.0, beta = 0.0;
   Prec prec = Prec::F64;
-  int splits = 1;  // split-K factor (partials reduced in FP64)
+  int splits = 0;             // split-K factor (partials reduced in FP64); 0 chooses it from the extents
+  bool prepare_only = false;  // size the split-K scratch and return without launching
 };
 
-// Chooses tile shape and split-K and launches on `stream`; `ctx` provides split-K scratch.
+// Chooses tile shape and split-K and launches on ctx.stream; `ctx` provides the split-K scratch. The choice
+// depends only on the tables' extents and the precision, never on `groups`.
 void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l);
 
 }  // namespace mera

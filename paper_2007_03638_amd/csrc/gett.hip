@@ -10,10 +10,13 @@ namespace mera {
 
 namespace {
 
+// One launch runs the same contraction (same tables and extents) for up to kGettMaxGroup independent operand
+// sets; blockIdx.y selects the set.
 struct Args {
-  const void* A;
-  const void* B;
-  void* C;
+  const void* A[kGettMaxGroup];
+  const void* B[kGettMaxGroup];
+  void* C[kGettMaxGroup];
+  void* partial[kGettMaxGroup];  // splits x M x N partial sums per set (accumulator type); used when split != 0
   const int64_t* a_m;
   const int64_t* a_k;
   const int64_t* b_k;
@@ -23,7 +26,7 @@ struct Args {
   int64_t M, N, K;
   int64_t kchunk;  // K range per split, a multiple of BK
   double alpha, beta;
-  void* partial;   // splits x M x N partial sums (element type of the accumulator), or null
+  int split;       // 1: write partial sums, 0: write C
 };
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -157,8 +160,9 @@ __global__ void __launch_bounds__(256) gett_kernel(Args g) {
   const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
   const int64_t ke = (g.K < kb + g.kchunk) ? g.K : kb + g.kchunk;
 
-  const T* __restrict__ A = static_cast<const T*>(g.A);
-  const T* __restrict__ B = static_cast<const T*>(g.B);
+  const int grp = blockIdx.y;
+  const T* __restrict__ A = static_cast<const T*>(g.A[grp]);
+  const T* __restrict__ B = static_cast<const T*>(g.B[grp]);
 
   Loader<T, BM, BK, AKF> la;
   Loader<T, BN, BK, BKF> lb;
@@ -221,8 +225,8 @@ __global__ void __launch_bounds__(256) gett_kernel(Args g) {
   else kloop(std::true_type{});
 
   // epilogue
-  if (g.partial) {
-    T* P = static_cast<T*>(g.partial) + (int64_t)blockIdx.z * g.M * g.N;
+  if (g.split) {
+    T* P = static_cast<T*>(g.partial[grp]) + (int64_t)blockIdx.z * g.M * g.N;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -235,7 +239,7 @@ __global__ void __launch_bounds__(256) gett_kernel(Args g) {
         }
     return;
   }
-  T* __restrict__ C = static_cast<T*>(g.C);
+  T* __restrict__ C = static_cast<T*>(g.C[grp]);
   const T alpha = T(g.alpha), beta = T(g.beta);
   // table lookups first (padded: always in range), then the masked stores
   int64_t cn[FN];
@@ -306,8 +310,9 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
   const int64_t n0 = (tile % tiles_n) * BN;
   const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
   const int64_t ke = (g.K < kb + g.kchunk) ? g.K : kb + g.kchunk;
-  const float* __restrict__ A = static_cast<const float*>(g.A);
-  const float* __restrict__ B = static_cast<const float*>(g.B);
+  const int grp = blockIdx.y;
+  const float* __restrict__ A = static_cast<const float*>(g.A[grp]);
+  const float* __restrict__ B = static_cast<const float*>(g.B[grp]);
 
   Loader<float, BM, BK, AKF> la;
   Loader<float, BN, BK, BKF> lb;
@@ -379,8 +384,8 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
     __syncthreads();
   }
 
-  if (g.partial) {
-    float* P = static_cast<float*>(g.partial) + (int64_t)blockIdx.z * g.M * g.N;
+  if (g.split) {
+    float* P = static_cast<float*>(g.partial[grp]) + (int64_t)blockIdx.z * g.M * g.N;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -393,7 +398,7 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
         }
     return;
   }
-  float* __restrict__ C = static_cast<float*>(g.C);
+  float* __restrict__ C = static_cast<float*>(g.C[grp]);
   const float alpha = float(g.alpha), beta = float(g.beta);
   int64_t cn[FN];
   bool cv[FN];
@@ -426,10 +431,16 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
   }
 }
 
+struct RedArgs {
+  const void* P[kGettMaxGroup];
+  void* C[kGettMaxGroup];
+};
+
 template <typename T>
-__global__ void splitk_reduce_kernel(const T* __restrict__ P, int splits, int64_t M, int64_t N,
-                                     const int64_t* __restrict__ c_m, const int64_t* __restrict__ c_n, T* C,
-                                     double alpha, double beta) {
+__global__ void splitk_reduce_kernel(RedArgs r, int splits, int64_t M, int64_t N, const int64_t* __restrict__ c_m,
+                                     const int64_t* __restrict__ c_n, double alpha, double beta) {
+  const T* __restrict__ P = static_cast<const T*>(r.P[blockIdx.y]);
+  T* C = static_cast<T*>(r.C[blockIdx.y]);
   const int64_t total = M * N;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -444,9 +455,9 @@ __global__ void splitk_reduce_kernel(const T* __restrict__ P, int splits, int64_
 }
 
 template <typename T, int BM, int BN, int BK>
-void launch_tile(const Args& a, int splits, hipStream_t s, bool akf, bool bkf) {
+void launch_tile(const Args& a, int groups, int splits, hipStream_t s, bool akf, bool bkf) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
-  dim3 grid((unsigned)tiles, 1, (unsigned)splits), block(256);
+  dim3 grid((unsigned)tiles, (unsigned)groups, (unsigned)splits), block(256);
   if (akf && bkf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, true, true>), grid, block, 0, s, a);
   else if (akf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, true, false>), grid, block, 0, s, a);
   else if (bkf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, false, true>), grid, block, 0, s, a);
@@ -454,9 +465,9 @@ void launch_tile(const Args& a, int splits, hipStream_t s, bool akf, bool bkf) {
 }
 
 template <int BM, int BN, int BK>
-void launch_bf16x3(const Args& a, int splits, hipStream_t s, bool akf, bool bkf) {
+void launch_bf16x3(const Args& a, int groups, int splits, hipStream_t s, bool akf, bool bkf) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
-  dim3 grid((unsigned)tiles, 1, (unsigned)splits), block(256);
+  dim3 grid((unsigned)tiles, (unsigned)groups, (unsigned)splits), block(256);
   if (akf && bkf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, true, true>), grid, block, 0, s, a);
   else if (akf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, true, false>), grid, block, 0, s, a);
   else if (bkf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, false, true>), grid, block, 0, s, a);
@@ -467,10 +478,14 @@ void launch_bf16x3(const Args& a, int splits, hipStream_t s, bool akf, bool bkf)
 
 void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
   if (t.M <= 0 || t.N <= 0) return;
+  const int G = l.groups;
+  if (G < 1 || G > kGettMaxGroup) throw Error(MERA_EINVAL, "gett: group count out of range");
   Args a{};
-  a.A = l.A;
-  a.B = l.B;
-  a.C = l.C;
+  for (int g = 0; g < G; ++g) {
+    a.A[g] = l.A[g];
+    a.B[g] = l.B[g];
+    a.C[g] = l.C[g];
+  }
   a.a_m = t.a_m;
   a.a_k = t.a_k;
   a.b_k = t.b_k;
@@ -482,7 +497,7 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
   a.K = t.K;
   a.alpha = l.alpha;
   a.beta = l.beta;
-  a.partial = nullptr;
+  a.split = 0;
 
   // tile shape: large tiles when both extents allow, otherwise 64-wide. FP64 uses at most 128 x 64: the 128 x 128
   // FP64 tile needs more than 256 registers per lane, leaving one wave per SIMD.
@@ -505,33 +520,37 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
 
   const size_t eb = (l.prec == Prec::F64) ? 8 : 4;
   if (splits > 1) {
-    a.partial = ctx.buf("gett.partial", (size_t)splits * t.M * t.N * eb);
+    const size_t per = (size_t)splits * t.M * t.N * eb;
+    char* p = static_cast<char*>(ctx.buf("gett.partial", per * G));
+    for (int g = 0; g < G; ++g) a.partial[g] = p + per * g;
+    a.split = 1;
   }
+  if (l.prepare_only) return;
   hipStream_t s = ctx.stream;
   LaunchRecord rec;
   if (ctx.profiling) {
     rec.kernel = std::string("gett<") + (l.prec == Prec::F64 ? "f64" : (l.prec == Prec::F32 ? "f32" : "bf16x3")) +
                  "," + std::to_string(BMsel) + "x" + std::to_string(BNsel) + (t.a_kfast ? ",Ak" : ",Am") +
-                 (t.b_kfast ? ",Bk" : ",Bn") + (splits > 1 ? ",splitk" : "") + ">";
-    rec.flops = 2.0 * (double)t.M * (double)t.N * (double)t.K;
-    rec.bytes = (double)eb * ((double)t.M * t.K + (double)t.K * t.N + (double)t.M * t.N * (l.beta != 0.0 ? 2 : 1));
+                 (t.b_kfast ? ",Bk" : ",Bn") + (splits > 1 ? ",splitk" : "") + (G > 1 ? ",grouped" : "") + ">";
+    rec.flops = 2.0 * G * (double)t.M * (double)t.N * (double)t.K;
+    rec.bytes = G * (double)eb * ((double)t.M * t.K + (double)t.K * t.N + (double)t.M * t.N * (l.beta != 0.0 ? 2 : 1));
     rec.start = ctx.take_event();
     rec.stop = ctx.take_event();
     MERA_HIP(hipEventRecord(rec.start, s));
   }
   if (l.prec == Prec::F64) {
-    if (bigm) launch_tile<double, 128, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
-    else launch_tile<double, 64, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
+    if (bigm) launch_tile<double, 128, 64, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
+    else launch_tile<double, 64, 64, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
   } else if (l.prec == Prec::F32) {
-    if (bigm && bign) launch_tile<float, 128, 128, 16>(a, splits, s, t.a_kfast, t.b_kfast);
-    else if (bigm) launch_tile<float, 128, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
-    else if (bign) launch_tile<float, 64, 128, 16>(a, splits, s, t.a_kfast, t.b_kfast);
-    else launch_tile<float, 64, 64, 16>(a, splits, s, t.a_kfast, t.b_kfast);
+    if (bigm && bign) launch_tile<float, 128, 128, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
+    else if (bigm) launch_tile<float, 128, 64, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
+    else if (bign) launch_tile<float, 64, 128, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
+    else launch_tile<float, 64, 64, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
   } else {
-    if (bigm && bign) launch_bf16x3<128, 128, 32>(a, splits, s, t.a_kfast, t.b_kfast);
-    else if (bigm) launch_bf16x3<128, 64, 32>(a, splits, s, t.a_kfast, t.b_kfast);
-    else if (bign) launch_bf16x3<64, 128, 32>(a, splits, s, t.a_kfast, t.b_kfast);
-    else launch_bf16x3<64, 64, 32>(a, splits, s, t.a_kfast, t.b_kfast);
+    if (bigm && bign) launch_bf16x3<128, 128, 32>(a, G, splits, s, t.a_kfast, t.b_kfast);
+    else if (bigm) launch_bf16x3<128, 64, 32>(a, G, splits, s, t.a_kfast, t.b_kfast);
+    else if (bign) launch_bf16x3<64, 128, 32>(a, G, splits, s, t.a_kfast, t.b_kfast);
+    else launch_bf16x3<64, 64, 32>(a, G, splits, s, t.a_kfast, t.b_kfast);
   }
   MERA_HIP(hipGetLastError());
   if (ctx.profiling) {
@@ -539,16 +558,19 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
     ctx.records.push_back(rec);
   }
   if (splits > 1) {
+    RedArgs r{};
+    for (int g = 0; g < G; ++g) {
+      r.P[g] = a.partial[g];
+      r.C[g] = l.C[g];
+    }
     const int64_t total = t.M * t.N;
     int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
     if (l.prec == Prec::F64)
-      hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3(blocks), dim3(256), 0, s,
-                         static_cast<const double*>(a.partial), splits, t.M, t.N, t.c_m, t.c_n,
-                         static_cast<double*>(l.C), l.alpha, l.beta);
+      hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3(blocks, G), dim3(256), 0, s, r, splits, t.M, t.N, t.c_m,
+                         t.c_n, l.alpha, l.beta);
     else
-      hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(blocks), dim3(256), 0, s,
-                         static_cast<const float*>(a.partial), splits, t.M, t.N, t.c_m, t.c_n,
-                         static_cast<float*>(l.C), l.alpha, l.beta);
+      hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(blocks, G), dim3(256), 0, s, r, splits, t.M, t.N, t.c_m,
+                         t.c_n, l.alpha, l.beta);
     MERA_HIP(hipGetLastError());
   }
 }

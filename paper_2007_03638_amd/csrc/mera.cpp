@@ -171,6 +171,8 @@ struct Programs {
     grad[0] = Program::parse("gradL", lines(kGradL), ext);
     grad[1] = Program::parse("gradR", lines(kGradR), ext);
     rhou = Program::parse("rhou", lines(kRhoU), ext);
+    // the chi^9 networks are worth grouping across concurrent jobs
+    for (Program* p : {&asc[0], &asc[1], &des[0], &des[1], &grad[0], &grad[1]}) p->batch = true;
   }
 };
 

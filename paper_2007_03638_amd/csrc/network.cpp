@@ -171,6 +171,7 @@ PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegD
     const unsigned char L = (unsigned char)prog.slice_leg;
     for (int o = 0; o < 3; ++o) key += "/" + std::to_string((*sdims[o])[L]);
   }
+  std::lock_guard<std::mutex> lock(ctx.plans->mu);
   auto it = ctx.plans->map.find(key);
   if (it != ctx.plans->map.end()) return *it->second;
 
@@ -223,7 +224,10 @@ PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegD
 
   auto e = std::make_unique<PlanCache::Entry>();
   e->tables.alloc(host.size() * sizeof(int64_t));
-  MERA_HIP(hipMemcpy(e->tables.ptr, host.data(), host.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  // stream-ordered upload (the host vector lives until the sync); no work on the legacy null stream
+  MERA_HIP(hipMemcpyAsync(e->tables.ptr, host.data(), host.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                          ctx.stream));
+  MERA_HIP(hipStreamSynchronize(ctx.stream));
   const int64_t* base = e->tables.as<int64_t>();
   e->t.a_m = base + off_am;
   e->t.a_k = base + off_ak;
@@ -244,9 +248,12 @@ PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegD
 
 }  // namespace
 
-void run_program(Ctx& ctx, const Program& prog, const LegDims& dims, const std::vector<void*>& ext, Prec prec,
-                 int64_t chunk) {
-  if (ext.size() != prog.tensors.size()) throw Error(MERA_EINVAL, prog.name + ": binding count");
+double run_group(Ctx& lead, const Program& prog, const LegDims& dims, const std::vector<Binding>& group, Prec prec,
+                 int64_t chunk, bool prepare_only, std::vector<const void*>* touched) {
+  const int G = (int)group.size();
+  if (G < 1 || G > kGettMaxGroup) throw Error(MERA_EINVAL, prog.name + ": group size out of range");
+  for (const Binding& b : group)
+    if (!b.ctx || b.ext.size() != prog.tensors.size()) throw Error(MERA_EINVAL, prog.name + ": binding count");
   const size_t eb = elem_bytes(prec);
   const unsigned char L = (unsigned char)prog.slice_leg;
   const bool sliced = prog.slice_leg && chunk > 0 && chunk < dims[L];
@@ -258,56 +265,65 @@ void run_program(Ctx& ctx, const Program& prog, const LegDims& dims, const std::
   auto inner = [&](int t) {
     return sliced && prog.produced_at[t] >= prog.loop_begin && prog.produced_at[t] < prog.loop_end;
   };
-  std::vector<void*> ptr(prog.tensors.size(), nullptr);
-  for (size_t i = 0; i < prog.tensors.size(); ++i) {
-    if (prog.external[i]) {
-      if (!ext[i]) throw Error(MERA_EINVAL, prog.name + ": unbound tensor " + prog.tensors[i]);
-      ptr[i] = ext[i];
-    } else {
-      const LegDims& d = inner((int)i) ? cdims : dims;
-      int64_t n = 1;
-      for (char c : prog.layout[i]) n *= d[(unsigned char)c];
-      ptr[i] = ctx.buf("net/" + prog.tensors[i], (size_t)n * eb);
+  const size_t nt = prog.tensors.size();
+  std::vector<void*> ptr(nt * G, nullptr);  // ptr[g * nt + i]
+  for (int g = 0; g < G; ++g)
+    for (size_t i = 0; i < nt; ++i) {
+      void*& p = ptr[g * nt + i];
+      if (prog.external[i]) {
+        if (!group[g].ext[i]) throw Error(MERA_EINVAL, prog.name + ": unbound tensor " + prog.tensors[i]);
+        p = group[g].ext[i];
+      } else {
+        const LegDims& d = inner((int)i) ? cdims : dims;
+        int64_t n = 1;
+        for (char c : prog.layout[i]) n *= d[(unsigned char)c];
+        p = group[g].ctx->buf("net/" + prog.tensors[i], (size_t)n * eb);
+      }
     }
-  }
+  double macs = 0;  // per binding
   auto launch = [&](size_t si, const LegDims& idims, int64_t c0) {
     const StepDef& s = prog.steps[si];
     const int ids[3] = {s.a, s.b, s.c};
     const std::string* labs[3] = {&s.la, &s.lb, &s.lc};
     const LegDims* sd[3];
-    void* p[3];
+    size_t shift[3];
     for (int o = 0; o < 3; ++o) {
       const bool full = !in_loop((int)si) || !inner(ids[o]);
       sd[o] = full ? &dims : &cdims;
-      p[o] = ptr[ids[o]];
+      shift[o] = 0;
       const size_t pos = labs[o]->find((char)L);
       if (in_loop((int)si) && full && pos != std::string::npos) {
         // full-extent tensor addressed at this chunk of the loop leg
         int64_t stride = 1;
         for (size_t j = pos + 1; j < labs[o]->size(); ++j) stride *= dims[(unsigned char)(*labs[o])[j]];
-        p[o] = static_cast<char*>(p[o]) + (size_t)(c0 * stride) * eb;
+        shift[o] = (size_t)(c0 * stride) * eb;
       }
     }
-    PlanCache::Entry& e = plan_step(ctx, prog, si, idims, sd);
+    PlanCache::Entry& e = plan_step(lead, prog, si, idims, sd);
     GettLaunch l;
-    l.A = p[0];
-    l.B = p[1];
-    l.C = p[2];
+    l.groups = G;
+    for (int g = 0; g < G; ++g) {
+      l.A[g] = static_cast<char*>(ptr[g * nt + ids[0]]) + shift[0];
+      l.B[g] = static_cast<char*>(ptr[g * nt + ids[1]]) + shift[1];
+      l.C[g] = static_cast<char*>(ptr[g * nt + ids[2]]) + shift[2];
+    }
     l.alpha = s.alpha;
     l.beta = s.accumulate ? 1.0 : 0.0;
     l.prec = prec;
     l.splits = 0;
-    gett_run(ctx, e.t, l);
-    ctx.macs += e.macs;
+    l.prepare_only = prepare_only;
+    gett_run(lead, e.t, l);
+    macs += e.macs;
   };
   const int lb = prog.loop_begin >= 0 ? prog.loop_begin : 0;
   const int le = prog.loop_end >= 0 ? prog.loop_end : 0;
   for (int si = 0; si < lb; ++si) launch(si, dims, 0);
-  for (int t : prog.zero_before) {
-    int64_t n = 1;
-    for (char c : prog.layout[t]) n *= dims[(unsigned char)c];
-    fill(ctx, VPtr{ptr[t], prec}, n, 0.0);
-  }
+  if (!prepare_only)
+    for (int t : prog.zero_before) {
+      int64_t n = 1;
+      for (char c : prog.layout[t]) n *= dims[(unsigned char)c];
+      for (int g = 0; g < G; ++g) fill(lead, VPtr{ptr[g * nt + t], prec}, n, 0.0);
+    }
   if (sliced) {
     for (int64_t c0 = 0; c0 < dims[L]; c0 += chunk)
       for (int si = lb; si < le; ++si) launch(si, cdims, c0);
@@ -315,6 +331,24 @@ void run_program(Ctx& ctx, const Program& prog, const LegDims& dims, const std::
     for (int si = lb; si < le; ++si) launch(si, dims, 0);
   }
   for (size_t si = le; si < prog.steps.size(); ++si) launch(si, dims, 0);
+  if (touched) {
+    touched->assign(ptr.begin(), ptr.end());
+    auto it = lead.scratch.find("gett.partial");
+    touched->push_back(it == lead.scratch.end() ? nullptr : it->second.ptr);
+  }
+  if (!prepare_only)
+    for (int g = 0; g < G; ++g) group[g].ctx->macs += macs;
+  return macs;
+}
+
+void run_program(Ctx& ctx, const Program& prog, const LegDims& dims, const std::vector<void*>& ext, Prec prec,
+                 int64_t chunk) {
+  if (ext.size() != prog.tensors.size()) throw Error(MERA_EINVAL, prog.name + ": binding count");
+  if (ctx.batcher) {
+    ctx.batcher->run(ctx, prog, dims, ext, prec, chunk);
+    return;
+  }
+  run_group(ctx, prog, dims, {Binding{&ctx, ext}}, prec, chunk, false, nullptr);
 }
 
 void run_program(Ctx& ctx, const Program& prog, const LegDims& dims,

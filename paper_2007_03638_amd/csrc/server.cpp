@@ -1,7 +1,10 @@
 // Continuous-batching job server: a FIFO queue, admission by device-memory footprint and free slots, one
 // host worker per slot with its own HIP stream and workspace, so the device work of concurrently running
-// jobs overlaps. Each job runs exactly the kernels and reduction order it would run alone, so its result is
-// independent of the mix.
+// jobs overlaps. Contraction programs of concurrent jobs meet in a batcher: calls of the same program at the
+// same extents are run as one sequence of grouped MFMA launches, and a sequence seen before with the same
+// buffers is replayed from a captured HIP graph. Each job's operands go through exactly the kernels, tiles and
+// reduction order they would alone, so its result is independent of the mix.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -40,6 +43,229 @@ size_t job_footprint(const mera_shape& s, Prec prec) {
   return (size_t)(bytes * 1.1) + ((size_t)64 << 20);
 }
 
+
+// Groups run_program calls of concurrently running jobs. A call opens a batch keyed by (program, extents,
+// precision, chunk) or joins the open batch of that key; the opener (leader) waits until every other worker
+// running a job of the same shape is itself waiting in the batcher (or the batch is full, or max_wait has
+// passed), then runs the group on its own stream. Stream order: the leader's stream waits for each member's
+// "ready" event (recorded on the member's stream at the call), and each member's stream waits for the
+// leader's "done" event afterwards, so a member continues exactly as if it had launched the work itself.
+struct GroupBatcher : Batcher {
+  bool grouping = true;
+  bool graphs = true;
+  double max_wait = 2e-3;  // seconds a leader waits for members
+
+  struct WorkerState {
+    std::string shape;  // shape of the job being run ("" while idle)
+    bool waiting = false;
+    hipEvent_t ready = nullptr, done = nullptr;
+  };
+  struct Request {
+    Ctx* ctx = nullptr;
+    const std::vector<void*>* ext = nullptr;
+    bool done = false;
+    int status = 0;
+    std::string err;
+  };
+  struct Batch {
+    std::vector<Request*> reqs;
+  };
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    int seen = 0;
+  };
+
+  std::mutex mu;
+  std::condition_variable cv;
+  std::map<const Ctx*, WorkerState> states;
+  std::map<std::string, Batch*> open;
+  std::mutex gmu;
+  std::map<std::string, GraphEntry> graph_cache;
+  static constexpr size_t kMaxGraphs = 4096;
+  mera_server_stats stats{};
+
+  ~GroupBatcher() override {
+    (void)hipDeviceSynchronize();
+    for (auto& kv : graph_cache)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    for (auto& kv : states) {
+      if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+      if (kv.second.done) (void)hipEventDestroy(kv.second.done);
+    }
+  }
+
+  void attach(Ctx& ctx) {
+    std::lock_guard<std::mutex> lk(mu);
+    WorkerState& w = states[&ctx];
+    MERA_HIP(hipEventCreateWithFlags(&w.ready, hipEventDisableTiming));
+    MERA_HIP(hipEventCreateWithFlags(&w.done, hipEventDisableTiming));
+  }
+  void set_shape(const Ctx& ctx, const std::string& shape) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      states[&ctx].shape = shape;
+    }
+    cv.notify_all();
+  }
+
+  static std::string batch_key(const Program& prog, const LegDims& dims, Prec prec, int64_t chunk) {
+    std::string k = prog.name + "|" + std::to_string((int)prec) + "|" + std::to_string(chunk);
+    for (size_t c = 0; c < dims.size(); ++c)
+      if (dims[c]) k += "," + std::to_string(c) + ":" + std::to_string(dims[c]);
+    return k;
+  }
+
+  // true while some other worker running a job of the same shape is neither waiting nor in the batch
+  bool others_coming(const Ctx* me, const Batch& b) const {
+    const std::string& shape = states.at(me).shape;
+    for (const auto& kv : states) {
+      if (kv.first == me || kv.second.waiting || kv.second.shape.empty() || kv.second.shape != shape) continue;
+      bool member = false;
+      for (const Request* r : b.reqs) member = member || r->ctx == kv.first;
+      if (!member) return true;
+    }
+    return false;
+  }
+
+  void run(Ctx& ctx, const Program& prog, const LegDims& dims, const std::vector<void*>& ext, Prec prec,
+           int64_t chunk) override {
+    if ((!grouping && !graphs) || !prog.batch) {
+      run_group(ctx, prog, dims, {Binding{&ctx, ext}}, prec, chunk, false, nullptr);
+      return;
+    }
+    const std::string key = batch_key(prog, dims, prec, chunk);
+    Request req;
+    req.ctx = &ctx;
+    req.ext = &ext;
+    std::unique_lock<std::mutex> lk(mu);
+    WorkerState& me = states.at(&ctx);
+    MERA_HIP(hipEventRecord(me.ready, ctx.stream));
+    if (grouping) {
+      auto it = open.find(key);
+      if (it != open.end() && (int)it->second->reqs.size() < kGettMaxGroup) {
+        it->second->reqs.push_back(&req);
+        me.waiting = true;
+        cv.notify_all();
+        cv.wait(lk, [&] { return req.done; });
+        me.waiting = false;
+        if (req.status) throw Error((mera_status)req.status, req.err);
+        return;
+      }
+    }
+    Batch b;
+    b.reqs.push_back(&req);
+    const bool opened = grouping && !open.count(key);
+    if (opened) open[key] = &b;
+    me.waiting = true;
+    cv.notify_all();
+    if (opened) {
+      const auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(max_wait);
+      cv.wait_until(lk, deadline,
+                    [&] { return (int)b.reqs.size() >= kGettMaxGroup || !others_coming(&ctx, b); });
+      open.erase(key);
+    }
+    stats.batches += 1;
+    stats.bindings += (int64_t)b.reqs.size();
+    if (b.reqs.size() > 1) stats.grouped_batches += 1;
+    lk.unlock();
+
+    int status = 0;
+    std::string err;
+    try {
+      execute(ctx, prog, dims, b.reqs, prec, chunk, key);
+    } catch (const Error& e) {
+      status = e.status;
+      err = e.what();
+    } catch (const std::exception& e) {
+      status = MERA_EINVAL;
+      err = e.what();
+    } catch (...) {
+      status = MERA_EINVAL;
+      err = "unknown error in grouped run";
+    }
+    lk.lock();
+    for (Request* r : b.reqs)
+      if (r != &req) {
+        r->status = status;
+        r->err = err;
+        r->done = true;
+      }
+    me.waiting = false;
+    lk.unlock();
+    cv.notify_all();
+    if (status) throw Error((mera_status)status, err);
+  }
+
+  void execute(Ctx& lead, const Program& prog, const LegDims& dims, const std::vector<Request*>& reqs, Prec prec,
+               int64_t chunk, const std::string& key) {
+    std::vector<Binding> group;
+    for (Request* r : reqs) group.push_back(Binding{r->ctx, *r->ext});
+    for (Request* r : reqs)
+      if (r->ctx != &lead) MERA_HIP(hipStreamWaitEvent(lead.stream, states_at(r->ctx).ready, 0));
+    if (graphs && !lead.profiling) {
+      std::vector<const void*> touched;
+      const double macs = run_group(lead, prog, dims, group, prec, chunk, true, &touched);
+      std::string gk = key;
+      char hex[24];
+      for (const void* p : touched) {
+        std::snprintf(hex, sizeof hex, "|%llx", (unsigned long long)(uintptr_t)p);
+        gk += hex;
+      }
+      GraphEntry* ge = nullptr;
+      {
+        std::lock_guard<std::mutex> g(gmu);
+        auto it = graph_cache.find(gk);
+        if (it != graph_cache.end()) ge = &it->second;
+        else if (graph_cache.size() < kMaxGraphs) ge = &graph_cache[gk];
+      }
+      if (ge && ge->exec) {
+        MERA_HIP(hipGraphLaunch(ge->exec, lead.stream));
+        for (const Binding& b : group) b.ctx->macs += macs;
+        stats_add(&mera_server_stats::graph_launches);
+      } else if (ge && ge->seen >= 1) {
+        // second sight of the same program on the same buffers: capture it once, replay it from now on
+        hipGraph_t graph = nullptr;
+        MERA_HIP(hipStreamBeginCapture(lead.stream, hipStreamCaptureModeThreadLocal));
+        try {
+          run_group(lead, prog, dims, group, prec, chunk, false, nullptr);
+        } catch (...) {
+          (void)hipStreamEndCapture(lead.stream, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          throw;
+        }
+        MERA_HIP(hipStreamEndCapture(lead.stream, &graph));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ie = hipGraphInstantiateWithFlags(&exec, graph, 0);
+        (void)hipGraphDestroy(graph);
+        MERA_HIP(ie);
+        ge->exec = exec;
+        MERA_HIP(hipGraphLaunch(exec, lead.stream));
+        stats_add(&mera_server_stats::graph_captures);
+      } else {
+        if (ge) ge->seen += 1;
+        run_group(lead, prog, dims, group, prec, chunk, false, nullptr);
+        stats_add(&mera_server_stats::eager_runs);
+      }
+    } else {
+      run_group(lead, prog, dims, group, prec, chunk, false, nullptr);
+      stats_add(&mera_server_stats::eager_runs);
+    }
+    const hipEvent_t done = states_at(&lead).done;
+    MERA_HIP(hipEventRecord(done, lead.stream));
+    for (Request* r : reqs)
+      if (r->ctx != &lead) MERA_HIP(hipStreamWaitEvent(r->ctx->stream, done, 0));
+  }
+
+  WorkerState& states_at(const Ctx* c) {
+    std::lock_guard<std::mutex> lk(mu);
+    return states.at(c);
+  }
+  void stats_add(int64_t mera_server_stats::*field) {
+    std::lock_guard<std::mutex> lk(mu);
+    stats.*field += 1;
+  }
+};
+
 struct Server {
   int device = 0;
   size_t budget = 0;
@@ -59,6 +285,9 @@ struct Server {
   size_t in_use = 0;
   uint64_t next_id = 1;
   bool stop = false;
+  bool started = false;  // a job has been submitted (configuration is frozen)
+  GroupBatcher batcher;
+  std::shared_ptr<PlanCache> plans = std::make_shared<PlanCache>();
   std::vector<std::thread> workers;
 
   void worker() {
@@ -66,8 +295,13 @@ struct Server {
     ctx.device = device;
     (void)hipSetDevice(device);
     hipStream_t st = nullptr;
-    if (hipStreamCreate(&st) != hipSuccess) st = nullptr;
+    // non-blocking: no implicit ordering with the legacy null stream, so stream capture on one worker cannot be
+    // invalidated by another thread's null-stream work
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
     ctx.stream = st;
+    ctx.plans = plans;
+    ctx.batcher = &batcher;
+    batcher.attach(ctx);
     for (;;) {
       uint64_t id = 0;
       JobSpec spec;
@@ -90,6 +324,8 @@ struct Server {
       mera_result res{};
       int err = 0;
       const auto t0 = std::chrono::steady_clock::now();
+      batcher.set_shape(ctx, std::to_string(spec.shape.T) + "/" + std::to_string(spec.shape.d) + "/" +
+                                 std::to_string(spec.shape.chi) + "/" + std::to_string((int)spec.prec));
       try {
         OptResult r = optimize(ctx, spec, nullptr, 0);
         res.energy = r.energy;
@@ -115,8 +351,8 @@ struct Server {
         ctx.sync();
       } catch (...) {
       }
+      batcher.set_shape(ctx, "");
       ctx.scratch.clear();
-      ctx.plans->map.clear();
       {
         std::lock_guard<std::mutex> lk(mu);
         Entry& e = jobs[id];
@@ -166,6 +402,23 @@ mera_status mera_server_create(mera_ctx* ctx, size_t hbm_budget, int max_slots, 
   }
 }
 
+mera_status mera_server_configure(mera_server* srv, int group_launches, int graph_capture, double max_wait_us) {
+  if (!srv || max_wait_us < 0) return MERA_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->s.mu);
+  if (srv->s.started) return MERA_EBUSY;
+  srv->s.batcher.grouping = group_launches != 0;
+  srv->s.batcher.graphs = graph_capture != 0;
+  srv->s.batcher.max_wait = max_wait_us * 1e-6;
+  return MERA_OK;
+}
+
+mera_status mera_server_get_stats(mera_server* srv, mera_server_stats* out) {
+  if (!srv || !out) return MERA_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->s.batcher.mu);
+  *out = srv->s.batcher.stats;
+  return MERA_OK;
+}
+
 mera_status mera_server_submit(mera_server* srv, const mera_job* job, uint64_t* job_id) {
   if (!srv || !job || !job_id) return MERA_EINVAL;
   try {
@@ -174,6 +427,7 @@ mera_status mera_server_submit(mera_server* srv, const mera_job* job, uint64_t* 
     if (fp > srv->s.budget) return MERA_ENOMEM;
     {
       std::lock_guard<std::mutex> lk(srv->s.mu);
+      srv->s.started = true;
       const uint64_t id = srv->s.next_id++;
       auto& e = srv->s.jobs[id];
       e.spec = std::move(spec);

@@ -387,7 +387,9 @@ int jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol
       ring[1] = last;
     }
     s->pairs.alloc(host.size() * sizeof(int));
-    MERA_HIP(hipMemcpy(s->pairs.ptr, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice));
+    MERA_HIP(hipMemcpyAsync(s->pairs.ptr, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice,
+                            ctx.stream));
+    MERA_HIP(hipStreamSynchronize(ctx.stream));
     it = scheds.emplace(key, std::move(s)).first;
   }
   JacobiSchedule& s = *it->second;

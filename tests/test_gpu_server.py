@@ -45,24 +45,54 @@ def _wait(srv, ids, timeout=300):
     return [res[i] for i in ids]
 
 
-def test_alone_equals_mix(ctx):
+def _run_all(ctx, jobs, slots, **opts):
     from paper_2007_03638_amd import api
+    srv = api.Server(ctx, hbm_budget=64 << 30, max_slots=slots, **opts)
+    ids = [srv.submit(**j) for j in jobs]
+    res = _wait(srv, ids)
+    st = srv.stats()
+    srv.close()
+    return res, st
+
+
+def test_alone_equals_mix(ctx):
+    """Each job alone (one slot, every kernel launched eagerly on its own stream) gives bit-identical results
+    to the same job in a mix of four (grouped MFMA launches across same-shape jobs, graph replays)."""
     jobs = _jobs()
     alone = []
     for j in jobs:
-        srv = api.Server(ctx, hbm_budget=64 << 30, max_slots=1)
-        alone += _wait(srv, [srv.submit(**j)])
-        srv.close()
-    srv = api.Server(ctx, hbm_budget=64 << 30, max_slots=4)
-    ids = [srv.submit(**j) for j in jobs]
-    mixed = _wait(srv, ids)
-    srv.close()
+        r, st = _run_all(ctx, [j], 1, group_launches=False, graph_capture=False)
+        assert st["grouped_batches"] == 0 and st["graph_launches"] == 0
+        alone += r
+    mixed, st = _run_all(ctx, jobs, 4)
+    print("mix stats", st, flush=True)
     for a, b in zip(alone, mixed):
         print(a["energy"], b["energy"], a["iterations"], b["iterations"], flush=True)
         assert a["status"] == b["status"] == 1
         assert a["energy"] == b["energy"]
         assert a["gnorm"] == b["gnorm"]
         assert a["evaluations"] == b["evaluations"]
+    # the mix did batch: same-shape jobs shared launches, and repeated programs ran from captured graphs
+    assert st["grouped_batches"] > 0
+    assert st["graph_captures"] > 0 and st["graph_launches"] > st["graph_captures"]
+    assert st["bindings"] > st["batches"]
+
+
+def test_grouping_and_graphs_separately(ctx):
+    """Grouped launches without graphs, and graphs without grouping, each reproduce the eager results."""
+    jobs = _jobs()[:2] + _jobs()[:2]       # two pairs of identical jobs
+    ref, _ = _run_all(ctx, jobs[:2], 1, group_launches=False, graph_capture=False)
+    for opts in (dict(group_launches=True, graph_capture=False), dict(group_launches=False, graph_capture=True)):
+        res, st = _run_all(ctx, jobs, 4, **opts)
+        print(opts, st, flush=True)
+        for k, r in enumerate(res):
+            assert r["energy"] == ref[k % 2]["energy"]
+            assert r["gnorm"] == ref[k % 2]["gnorm"]
+            assert r["evaluations"] == ref[k % 2]["evaluations"]
+        if opts["group_launches"]:
+            assert st["grouped_batches"] > 0 and st["graph_launches"] == 0
+        else:
+            assert st["grouped_batches"] == 0 and st["graph_launches"] > 0
 
 
 def test_admission_budget(ctx):
