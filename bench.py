@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--jobs", type=int, default=16)
     ap.add_argument("--serve-iters", type=int, default=30)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--no-group", action="store_true", help="serving: no grouped launches across jobs")
+    ap.add_argument("--no-graphs", action="store_true", help="serving: no HIP graph replay")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference dispatch for hardware byte counters)")
     return ap.parse_args()
@@ -172,7 +175,8 @@ def run_serve_bench(a):
     from paper_2007_03638_amd import api, inputs
     rng = np.random.default_rng(3)
     ctx = api.Context(0)
-    srv = api.Server(ctx, hbm_budget=200 << 30, max_slots=8)
+    srv = api.Server(ctx, hbm_budget=200 << 30, max_slots=a.slots, group_launches=not a.no_group,
+                     graph_capture=not a.no_graphs)
     jobs = []
     t_arr = 0.0
     for k in range(a.jobs):
@@ -207,6 +211,7 @@ def run_serve_bench(a):
                           file=sys.stderr, flush=True)
         time.sleep(0.005)
     makespan = time.perf_counter() - t0
+    stats = srv.stats()
     srv.close()
     lat = np.array([results[i][1]["queued_seconds"] + results[i][1]["seconds"] for i in ids])
     conv = sum(1 for i in ids if results[i][1]["status"] == 0)
@@ -223,14 +228,16 @@ def run_serve_bench(a):
                                f"stop at |G|<=1e-7 or {a.serve_iters} iterations"},
         "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
         "jobs_per_s": a.jobs / makespan, "converged": conv, "makespan_s": makespan,
+        "slots": a.slots, "grouped_launches": not a.no_group, "graph_replay": not a.no_graphs,
+        "batcher": stats,
     }
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (this build runs on a single "
-              f"MI355X; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported: the library drives a single MI355X "
+              f"and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     out = run_serve_bench(a) if a.serve else run_eval_bench(a)
     print(json.dumps(out), flush=True)

@@ -136,8 +136,24 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t ntiles) {
   return (b < full * 8) ? (b % 8) * full + b / 8 : b;
 }
 
+// Origin of logical tile `tile`. Consecutive tiles run along the dimension with fewer tiles, so they share a
+// panel of the operand with more tiles (the larger one), which is then read from HBM about once.
+template <int BM, int BN>
+__device__ inline void tile_origin(int64_t tile, int64_t M, int64_t N, int64_t& m0, int64_t& n0) {
+  const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+  if (tm >= tn) {
+    m0 = (tile / tn) * BM;
+    n0 = (tile % tn) * BN;
+  } else {
+    m0 = (tile % tm) * BM;
+    n0 = (tile / tm) * BN;
+  }
+}
+
 template <typename T, int BM, int BN, int BK, bool AKF, bool BKF>
-__global__ void __launch_bounds__(256) gett_kernel(Args g) {
+// At most 256 registers per lane (2 waves per SIMD) for every tile; the register allocator then keeps the
+// accumulators in VGPRs and the 128 x 128 FP32 and 128 x 64 FP64 tiles reach 3 waves per SIMD.
+__global__ void __launch_bounds__(256, 2) gett_kernel(Args g) {
   using F = Mma<T>;
   constexpr int PAD = sizeof(T) == 4 ? 2 : 1;
   constexpr int LDA = BM + PAD, LDB = BN + PAD;
@@ -153,10 +169,8 @@ __global__ void __launch_bounds__(256) gett_kernel(Args g) {
   const int wm = (wave >> 1) * WM;
   const int wn = (wave & 1) * WN;
 
-  const int64_t tiles_n = (g.N + BN - 1) / BN;
-  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int64_t m0 = (tile / tiles_n) * BM;
-  const int64_t n0 = (tile % tiles_n) * BN;
+  int64_t m0, n0;
+  tile_origin<BM, BN>(xcd_tile(blockIdx.x, gridDim.x), g.M, g.N, m0, n0);
   const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
   const int64_t ke = (g.K < kb + g.kchunk) ? g.K : kb + g.kchunk;
 
@@ -304,10 +318,8 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
   const int wave = tid >> 6;
   const int wm = (wave >> 1) * WM;
   const int wn = (wave & 1) * WN;
-  const int64_t tiles_n = (g.N + BN - 1) / BN;
-  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int64_t m0 = (tile / tiles_n) * BM;
-  const int64_t n0 = (tile % tiles_n) * BN;
+  int64_t m0, n0;
+  tile_origin<BM, BN>(xcd_tile(blockIdx.x, gridDim.x), g.M, g.N, m0, n0);
   const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
   const int64_t ke = (g.K < kb + g.kchunk) ? g.K : kb + g.kchunk;
   const int grp = blockIdx.y;
@@ -474,6 +486,32 @@ void launch_bf16x3(const Args& a, int groups, int splits, hipStream_t s, bool ak
   else hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, false, false>), grid, block, 0, s, a);
 }
 
+struct Tile {
+  int bm, bn;
+};
+
+// Tile shape per precision and extents. FP64: 128 x 64 (the 128 x 128 FP64 tile gives no gain at its lower
+// occupancy). FP32: among 128 x 128, 128 x 192 and 192 x 128 the one with the least padding, ties to the larger
+// tile (higher arithmetic intensity); chi^2 = 576 and chi^4 extents at chi = 24 are multiples of 192 but not of
+// 128. BF16X3: at most 128 x 128. 64-wide tiles for extents below 128.
+Tile choose_tile(Prec p, int64_t M, int64_t N) {
+  const bool bigm = M >= 128, bign = N >= 128;
+  if (p == Prec::F64) return Tile{bigm ? 128 : 64, 64};
+  if (p == Prec::BF16X3 || !bigm || !bign) return Tile{bigm ? 128 : 64, bign ? 128 : 64};
+  const Tile cand[3] = {{128, 192}, {192, 128}, {128, 128}};
+  Tile best = cand[2];
+  double best_pad = 1e300;
+  for (const Tile& c : cand) {
+    if (M < c.bm || N < c.bn) continue;
+    const double pad = (double)((M + c.bm - 1) / c.bm * c.bm) * (double)((N + c.bn - 1) / c.bn * c.bn);
+    if (pad < best_pad * (1 - 1e-12)) {
+      best = c;
+      best_pad = pad;
+    }
+  }
+  return best;
+}
+
 }  // namespace
 
 void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
@@ -499,10 +537,8 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
   a.beta = l.beta;
   a.split = 0;
 
-  // tile shape: large tiles when both extents allow, otherwise 64-wide. FP64 uses at most 128 x 64: the 128 x 128
-  // FP64 tile needs more than 256 registers per lane, leaving one wave per SIMD.
-  const bool bigm = t.M >= 128, bign = t.N >= 128 && l.prec != Prec::F64;
-  const int BMsel = bigm ? 128 : 64, BNsel = bign ? 128 : 64;
+  const Tile tile = choose_tile(l.prec, t.M, t.N);
+  const int BMsel = tile.bm, BNsel = tile.bn;
   const int64_t tiles = ((t.M + BMsel - 1) / BMsel) * ((t.N + BNsel - 1) / BNsel);
   const int BK = 32;  // k-chunks stay multiples of every tile depth in use
 
@@ -538,19 +574,27 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
     rec.stop = ctx.take_event();
     MERA_HIP(hipEventRecord(rec.start, s));
   }
+  const int sel = BMsel * 1000 + BNsel;
+  const bool akf = t.a_kfast, bkf = t.b_kfast;
   if (l.prec == Prec::F64) {
-    if (bigm) launch_tile<double, 128, 64, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
-    else launch_tile<double, 64, 64, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
+    if (sel == 128064) launch_tile<double, 128, 64, 16>(a, G, splits, s, akf, bkf);
+    else launch_tile<double, 64, 64, 16>(a, G, splits, s, akf, bkf);
   } else if (l.prec == Prec::F32) {
-    if (bigm && bign) launch_tile<float, 128, 128, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
-    else if (bigm) launch_tile<float, 128, 64, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
-    else if (bign) launch_tile<float, 64, 128, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
-    else launch_tile<float, 64, 64, 16>(a, G, splits, s, t.a_kfast, t.b_kfast);
+    switch (sel) {
+      case 128192: launch_tile<float, 128, 192, 16>(a, G, splits, s, akf, bkf); break;
+      case 192128: launch_tile<float, 192, 128, 16>(a, G, splits, s, akf, bkf); break;
+      case 128128: launch_tile<float, 128, 128, 16>(a, G, splits, s, akf, bkf); break;
+      case 128064: launch_tile<float, 128, 64, 16>(a, G, splits, s, akf, bkf); break;
+      case 64128: launch_tile<float, 64, 128, 16>(a, G, splits, s, akf, bkf); break;
+      default: launch_tile<float, 64, 64, 16>(a, G, splits, s, akf, bkf); break;
+    }
   } else {
-    if (bigm && bign) launch_bf16x3<128, 128, 32>(a, G, splits, s, t.a_kfast, t.b_kfast);
-    else if (bigm) launch_bf16x3<128, 64, 32>(a, G, splits, s, t.a_kfast, t.b_kfast);
-    else if (bign) launch_bf16x3<64, 128, 32>(a, G, splits, s, t.a_kfast, t.b_kfast);
-    else launch_bf16x3<64, 64, 32>(a, G, splits, s, t.a_kfast, t.b_kfast);
+    switch (sel) {
+      case 128128: launch_bf16x3<128, 128, 32>(a, G, splits, s, akf, bkf); break;
+      case 128064: launch_bf16x3<128, 64, 32>(a, G, splits, s, akf, bkf); break;
+      case 64128: launch_bf16x3<64, 128, 32>(a, G, splits, s, akf, bkf); break;
+      default: launch_bf16x3<64, 64, 32>(a, G, splits, s, akf, bkf); break;
+    }
   }
   MERA_HIP(hipGetLastError());
   if (ctx.profiling) {

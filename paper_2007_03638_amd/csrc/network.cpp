@@ -176,15 +176,22 @@ PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegD
   if (it != ctx.plans->map.end()) return *it->second;
 
   auto has = [](const std::string& s_, char c) { return s_.find(c) != std::string::npos; };
+  // The kernels' lanes run along N when they store C. When C's unit-stride leg comes from A (an M leg), the
+  // roles of A and B are exchanged (C^T = B^T A^T) so that the stores stay coalesced.
+  const bool swap = has(s.la, s.lc.back());
+  const std::string& LA = swap ? s.lb : s.la;
+  const std::string& LB = swap ? s.la : s.lb;
+  const LegDims& DA = swap ? *sdims[1] : *sdims[0];
+  const LegDims& DB = swap ? *sdims[0] : *sdims[1];
   std::string Ml, Nl, Kl;
-  for (char c : s.la) {
-    bool inb = has(s.lb, c), inc = has(s.lc, c);
+  for (char c : LA) {
+    bool inb = has(LB, c), inc = has(s.lc, c);
     if (inc && !inb) Ml += c;
     else if (inb && !inc) Kl += c;
     else throw Error(MERA_EINVAL, prog.name + ": leg '" + std::string(1, c) + "' of A is batch or traced");
   }
-  for (char c : s.lb) {
-    bool ina = has(s.la, c), inc = has(s.lc, c);
+  for (char c : LB) {
+    bool ina = has(LA, c), inc = has(s.lc, c);
     if (inc && !ina) Nl += c;
     else if (!(ina && !inc)) throw Error(MERA_EINVAL, prog.name + ": leg of B is batch or traced");
   }
@@ -194,12 +201,12 @@ PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegD
   for (char c : all)
     if (dims[(unsigned char)c] <= 0) throw Error(MERA_EINVAL, prog.name + ": unset leg extent");
 
-  const bool a_kfast = !Kl.empty() && has(Kl, s.la.back());
-  const bool b_kfast = !Kl.empty() && has(Kl, s.lb.back());
+  const bool a_kfast = !Kl.empty() && has(Kl, LA.back());
+  const bool b_kfast = !Kl.empty() && has(Kl, LB.back());
   if (!a_kfast && b_kfast) {
     // order K legs as B stores them so B's unit-stride leg is fastest in k
     std::string k2;
-    for (char c : s.lb)
+    for (char c : LB)
       if (has(Kl, c)) k2 += c;
     Kl = k2;
   }
@@ -210,15 +217,15 @@ PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegD
   };
   const int64_t M = ext(Ml), N = ext(Nl), K = ext(Kl);
   const int64_t Mp = roundup(M, 128), Np = roundup(N, 128), Kp = roundup(K, 32);
-  auto sa = strides_of(s.la, *sdims[0]), sb = strides_of(s.lb, *sdims[1]), sc = strides_of(s.lc, *sdims[2]);
+  auto sa = strides_of(LA, DA), sb = strides_of(LB, DB), sc = strides_of(s.lc, *sdims[2]);
   std::vector<int64_t> host;
   host.reserve(2 * Mp + 2 * Np + 2 * Kp);
   std::vector<int64_t> tmp;
   size_t off_am, off_ak, off_bk, off_bn, off_cm, off_cn;
-  off_am = host.size(); fill_table(tmp, Ml, dims, s.la, sa, Mp); host.insert(host.end(), tmp.begin(), tmp.end());
-  off_ak = host.size(); fill_table(tmp, Kl, dims, s.la, sa, Kp); host.insert(host.end(), tmp.begin(), tmp.end());
-  off_bk = host.size(); fill_table(tmp, Kl, dims, s.lb, sb, Kp); host.insert(host.end(), tmp.begin(), tmp.end());
-  off_bn = host.size(); fill_table(tmp, Nl, dims, s.lb, sb, Np); host.insert(host.end(), tmp.begin(), tmp.end());
+  off_am = host.size(); fill_table(tmp, Ml, dims, LA, sa, Mp); host.insert(host.end(), tmp.begin(), tmp.end());
+  off_ak = host.size(); fill_table(tmp, Kl, dims, LA, sa, Kp); host.insert(host.end(), tmp.begin(), tmp.end());
+  off_bk = host.size(); fill_table(tmp, Kl, dims, LB, sb, Kp); host.insert(host.end(), tmp.begin(), tmp.end());
+  off_bn = host.size(); fill_table(tmp, Nl, dims, LB, sb, Np); host.insert(host.end(), tmp.begin(), tmp.end());
   off_cm = host.size(); fill_table(tmp, Ml, dims, s.lc, sc, Mp); host.insert(host.end(), tmp.begin(), tmp.end());
   off_cn = host.size(); fill_table(tmp, Nl, dims, s.lc, sc, Np); host.insert(host.end(), tmp.begin(), tmp.end());
 
@@ -241,6 +248,7 @@ PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegD
   e->t.a_kfast = a_kfast;
   e->t.b_kfast = b_kfast;
   e->macs = (double)M * (double)N * (double)K;
+  e->swap = swap;
   auto& ref = *e;
   ctx.plans->map.emplace(key, std::move(e));
   return ref;
@@ -302,9 +310,10 @@ double run_group(Ctx& lead, const Program& prog, const LegDims& dims, const std:
     PlanCache::Entry& e = plan_step(lead, prog, si, idims, sd);
     GettLaunch l;
     l.groups = G;
+    const int oa = e.swap ? 1 : 0, ob = 1 - oa;  // operand roles (exchanged for an m-fast C)
     for (int g = 0; g < G; ++g) {
-      l.A[g] = static_cast<char*>(ptr[g * nt + ids[0]]) + shift[0];
-      l.B[g] = static_cast<char*>(ptr[g * nt + ids[1]]) + shift[1];
+      l.A[g] = static_cast<char*>(ptr[g * nt + ids[oa]]) + shift[oa];
+      l.B[g] = static_cast<char*>(ptr[g * nt + ids[ob]]) + shift[ob];
       l.C[g] = static_cast<char*>(ptr[g * nt + ids[2]]) + shift[2];
     }
     l.alpha = s.alpha;

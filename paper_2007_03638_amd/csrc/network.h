@@ -61,6 +61,7 @@ struct PlanCache {
     DevBuf tables;
     GettTables t;
     double macs = 0;
+    bool swap = false;  // tables built for C^T = B^T A^T: the step's B is the kernel's A operand
   };
   std::unordered_map<std::string, std::unique_ptr<Entry>> map;
 };
