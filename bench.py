@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=2,
+                    help="optimiser iterations of the plain FP64 form timed for comparison (0: skip)")
+    ap.add_argument("--fp64-warmup", type=int, default=1)
     ap.add_argument("--cpu-sample-chi", type=int, default=14)
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--jobs", type=int, default=16)
@@ -85,13 +88,39 @@ def counter_traffic(kernel_variant):
     import hashlib
     path = os.path.join(ROOT, "profiles", "gett_f32_chi24_counters.md")
     src = os.path.join(ROOT, "paper_2007_03638_amd", "csrc", "gett.hip")
-    if not os.path.exists(path) or kernel_variant != "gett<f32,128x128,Am,Bn>":
+    if not os.path.exists(path):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     fields = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith("|"))
     if fields.get("gett_source_sha256_prefix", "").strip() != sha:
         return None
+    if fields.get("kernel_variant", "").strip() != kernel_variant:
+        return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+def fp64_rate(a):
+    """Evaluations/s of the plain FP64 form on the same workload (same seed and start point)."""
+    import torch
+    from paper_2007_03638_amd import api, inputs
+    ctx = api.Context(0)
+    dims = api.layer_dims(a.T, a.chi)
+    init = [m for pair in inputs.mera_init(a.seed, dims) for m in pair]
+    opt = ctx.optimizer(T=a.T, chi=a.chi, h3=api.h3_tfim(1.0), init=init, prec="fp64", m=8, max_iter=10 ** 6,
+                        grad_tol=0.0, polish_tol=0.0, precondition=True, max_ls_evals=10)
+    state = None
+    for _ in range(a.fp64_warmup):
+        _, state = opt.step()
+    s0 = state if state is not None else {"evaluations": 1}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.fp64_steps):
+        _, state = opt.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    evals = state["evaluations"] - s0["evaluations"]
+    print(f"[bench] fp64 form: {evals} evaluations in {dt:.1f} s", file=sys.stderr, flush=True)
+    return evals / dt
 
 
 def run_eval_bench(a):
@@ -111,16 +140,20 @@ def run_eval_bench(a):
     opt = ctx.optimizer(T=a.T, chi=a.chi, h3=h3, init=init, prec=a.prec, m=8, max_iter=10 ** 6, grad_tol=0.0,
                         polish_tol=0.0, precondition=True, max_ls_evals=10)
     state = None
-    for _ in range(a.warmup):
+    for i in range(a.warmup):
         _, state = opt.step()
+        print(f"[bench] warmup step {i + 1}/{a.warmup}: e={state['energy']:.12f} |G|={state['gnorm']:.3e}",
+              file=sys.stderr, flush=True)
     # state after the untimed part (with no warmup: the initial evaluation done at creation)
     s0 = state if state is not None else {"evaluations": 1, "macs": ctx.macs(), "krylov_applications": 0}
     ctx.profile(True)
     ctx.kernel_stats()  # clear
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for i in range(a.steps):
         _, state = opt.step()
+        print(f"[bench] step {i + 1}/{a.steps}: e={state['energy']:.12f} |G|={state['gnorm']:.3e} "
+              f"evaluations={state['evaluations']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = ctx.kernel_stats()
@@ -163,6 +196,10 @@ def run_eval_bench(a):
         "kernels": [{"kernel": s["kernel"], "launches": s["launches"], "ms": 1000.0 * s["seconds"],
                      "tflops": s["flops"] / s["seconds"] / 1e12} for s in stats[:6]],
     }
+    if a.fp64_steps > 0 and a.prec != "fp64":
+        r64 = fp64_rate(a)
+        out["fp64_form_evals_per_s"] = r64
+        out["speedup_vs_fp64_form"] = out["value"] / r64
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_sample_chi, flops / max(evals, 1))
     return out
