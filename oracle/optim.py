@@ -12,6 +12,12 @@ Sec. 3 of the paper. Readings where the paper leaves details open (constants are
     Hessian gamma * P with P the preconditioner and gamma = <s, y> / <y, P y> from the newest pair;
     s_k = T(alpha d_k), y_k = G_{k+1} - T(G_k); a pair with <s, y> <= 1e-12 |s| |y| is not stored; if the
     direction is not a descent direction the history is dropped and d = -P(G).
+  * Nonlinear conjugate gradient (Sec. 3, with the Hager-Zhang coefficient the paper uses): d_{k+1} = -P G_{k+1}
+    + beta_k T(d_k), inner products in the metric, the previous direction carried over by the transport; beta_k in
+    the preconditioned Hager-Zhang form <y, P g>/<d, y> - 2 <y, P y> <d, g>/<d, y>^2 (y = G_{k+1} - T(G_k), d the
+    transported previous direction), truncated below at -1/(|d| min(0.01, |G_k|)) as Hager and Zhang do. A
+    non-descent direction restarts from -P G. First trial step: 1 after a (re)start, otherwise
+    alpha_{k-1} <G_{k-1}, d_{k-1}> / <G_k, d_k> (the usual scaling for methods without a natural step length).
 """
 import math
 import numpy as np
@@ -173,6 +179,84 @@ def optimize(W0, problem, m=8, max_iter=200, grad_tol=1e-10, use_precond=True, l
         y = [gn - mf.transport(w, g) for w, gn, g in zip(Wn, Gn, G)]
         hist.transport(Wn)
         hist.push(s, y)
+        W, f, G, rv = Wn, fn, Gn, rvn
+    else:
+        it = max_iter
+    gnorm = math.sqrt(mf.inner(G, G))
+    return W, f, gnorm, dict(iterations=it, evals=problem.evals, status=status)
+
+
+def hz_beta(g, pg, y, py, d, g_old_norm, eta=0.01, truncate=True):
+    """Hager-Zhang conjugate-gradient coefficient with a preconditioner P (pg = P g, py = P y):
+    <y, P g>/<d, y> - 2 <y, P y> <d, g>/<d, y>^2, optionally truncated below at -1/(|d| min(eta, |g_old|)).
+    Returns 0 when <d, y> vanishes."""
+    dy = mf.inner(d, y)
+    if dy == 0.0 or not math.isfinite(dy):
+        return 0.0
+    beta = mf.inner(y, pg) / dy - 2.0 * mf.inner(y, py) * mf.inner(d, g) / (dy * dy)
+    if truncate:
+        dn = math.sqrt(mf.inner(d, d))
+        if dn > 0.0 and g_old_norm > 0.0:
+            beta = max(beta, -1.0 / (dn * min(eta, g_old_norm)))
+    return beta
+
+
+def optimize_cg(W0, problem, max_iter=200, grad_tol=1e-10, use_precond=True, ls_max_evals=10, log=None):
+    """Riemannian nonlinear conjugate gradient (Sec. 3, Hager-Zhang coefficient) on the flattened parameter list W0.
+    Returns (W, energy, |G|, info)."""
+    W = [w.copy() for w in W0]
+    f, G, rv = problem.evaluate(W)
+    d_prev = None          # previous direction, transported to the current point
+    y = None               # G_k - T(G_{k-1})
+    g_old_norm = None
+    alpha_prev = slope_prev = None
+    it = 0
+    status = 'maxiter'
+    for it in range(max_iter):
+        gnorm = math.sqrt(mf.inner(G, G))
+        if log is not None:
+            log.append(dict(iter=it, energy=f, gnorm=gnorm, evals=problem.evals))
+        if gnorm <= grad_tol:
+            status = 'converged'
+            break
+
+        def P(X, _W=W, _rv=rv):
+            if not use_precond:
+                return [x.copy() for x in X]
+            return [mf.precondition(w, x, r) for w, x, r in zip(_W, X, _rv)]
+        pg = P(G)
+        d = _scale(-1.0, pg)
+        momentum = False
+        if d_prev is not None:
+            beta = hz_beta(G, pg, y, P(y), d_prev, g_old_norm)
+            d = _axpy(beta, d_prev, d)
+            momentum = True
+        slope = mf.inner(G, d)
+        if not slope < 0.0:
+            d = _scale(-1.0, pg)
+            slope = mf.inner(G, d)
+            momentum = False
+        alpha0 = alpha_prev * slope_prev / slope if (momentum and alpha_prev is not None) else 1.0
+
+        def phi(alpha, _W=W, _d=d):
+            pairs = [mf.retract(w, x, alpha) for w, x in zip(_W, _d)]
+            Wn = [p[0] for p in pairs]
+            Xp = [p[1] for p in pairs]
+            fn, Gn, rvn = problem.evaluate(Wn)
+            return fn, mf.inner(Gn, Xp), (Wn, Gn, rvn)
+        ok, alpha, fn, dfn, payload, _ = line_search(phi, f, slope, alpha0=alpha0, max_evals=ls_max_evals)
+        if not ok and momentum:
+            d = _scale(-1.0, pg)
+            slope = mf.inner(G, d)
+            ok, alpha, fn, dfn, payload, _ = line_search(phi, f, slope, alpha0=1.0, max_evals=ls_max_evals)
+        if not ok:
+            status = 'linesearch_failed'
+            break
+        Wn, Gn, rvn = payload
+        d_prev = [mf.transport(w, x) for w, x in zip(Wn, d)]
+        y = [gn - mf.transport(w, g) for w, gn, g in zip(Wn, Gn, G)]
+        g_old_norm = gnorm
+        alpha_prev, slope_prev = alpha, slope
         W, f, G, rv = Wn, fn, Gn, rvn
     else:
         it = max_iter

@@ -91,3 +91,77 @@ def test_optimizer_small_run_decreases_energy_above_bound():
     assert log[-1]['gnorm'] < log[0]['gnorm']
     for w in W:
         assert np.max(np.abs(w.T @ w - np.eye(w.shape[1]))) < 1e-13
+
+
+def _pcg_with_hz(A, b, M, n_steps):
+    """Nonlinear CG with the oracle's Hager-Zhang coefficient and exact line searches on the quadratic
+    f(x) = x^T A x / 2 - b^T x (Euclidean, identity transport), preconditioner M."""
+    x = np.zeros(len(b))
+    g = A @ x - b
+    d = -(M @ g)
+    grads = [np.linalg.norm(g)]
+    for _ in range(n_steps):
+        alpha = -(g @ d) / (d @ A @ d)
+        x = x + alpha * d
+        g_new = A @ x - b
+        y = g_new - g
+        beta = optim.hz_beta([g_new], [M @ g_new], [y], [M @ y], [d], np.linalg.norm(g))
+        d = -(M @ g_new) + beta * d
+        g = g_new
+        grads.append(np.linalg.norm(g))
+    return x, grads
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_hz_cg_terminates_on_quadratic(precond):
+    """With exact line searches <d, g_new> = 0 and the Hager-Zhang coefficient reduces to the Hestenes-Stiefel one,
+    so (preconditioned) nonlinear CG is linear CG: it solves an n-dimensional SPD quadratic in n steps."""
+    rng = np.random.default_rng(5)
+    n = 7
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    A = Q @ np.diag(np.linspace(1.0, 30.0, n)) @ Q.T
+    b = rng.standard_normal(n)
+    if precond:
+        R = rng.standard_normal((n, n))
+        M = R @ R.T / n + 0.5 * np.eye(n)   # an SPD preconditioner unrelated to A
+    else:
+        M = np.eye(n)
+    x, grads = _pcg_with_hz(A, b, M, n)
+    assert np.allclose(x, np.linalg.solve(A, b), atol=1e-9)
+    assert grads[-1] < 1e-9 * grads[0]
+    assert grads[n - 2] > 1e-6 * grads[0]   # not earlier: M A has n distinct eigenvalues
+
+
+def test_hz_beta_sufficient_descent():
+    """Hager-Zhang (2005): with <d, y> != 0 the untruncated coefficient gives <g, -g + beta d> <= -7/8 |g|^2 for
+    any g, d, y."""
+    rng = np.random.default_rng(6)
+    for _ in range(200):
+        g, d, y = (rng.standard_normal(9) for _ in range(3))
+        beta = optim.hz_beta([g], [g], [y], [y], [d], 1.0, truncate=False)
+        assert g @ (-g + beta * d) <= -0.875 * (g @ g) + 1e-12
+
+
+def test_hz_beta_truncation():
+    """The truncated coefficient is max(beta, -1/(|d| min(0.01, |g_old|)))."""
+    rng = np.random.default_rng(7)
+    g, d, y = (rng.standard_normal(5) for _ in range(3))
+    raw = optim.hz_beta([g], [g], [y], [y], [d], 1.0, truncate=False)
+    floor = -1.0 / (np.linalg.norm(d) * 0.01)
+    assert optim.hz_beta([g], [g], [y], [y], [d], 1.0) == max(raw, floor)
+    assert optim.hz_beta([g], [g], [y], [y], [np.zeros(5)], 1.0) == 0.0
+
+
+def test_cg_small_run_decreases_energy_above_bound():
+    chi, T = 4, 2
+    dims = mera.layer_dims(chi, T)
+    W0 = [m for pair in inputs.mera_init(0, dims) for m in pair]
+    prob = optim.Problem(model.tfim_h3(1.0), chi, T)
+    log = []
+    W, f, gnorm, info = optim.optimize_cg(W0, prob, max_iter=12, log=log)
+    energies = [r['energy'] for r in log] + [f]
+    assert all(b <= a + 1e-12 for a, b in zip(energies, energies[1:]))
+    assert f / 2 > model.tfim_exact_energy_per_spin(1.0)
+    assert energies[-1] < energies[0] - 0.1
+    for w in W:
+        assert np.max(np.abs(w.T @ w - np.eye(w.shape[1]))) < 1e-13
