@@ -10,11 +10,16 @@ Sec. 2 of the paper, specialised to real matrices (W^T W = 1):
     factor given in App. A (eqs. polar_perturbation / polar_perturbation_dQ).
   * vector transport: projection of the vector onto the tangent space at the new point (reading; the paper's
     exponential transport belongs to its exponential retraction).
+  * the paper's own pair (Sec. 2.3, eqs. retraction and transport): R_W(X, alpha) = exp(alpha Q_X) W and
+    T(Y) = exp(alpha Q_X) Y with Q_X = [W W_perp] [[A, -B^T], [B, 0]] [W W_perp]^T; W_perp B = Z = (1 - W W^T) X
+    comes from a QR decomposition of [W Z] (the footnote to eq. retraction), so only a (p+r)-dimensional exponential
+    is needed. The Grassmann case is the same with A = 0.
   * Hilbert-space preconditioner (Sec. 3, eqs. preconditioner / preconditioner_solution): X~ = W A~ + W_perp B~
     with A~ rho + rho A~ = 2A and B~ = B rho^{-1}, rho regularised as (rho^2 + delta^2)^{1/2} (Sec. 3), with
     delta = ||X_v|| (Sec. 4).
 """
 import numpy as np
+import scipy.linalg
 
 
 def inner(X, Y):
@@ -75,3 +80,45 @@ def precondition(W, X, rho, delta=None):
     Bpart = X - W @ A
     Bt = Bpart @ (V @ np.diag(1.0 / f) @ V.T)
     return W @ At + Bt
+
+
+def exp_frame(W, X):
+    """Low-rank factors of Q_X (Sec. 2.3, eq. retraction): U = [W Q] with orthonormal columns and the skew matrix
+    M = [[A, -B^T], [B, 0]] with Q_X = U M U^T. A = W^T X; Z = X - W A; Q spans the complement part: the columns
+    p..p+r of the QR factor of [W Z], r = min(p, n - p), and B = Q^T Z."""
+    n, p = W.shape
+    A = W.T @ X
+    r = min(p, n - p)
+    if r == 0:
+        return W.copy(), A.copy()
+    Z = X - W @ A
+    Qf, _ = np.linalg.qr(np.hstack([W, Z]))
+    Q = Qf[:, p:p + r]
+    B = Q.T @ Z
+    M = np.zeros((p + r, p + r))
+    M[:p, :p] = A
+    M[:p, p:] = -B.T
+    M[p:, :p] = B
+    return np.hstack([W, Q]), M
+
+
+def retract_exp(W, X, alpha):
+    """Exponential retraction of eq. retraction, R = exp(alpha Q_X) W = U expm(alpha M)[:, :p], and its curve
+    derivative dR/dalpha = exp(alpha Q_X) Q_X W = exp(alpha Q_X) X (Q_X W = X)."""
+    U, M = exp_frame(W, X)
+    E = scipy.linalg.expm(alpha * M)
+    p = W.shape[1]
+    Wn = U @ E[:, :p]
+    return Wn, transport_exp(W, X, alpha, X)
+
+
+def transport_exp(W, X, alpha, Y):
+    """Vector transport of eq. transport, T(Y) = exp(alpha Q_X) Y = Y + U (expm(alpha M) - 1) U^T Y."""
+    U, M = exp_frame(W, X)
+    E = scipy.linalg.expm(alpha * M)
+    return Y + U @ ((E - np.eye(E.shape[0])) @ (U.T @ Y))
+
+
+def grassmann_project(W, D):
+    """Grassmann tangent projection (Sec. 2.2, eq. grassmann_gradient, real case): G = (1 - W W^T) D."""
+    return D - W @ (W.T @ D)

@@ -1,6 +1,7 @@
 """Pins of the oracle's Stiefel projection, polar retraction, transport and preconditioner."""
 import numpy as np
 import pytest
+import scipy.linalg
 
 from oracle import manifold as mf
 from paper_2007_03638_amd import inputs
@@ -76,3 +77,63 @@ def test_preconditioner_defining_identity(n, p):
     lam, V = np.linalg.eigh(rho)
     rho_reg = V @ np.diag(np.sqrt(lam ** 2 + 0.09)) @ V.T
     assert np.max(np.abs(mf.precondition(W, X, rho_reg, delta=0.0) - Xd)) < 1e-11
+
+
+def _full_q(W, X):
+    """Q_X of eq. retraction built in full (n x n) from an explicit orthonormal complement W_perp."""
+    Wp = scipy.linalg.null_space(W.T)
+    A = W.T @ X
+    B = Wp.T @ X
+    Ub = np.hstack([W, Wp])
+    Mb = np.block([[A, -B.T], [B, np.zeros((B.shape[0], B.shape[0]))]])
+    return Ub @ Mb @ Ub.T
+
+
+@pytest.mark.parametrize("n,p", [(12, 5), (9, 6), (7, 7), (16, 4)])
+def test_exp_retraction_and_transport_equal_full_exponential(n, p):
+    """Brute force of eqs. retraction and transport: the low-rank evaluation equals exp(alpha Q_X) applied to W and
+    to Y with the n x n matrix exponential (covers n - p >= p, 0 < n - p < p and square W)."""
+    rng = np.random.default_rng(n * 10 + p)
+    W = np.linalg.qr(rng.standard_normal((n, p)))[0]
+    X = mf.project(W, rng.standard_normal((n, p)))
+    Y = mf.project(W, rng.standard_normal((n, p)))
+    for alpha in (0.3, -1.1, 2.0):
+        E = scipy.linalg.expm(alpha * _full_q(W, X))
+        Wn, Xp = mf.retract_exp(W, X, alpha)
+        assert np.allclose(Wn, E @ W, atol=1e-12)
+        assert np.allclose(Xp, E @ X, atol=1e-12)
+        assert np.allclose(mf.transport_exp(W, X, alpha, Y), E @ Y, atol=1e-12)
+
+
+def test_exp_retraction_properties():
+    rng = np.random.default_rng(3)
+    W = np.linalg.qr(rng.standard_normal((14, 5)))[0]
+    X = mf.project(W, rng.standard_normal((14, 5)))
+    assert np.allclose(mf.retract_exp(W, X, 0.0)[0], W, atol=1e-14)
+    for alpha in (0.0, 0.4, 1.7):
+        Wn, Xp = mf.retract_exp(W, X, alpha)
+        assert np.max(np.abs(Wn.T @ Wn - np.eye(5))) < 1e-13
+        eps = 1e-5
+        fd = (mf.retract_exp(W, X, alpha + eps)[0] - mf.retract_exp(W, X, alpha - eps)[0]) / (2 * eps)
+        assert np.allclose(fd, Xp, atol=1e-8)
+    # transport: a metric connection (the paper notes it preserves inner products) mapping tangents to tangents
+    Y1 = mf.project(W, rng.standard_normal((14, 5)))
+    Y2 = mf.project(W, rng.standard_normal((14, 5)))
+    Wn = mf.retract_exp(W, X, 0.9)[0]
+    T1, T2 = mf.transport_exp(W, X, 0.9, Y1), mf.transport_exp(W, X, 0.9, Y2)
+    assert abs(mf.inner([T1], [T2]) - mf.inner([Y1], [Y2])) < 1e-12
+    S = Wn.T @ T1
+    assert np.max(np.abs(S + S.T)) < 1e-12
+
+
+def test_exp_retraction_grassmann_geodesic():
+    """With A = W^T X = 0 the curve is the Grassmann geodesic W V cos(S alpha) V^T + U sin(S alpha) V^T for the thin
+    SVD X = U S V^T (Edelman, Arias and Smith 1998, the closed form the paper's footnote refers to)."""
+    rng = np.random.default_rng(4)
+    W = np.linalg.qr(rng.standard_normal((15, 4)))[0]
+    X = mf.grassmann_project(W, rng.standard_normal((15, 4)))
+    assert np.max(np.abs(W.T @ X)) < 1e-13
+    U, s, Vt = np.linalg.svd(X, full_matrices=False)
+    for alpha in (0.5, 1.3):
+        geo = W @ Vt.T @ np.diag(np.cos(s * alpha)) @ Vt + U @ np.diag(np.sin(s * alpha)) @ Vt
+        assert np.allclose(mf.retract_exp(W, X, alpha)[0], geo, atol=1e-12)
