@@ -204,6 +204,9 @@ typedef struct {
   int precondition;                /* 1: Hilbert-space preconditioner as H0 (Sec. 3, Sec. 4)                */
   int max_ls_evals;                /* line-search evaluations per iteration (10)                            */
   mera_krylov_opts krylov;
+  int method;                      /* 0: L-BFGS (Sec. 3); 1: nonlinear conjugate gradient with the           */
+                                   /* preconditioned Hager-Zhang coefficient (Sec. 3), the previous         */
+                                   /* direction carried over by the transport; lbfgs_m is then ignored     */
 } mera_job;
 
 typedef struct {

@@ -30,7 +30,7 @@ class Job(ctypes.Structure):
     _fields_ = [("shape", MeraShape), ("h3_host", ctypes.POINTER(c_double)),
                 ("init_host", ctypes.POINTER(ctypes.POINTER(c_double))), ("prec", c_int), ("lbfgs_m", c_int),
                 ("max_iter", c_int), ("grad_tol", c_double), ("polish_tol", c_double), ("precondition", c_int),
-                ("max_ls_evals", c_int), ("krylov", KrylovOpts)]
+                ("max_ls_evals", c_int), ("krylov", KrylovOpts), ("method", c_int)]
 
 
 class Result(ctypes.Structure):

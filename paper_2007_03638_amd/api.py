@@ -228,9 +228,10 @@ class Context:
 
     # ---- whole optimisation -------------------------------------------------------------------------------
     def run_optimize(self, T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, polish_tol=0.0,
-                     precondition=True, max_ls_evals=10, krylov=None, d=4, log_cap=0, want_final=False):
+                     precondition=True, max_ls_evals=10, krylov=None, d=4, log_cap=0, want_final=False,
+                     method="lbfgs"):
         job, keep = make_job(T, chi, h3, init, prec, m, max_iter, grad_tol, polish_tol, precondition,
-                             max_ls_evals, krylov, d)
+                             max_ls_evals, krylov, d, method)
         res = L.Result()
         logs = (L.IterLog * max(log_cap, 1))()
         nlog = ctypes.c_int(0)
@@ -259,7 +260,7 @@ def result_dict(res):
 
 
 def make_job(T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, polish_tol=0.0, precondition=True,
-             max_ls_evals=10, krylov=None, d=4):
+             max_ls_evals=10, krylov=None, d=4, method="lbfgs"):
     """Build a mera_job; returns (job, keepalive) — keep the second item alive while the job is in use."""
     h3c = np.ascontiguousarray(h3, dtype=np.float64)
     mats = [np.ascontiguousarray(x, dtype=np.float64) for x in init]
@@ -268,7 +269,8 @@ def make_job(T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, p
     kr = krylov or {}
     job = L.Job(_shape(T, chi, d), h3c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ptrs, _prec(prec), m,
                 max_iter, grad_tol, polish_tol, 1 if precondition else 0, max_ls_evals,
-                L.KrylovOpts(kr.get("dim", 0), kr.get("max_restarts", 0), kr.get("tol", 0.0)))
+                L.KrylovOpts(kr.get("dim", 0), kr.get("max_restarts", 0), kr.get("tol", 0.0)),
+                {"lbfgs": 0, "cg": 1}[method])
     return job, (h3c, mats, ptrs)
 
 

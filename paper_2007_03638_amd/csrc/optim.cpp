@@ -345,6 +345,8 @@ JobSpec JobSpec::from_c(const mera_job& j) {
   s.polish_tol = j.polish_tol;
   s.precondition = j.precondition != 0;
   s.max_ls_evals = j.max_ls_evals > 0 ? j.max_ls_evals : 10;
+  MERA_CHECK(j.method == 0 || j.method == 1, MERA_EINVAL, "job: method must be 0 (L-BFGS) or 1 (CG)");
+  s.method = j.method;
   if (j.krylov.krylov_dim > 0) s.krylov.dim = j.krylov.krylov_dim;
   if (j.krylov.max_restarts > 0) s.krylov.max_restarts = j.krylov.max_restarts;
   if (j.krylov.tol > 0) s.krylov.tol = j.krylov.tol;
@@ -369,7 +371,10 @@ void Optimizer::start(Ctx& c, const JobSpec& j, int log_cap_) {
   for (Flat* F : {&W, &G, &Wn, &Gn, &D, &Xp, &dir}) F->init(n, p);
   rv.init(rp, rp);
   rvn.init(rp, rp);
-  hist.init(c, n, p, job.m);
+  hist.init(c, n, p, job.method == 0 ? job.m : 0);
+  if (job.method == 1)
+    for (Flat* F : {&cg_d, &cg_y, &cg_pg, &cg_py}) F->init(n, p);
+  cg_have = false;
   const size_t h3n = job.h3.size();
   h3dev.alloc(h3n * 8);
   MERA_HIP(hipMemcpyAsync(h3dev.ptr, job.h3.data(), h3n * 8, hipMemcpyHostToDevice, c.stream));
@@ -434,7 +439,10 @@ bool Optimizer::advance() {
   }
   Metric* mp = job.precondition ? &met : nullptr;
   const auto Wv = W.views();
-  double slope = hist.step(c, Wv, G.views(), mp, dir.views());
+  const bool cg = job.method == 1;
+  bool momentum = false;
+  double alpha0 = 1.0;
+  double slope = cg ? cg_direction(mp, momentum, alpha0) : hist.step(c, Wv, G.views(), mp, dir.views());
 
   double f_trial = 0.0;
   auto phi = [&](double alpha, double& fa, double& dfa) {
@@ -447,14 +455,14 @@ bool Optimizer::advance() {
     f_trial = fa;
   };
   // Wolfe / approximate-Wolfe line search (same rules as the reference optimiser of the tests)
-  auto line_search = [&](double f0, double df0, double& alpha_out) {
+  auto line_search = [&](double f0, double df0, double a0, double& alpha_out) {
     const double c1 = 1e-4, c2 = 0.9, eps = 1e-6;
     const double epsk = eps * std::fabs(f0);
     double lo_a = 0.0, lo_df = df0;
     double hi_a = std::numeric_limits<double>::infinity();
     double hi_df = std::numeric_limits<double>::quiet_NaN();
     bool has_hi_df = false;
-    double alpha = 1.0;
+    double alpha = a0;
     for (int k = 1; k <= job.max_ls_evals; ++k) {
       double fa, dfa;
       phi(alpha, fa, dfa);
@@ -492,11 +500,15 @@ bool Optimizer::advance() {
     return false;
   };
   double alpha = 0.0;
-  bool ok = line_search(f, slope, alpha);
-  if (!ok && hist.size() > 0) {
+  bool ok = line_search(f, slope, alpha0, alpha);
+  if (!ok && !cg && hist.size() > 0) {
     hist.reset();
     slope = hist.step(c, Wv, G.views(), mp, dir.views());
-    ok = line_search(f, slope, alpha);
+    ok = line_search(f, slope, 1.0, alpha);
+  } else if (!ok && cg && momentum) {
+    cg_restart(mp);
+    slope = inner(c, G.views(), dir.views());
+    ok = line_search(f, slope, 1.0, alpha);
   }
   if (!ok) {
     status = 2;
@@ -504,7 +516,21 @@ bool Optimizer::advance() {
     return true;
   }
   // Wn, Gn, rvn hold the accepted (last evaluated) point
-  hist.push(c, Wn.views(), dir.views(), alpha, G.views(), Gn.views());
+  if (cg) {
+    // previous direction and gradient carried to the new point by the transport; y = G_new - T(G_old)
+    for (int i = 0; i < W.count(); ++i) {
+      MatView dv = cg_d.view(i), yv = cg_y.view(i);
+      stiefel_project_one(c, Wn.view(i), dir.view(i), dv);
+      stiefel_project_one(c, Wn.view(i), G.view(i), yv);
+    }
+    axpby(c, 1.0, VPtr{Gn.ptr(), Prec::F64}, -1.0, VPtr{cg_y.ptr(), Prec::F64}, cg_y.total);
+    cg_gold = gnorm;
+    cg_alpha_prev = alpha;
+    cg_slope_prev = slope;
+    cg_have = true;
+  } else {
+    hist.push(c, Wn.views(), dir.views(), alpha, G.views(), Gn.views());
+  }
   std::swap(W.buf, Wn.buf);
   std::swap(G.buf, Gn.buf);
   std::swap(rv.buf, rvn.buf);
@@ -513,6 +539,43 @@ bool Optimizer::advance() {
   iter++;
   if (job.precondition) met.compute(c, rv.views());
   return false;
+}
+
+void Optimizer::cg_restart(Metric* met) {
+  Ctx& c = *ctx;
+  apply_precond(c, G, W.views(), met, G.ptr(), cg_pg.ptr());
+  copy(c, VPtr{dir.ptr(), Prec::F64}, VPtr{cg_pg.ptr(), Prec::F64}, G.total);
+  scal(c, -1.0, VPtr{dir.ptr(), Prec::F64}, G.total);
+}
+
+double Optimizer::cg_direction(Metric* met, bool& momentum, double& alpha0) {
+  Ctx& c = *ctx;
+  const int64_t N = G.total;
+  const VPtr g{G.ptr(), Prec::F64}, pg{cg_pg.ptr(), Prec::F64}, d{dir.ptr(), Prec::F64};
+  const VPtr pd{cg_d.ptr(), Prec::F64}, y{cg_y.ptr(), Prec::F64}, py{cg_py.ptr(), Prec::F64};
+  cg_restart(met);  // dir = -P G (and cg_pg = P G)
+  momentum = false;
+  if (cg_have) {
+    apply_precond(c, G, W.views(), met, cg_y.ptr(), cg_py.ptr());
+    const double dy = dot(c, pd, y, N);
+    double beta = 0.0;
+    if (dy != 0.0 && std::isfinite(dy)) {
+      // preconditioned Hager-Zhang coefficient, truncated below as in Hager and Zhang
+      beta = dot(c, y, pg, N) / dy - 2.0 * dot(c, y, py, N) * dot(c, pd, g, N) / (dy * dy);
+      const double dn = std::sqrt(dot(c, pd, pd, N));
+      if (dn > 0.0 && cg_gold > 0.0) beta = std::max(beta, -1.0 / (dn * std::min(0.01, cg_gold)));
+    }
+    axpby(c, beta, pd, 1.0, d, N);
+    momentum = true;
+  }
+  double slope = dot(c, g, d, N);
+  if (!(slope < 0.0)) {
+    cg_restart(met);
+    slope = dot(c, g, d, N);
+    momentum = false;
+  }
+  alpha0 = (momentum && cg_alpha_prev > 0.0) ? cg_alpha_prev * cg_slope_prev / slope : 1.0;
+  return slope;
 }
 
 void Optimizer::finish(std::vector<double*>* final_host) {
@@ -537,7 +600,7 @@ void Optimizer::finish(std::vector<double*>* final_host) {
 
 size_t Optimizer::device_bytes() const {
   size_t b = 0;
-  for (const Flat* F : {&W, &G, &Wn, &Gn, &D, &Xp, &dir, &rv, &rvn}) b += F->buf.bytes;
+  for (const Flat* F : {&W, &G, &Wn, &Gn, &D, &Xp, &dir, &rv, &rvn, &cg_d, &cg_y, &cg_pg, &cg_py}) b += F->buf.bytes;
   b += warm.rho.bytes + warm.ht.bytes + h3dev.bytes;
   for (auto& x : hist.S) b += x.bytes;
   for (auto& x : hist.Y) b += x.bytes;

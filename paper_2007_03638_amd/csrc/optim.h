@@ -81,6 +81,7 @@ struct JobSpec {
   int m = 8, max_iter = 100, max_ls_evals = 10;
   double grad_tol = 1e-10, polish_tol = 0.0;
   bool precondition = true;
+  int method = 0;                          // 0: L-BFGS, 1: nonlinear CG (Hager-Zhang)
   KrylovOpts krylov;
   static JobSpec from_c(const mera_job& j);
 };
@@ -99,6 +100,10 @@ struct Optimizer {
   Warm warm;
   Lbfgs hist;
   Metric met;
+  // nonlinear CG state: previous direction transported to the current point, y = G - T(G_prev), scratch
+  Flat cg_d, cg_y, cg_pg, cg_py;
+  bool cg_have = false;
+  double cg_gold = 0, cg_alpha_prev = 0, cg_slope_prev = 0;
   Prec prec = Prec::F64;
   double f = 0, gnorm = 0, last_alpha = 0;
   int iter = 0, evals = 0, status = -1, polish_iter = -1, krylov_apps = 0;
@@ -114,7 +119,10 @@ struct Optimizer {
 
  private:
   double evaluate(const Flat& X, Flat& Gout, Flat& rvout);   // energy; fills G = P(D) and metrics
-  void precond_all(const std::vector<MatView>& W, const Flat& X, Flat& out);
+  // CG direction into `dir` (Sec. 3, Hager-Zhang coefficient); returns the slope <G, dir>, sets `momentum` when
+  // the previous direction was used and `alpha0` to the first trial step
+  double cg_direction(Metric* met, bool& momentum, double& alpha0);
+  void cg_restart(Metric* met);   // dir = -P G
 };
 
 }  // namespace mera

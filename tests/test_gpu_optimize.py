@@ -65,3 +65,27 @@ def test_fp32_with_fp64_polish(ctx):
     energies = [r["energy"] for r in got["log"]]
     assert energies[-1] < energies[0]
     assert got["energy"] / 2 > model.tfim_exact_energy_per_spin(1.0)
+
+
+@pytest.mark.parametrize("precondition", [True, False])
+def test_fp64_cg_trajectory_matches_oracle(ctx, precondition):
+    """Nonlinear CG (Hager-Zhang coefficient, transported previous direction) against the oracle's CG driver."""
+    chi, T, iters = 4, 2, 8
+    W0 = _init(1, chi, T)
+    h3 = model.tfim_h3(1.0)
+    prob = optim.Problem(h3, chi, T)
+    log = []
+    _, f_ref, g_ref, info = optim.optimize_cg(W0, prob, max_iter=iters, use_precond=precondition, log=log)
+    got = ctx.run_optimize(2, 4, h3, W0, prec="fp64", max_iter=iters, grad_tol=0.0, precondition=precondition,
+                           log_cap=64, want_final=True, method="cg")
+    print("gpu", [(r["iter"], r["evals"], r["energy"]) for r in got["log"]], flush=True)
+    print("ref", [(r["iter"], r["evals"], r["energy"]) for r in log], flush=True)
+    assert len(got["log"]) >= len(log)
+    for a, b in zip(got["log"], log):
+        assert a["evals"] == b["evals"]
+        assert abs(a["energy"] - b["energy"]) <= 1e-10 * abs(b["energy"])
+        assert abs(a["gnorm"] - b["gnorm"]) <= 1e-7 * b["gnorm"]
+    assert abs(got["energy"] - f_ref) <= 1e-10 * abs(f_ref)
+    W = got["final"]
+    params = [(W[2 * i], W[2 * i + 1]) for i in range(T + 1)]
+    assert abs(om.energy_only(params, h3, chi, T) - got["energy"]) <= 1e-12 * abs(got["energy"])
