@@ -165,6 +165,21 @@ mera_status stiefel_retract(mera_ctx* ctx, int count, const mera_mat* W, const m
                             mera_mat* W_out, mera_mat* X_out);
 /* Vector transport by projection onto the tangent space at W_new. Y_out may alias Y. */
 mera_status stiefel_transport(mera_ctx* ctx, int count, const mera_mat* W_new, const mera_mat* Y, mera_mat* Y_out);
+/* The paper's exponential retraction (Sec. 2.3, eq. retraction): W_out = exp(alpha Q_X) W with
+ * Q_X = [W W_perp] [[A, -B^T], [B, 0]] [W W_perp]^T, X = W A + W_perp B a tangent at W (Stiefel: A skew;
+ * Grassmann: A = 0). Evaluated in low-rank form: W_perp B = (1 - W W^T) X is spanned by an orthonormal basis of
+ * at most min(p, n - p) columns (from the FP64 Jacobi eigendecomposition of its Gram matrix), the (p + r)-square
+ * exponential by scaling and squaring of a degree-14 Taylor polynomial on FP64 MFMA GEMMs; the result gets one
+ * Newton-Schulz polar refinement. X_out (nullable) = exp(alpha Q_X) X = dW_out/dalpha. FP64 device buffers,
+ * caller-owned; W_out must not alias W or X. MERA_ENONFINITE for a non-finite generator. */
+mera_status stiefel_retract_exp(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* X, double alpha,
+                                mera_mat* W_out, mera_mat* X_out);
+/* The paper's vector transport (Sec. 2.3, eq. transport): Y_out = exp(alpha Q_X) Y for the retraction of W along
+ * X by alpha; it preserves inner products. Y_out may alias Y. */
+mera_status stiefel_transport_exp(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* X, double alpha,
+                                  const mera_mat* Y, mera_mat* Y_out);
+/* Grassmann tangent projection (Sec. 2.2, eq. grassmann_gradient, real case): G = (1 - W W^T) D. G may alias D. */
+mera_status grassmann_project(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, mera_mat* G);
 /* Hilbert-space preconditioner (Sec. 3 eqs. preconditioner / preconditioner_solution): X = W A + W_perp B
  * maps to W A~ + W_perp B~ with A~ f + f A~ = 2 A, B~ = B f^{-1}, f = (rho^2 + delta^2)^{1/2}; delta < 0 means
  * delta = ||X_v||_F per factor (Sec. 4). rho: count p x p symmetric PSD matrices. */
@@ -207,6 +222,10 @@ typedef struct {
   int method;                      /* 0: L-BFGS (Sec. 3); 1: nonlinear conjugate gradient with the           */
                                    /* preconditioned Hager-Zhang coefficient (Sec. 3), the previous         */
                                    /* direction carried over by the transport; lbfgs_m is then ignored     */
+  int retraction;                  /* 0: polar retraction + projection transport; 1: the paper's            */
+                                   /* exponential retraction and transport (Sec. 2.3)                       */
+  int grassmann_w;                 /* 1: isometries w on Grassmann manifolds (Sec. 4): Grassmann gradient    */
+                                   /* projection and projection transport for the w factors                 */
 } mera_job;
 
 typedef struct {

@@ -30,7 +30,8 @@ class Job(ctypes.Structure):
     _fields_ = [("shape", MeraShape), ("h3_host", ctypes.POINTER(c_double)),
                 ("init_host", ctypes.POINTER(ctypes.POINTER(c_double))), ("prec", c_int), ("lbfgs_m", c_int),
                 ("max_iter", c_int), ("grad_tol", c_double), ("polish_tol", c_double), ("precondition", c_int),
-                ("max_ls_evals", c_int), ("krylov", KrylovOpts), ("method", c_int)]
+                ("max_ls_evals", c_int), ("krylov", KrylovOpts), ("method", c_int), ("retraction", c_int),
+                ("grassmann_w", c_int)]
 
 
 class Result(ctypes.Structure):
@@ -78,6 +79,9 @@ SIGNATURES = {
     "stiefel_project": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P]),
     "stiefel_retract": (c_int, [c_void_p, c_int, MAT_P, MAT_P, c_double, MAT_P, MAT_P]),
     "stiefel_transport": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P]),
+    "stiefel_retract_exp": (c_int, [c_void_p, c_int, MAT_P, MAT_P, c_double, MAT_P, MAT_P]),
+    "stiefel_transport_exp": (c_int, [c_void_p, c_int, MAT_P, MAT_P, c_double, MAT_P, MAT_P]),
+    "grassmann_project": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P]),
     "stiefel_precondition": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P, c_double, MAT_P]),
     "mera_inner": (c_int, [c_void_p, c_int, MAT_P, MAT_P, ctypes.POINTER(c_double)]),
     "lbfgs_create": (c_int, [c_void_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int), c_int,

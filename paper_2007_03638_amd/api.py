@@ -206,6 +206,31 @@ class Context:
                     "stiefel_transport")
         return Yo
 
+    def stiefel_retract_exp(self, W, X, alpha, tangent=True):
+        W = [self._dev(x) for x in W]
+        X = [self._dev(x) for x in X]
+        Wo = [torch.empty_like(x) for x in W]
+        Xo = [torch.empty_like(x) for x in W] if tangent else None
+        self._check(self._lib.stiefel_retract_exp(self.ptr, len(W), _mats(W), _mats(X), float(alpha), _mats(Wo),
+                                                  _mats(Xo) if tangent else None), "stiefel_retract_exp")
+        return (Wo, Xo) if tangent else Wo
+
+    def stiefel_transport_exp(self, W, X, alpha, Y):
+        W = [self._dev(x) for x in W]
+        X = [self._dev(x) for x in X]
+        Y = [self._dev(x) for x in Y]
+        Yo = [torch.empty_like(x) for x in Y]
+        self._check(self._lib.stiefel_transport_exp(self.ptr, len(W), _mats(W), _mats(X), float(alpha), _mats(Y),
+                                                    _mats(Yo)), "stiefel_transport_exp")
+        return Yo
+
+    def grassmann_project(self, W, D):
+        W = [self._dev(x) for x in W]
+        D = [self._dev(x) for x in D]
+        G = [torch.empty_like(x) for x in D]
+        self._check(self._lib.grassmann_project(self.ptr, len(W), _mats(W), _mats(D), _mats(G)), "grassmann_project")
+        return G
+
     def stiefel_precondition(self, W, X, rho, delta=-1.0):
         W = [self._dev(x) for x in W]
         X = [self._dev(x) for x in X]
@@ -229,9 +254,9 @@ class Context:
     # ---- whole optimisation -------------------------------------------------------------------------------
     def run_optimize(self, T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, polish_tol=0.0,
                      precondition=True, max_ls_evals=10, krylov=None, d=4, log_cap=0, want_final=False,
-                     method="lbfgs"):
+                     method="lbfgs", retraction="polar", grassmann_w=False):
         job, keep = make_job(T, chi, h3, init, prec, m, max_iter, grad_tol, polish_tol, precondition,
-                             max_ls_evals, krylov, d, method)
+                             max_ls_evals, krylov, d, method, retraction, grassmann_w)
         res = L.Result()
         logs = (L.IterLog * max(log_cap, 1))()
         nlog = ctypes.c_int(0)
@@ -260,7 +285,7 @@ def result_dict(res):
 
 
 def make_job(T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, polish_tol=0.0, precondition=True,
-             max_ls_evals=10, krylov=None, d=4, method="lbfgs"):
+             max_ls_evals=10, krylov=None, d=4, method="lbfgs", retraction="polar", grassmann_w=False):
     """Build a mera_job; returns (job, keepalive) — keep the second item alive while the job is in use."""
     h3c = np.ascontiguousarray(h3, dtype=np.float64)
     mats = [np.ascontiguousarray(x, dtype=np.float64) for x in init]
@@ -270,7 +295,7 @@ def make_job(T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, p
     job = L.Job(_shape(T, chi, d), h3c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ptrs, _prec(prec), m,
                 max_iter, grad_tol, polish_tol, 1 if precondition else 0, max_ls_evals,
                 L.KrylovOpts(kr.get("dim", 0), kr.get("max_restarts", 0), kr.get("tol", 0.0)),
-                {"lbfgs": 0, "cg": 1}[method])
+                {"lbfgs": 0, "cg": 1}[method], {"polar": 0, "exp": 1}[retraction], 1 if grassmann_w else 0)
     return job, (h3c, mats, ptrs)
 
 

@@ -343,6 +343,75 @@ mera_status stiefel_transport(mera_ctx* ctx, int count, const mera_mat* W_new, c
   return stiefel_project(ctx, count, W_new, Y, Y_out);
 }
 
+mera_status stiefel_retract_exp(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* X, double alpha,
+                                mera_mat* W_out, mera_mat* X_out) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(count >= 0 && std::isfinite(alpha), MERA_EINVAL, "count/alpha");
+    check_isometry_shapes(W, count, "stiefel_retract_exp W");
+    check_mats(X, count, "stiefel_retract_exp X");
+    check_mats(W_out, count, "stiefel_retract_exp W_out");
+    same_shapes(W, X, count, "stiefel_retract_exp");
+    same_shapes(W, W_out, count, "stiefel_retract_exp");
+    if (X_out) {
+      check_mats(X_out, count, "stiefel_retract_exp X_out");
+      same_shapes(W, X_out, count, "stiefel_retract_exp");
+    }
+    for (int i = 0; i < count; ++i)
+      MERA_CHECK(W_out[i].data != W[i].data && W_out[i].data != X[i].data, MERA_EINVAL,
+                 "stiefel_retract_exp: W_out aliases an input");
+    DeviceGuard g(ctx->c.device);
+    ExpFrame fr;
+    for (int i = 0; i < count; ++i) {
+      const MatView Wv{W[i].n, W[i].p, W[i].data}, Xv{X[i].n, X[i].p, X[i].data};
+      exp_frame_one(ctx->c, Wv, Xv, fr);
+      MatView xo = X_out ? MatView{X_out[i].n, X_out[i].p, X_out[i].data} : MatView{};
+      exp_retract_one(ctx->c, Wv, Xv, fr, alpha, MatView{W_out[i].n, W_out[i].p, W_out[i].data},
+                      X_out ? &xo : nullptr);
+    }
+    ctx->c.sync();
+  });
+}
+
+mera_status stiefel_transport_exp(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* X, double alpha,
+                                  const mera_mat* Y, mera_mat* Y_out) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(count >= 0 && std::isfinite(alpha), MERA_EINVAL, "count/alpha");
+    check_isometry_shapes(W, count, "stiefel_transport_exp W");
+    for (const mera_mat* M : {X, Y, static_cast<const mera_mat*>(Y_out)}) {
+      check_mats(M, count, "stiefel_transport_exp");
+      same_shapes(W, M, count, "stiefel_transport_exp");
+    }
+    DeviceGuard g(ctx->c.device);
+    ExpFrame fr;
+    for (int i = 0; i < count; ++i) {
+      const MatView Wv{W[i].n, W[i].p, W[i].data};
+      exp_frame_one(ctx->c, Wv, MatView{X[i].n, X[i].p, X[i].data}, fr);
+      exp_set_alpha(ctx->c, fr, alpha);
+      exp_apply_one(ctx->c, Wv, fr, MatView{Y[i].n, Y[i].p, Y[i].data}, MatView{Y_out[i].n, Y_out[i].p, Y_out[i].data});
+    }
+    ctx->c.sync();
+  });
+}
+
+mera_status grassmann_project(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, mera_mat* G) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(count >= 0, MERA_EINVAL, "count");
+    check_isometry_shapes(W, count, "grassmann_project W");
+    check_mats(D, count, "grassmann_project D");
+    check_mats(G, count, "grassmann_project G");
+    same_shapes(W, D, count, "grassmann_project");
+    same_shapes(W, G, count, "grassmann_project");
+    DeviceGuard g(ctx->c.device);
+    for (int i = 0; i < count; ++i)
+      grassmann_project_one(ctx->c, MatView{W[i].n, W[i].p, W[i].data}, MatView{D[i].n, D[i].p, D[i].data},
+                            MatView{G[i].n, G[i].p, G[i].data});
+    ctx->c.sync();
+  });
+}
+
 mera_status stiefel_precondition(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* X,
                                  const mera_mat* rho, double delta, mera_mat* X_out) {
   if (!ctx) return MERA_EINVAL;

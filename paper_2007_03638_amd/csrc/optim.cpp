@@ -1,6 +1,7 @@
 // Stiefel manifold, preconditioner, L-BFGS and the optimisation driver (see optim.h).
 #include "optim.h"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <limits>
@@ -122,6 +123,142 @@ void stiefel_retract_one(Ctx& ctx, const MatView& W, const MatView& X, double al
     mm(ctx, "Xo[nq] += Y[np] * KZ[pq]", {{'n', n}, {'p', p}, {'q', p}},
        {{"Xo", Xout->data}, {"Y", Y}, {"KZ", Y2}});
   }
+}
+
+void grassmann_project_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& G) {
+  const int n = W.n, p = W.p;
+  double* S = tmp(ctx, "gp.S", (int64_t)p * p);
+  mm(ctx, "S[pq] = W[np] * D[nq]", {{'n', n}, {'p', p}, {'q', p}}, {{"S", S}, {"W", W.data}, {"D", D.data}});
+  if (G.data != D.data) copy(ctx, d64(G), d64(D), (int64_t)n * p);
+  mm(ctx, "G[nq] += -1.0 * W[np] * S[pq]", {{'n', n}, {'p', p}, {'q', p}},
+     {{"G", G.data}, {"W", W.data}, {"S", S}});
+}
+
+// ---- exponential retraction and transport (Sec. 2.3) -------------------------------------------------------
+
+void exp_frame_one(Ctx& ctx, const MatView& W, const MatView& X, ExpFrame& fr) {
+  const int n = W.n, p = W.p;
+  const int r = std::min(p, n - p);
+  fr.n = n;
+  fr.p = p;
+  fr.m = r > 0 ? 2 * p : p;
+  fr.has_alpha = false;
+  const int m = fr.m;
+  fr.M.ensure((size_t)m * m * 8);
+  fr.E.ensure((size_t)m * m * 8);
+  double* M = fr.M.as<double>();
+  const std::initializer_list<std::pair<char, int64_t>> dnp = {{'n', n}, {'p', p}, {'q', p}};
+  double* A = tmp(ctx, "ex.A", (int64_t)p * p);
+  mm(ctx, "A[pq] = W[np] * X[nq]", dnp, {{"A", A}, {"W", W.data}, {"X", X.data}});
+  fill(ctx, VPtr{M, Prec::F64}, (int64_t)m * m, 0.0);
+  copy_block(ctx, M, m, A, p, p, p, 1.0);
+  if (r == 0) return;
+  // Z = (1 - W W^T) X; an orthonormal basis of range(Z) from the eigendecomposition of Z^T Z (any basis gives the
+  // same exp(alpha Q_X)): Q = Z V_r diag(lam_r^{-1/2}) over the r largest eigenvalues above rounding
+  fr.Q.ensure((size_t)n * p * 8);
+  double* Q = fr.Q.as<double>();
+  double* Z = tmp(ctx, "ex.Z", (int64_t)n * p);
+  copy(ctx, VPtr{Z, Prec::F64}, d64(X), (int64_t)n * p);
+  mm(ctx, "Z[nq] += -1.0 * W[np] * A[pq]", dnp, {{"Z", Z}, {"W", W.data}, {"A", A}});
+  double* K = tmp(ctx, "ex.K", (int64_t)p * p);
+  mm(ctx, "K[pq] = Z[np] * Z2[nq]", dnp, {{"K", K}, {"Z", Z}, {"Z2", Z}});
+  symmetrize(ctx, VPtr{K, Prec::F64}, p);
+  double* lam = tmp(ctx, "ex.lam", p);
+  double* V = tmp(ctx, "ex.V", (int64_t)p * p);
+  jacobi_eigh(ctx, K, lam, V, p);
+  std::vector<double> hl(p), sc(p, 0.0);
+  MERA_HIP(hipMemcpyAsync(hl.data(), lam, (size_t)p * 8, hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  std::vector<int> order(p);
+  for (int i = 0; i < p; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return hl[a] > hl[b]; });
+  const double lmax = hl[order[0]];
+  for (int k = 0; k < r; ++k) {
+    const int i = order[k];
+    if (lmax > 0.0 && hl[i] > 1e-24 * lmax) sc[i] = 1.0 / std::sqrt(hl[i]);
+  }
+  double* sdev = tmp(ctx, "ex.s", p);
+  MERA_HIP(hipMemcpyAsync(sdev, sc.data(), (size_t)p * 8, hipMemcpyHostToDevice, ctx.stream));
+  mm(ctx, "Q[nq] = Z[np] * V[pq]", dnp, {{"Q", Q}, {"Z", Z}, {"V", V}});
+  scale_cols(ctx, Q, sdev, n, p);
+  ctx.sync();  // sc is host memory read by the copy above
+  double* B = tmp(ctx, "ex.B", (int64_t)p * p);
+  double* BT = tmp(ctx, "ex.BT", (int64_t)p * p);
+  mm(ctx, "B[pq] = Q[np] * Z[nq]", dnp, {{"B", B}, {"Q", Q}, {"Z", Z}});
+  mm(ctx, "BT[pq] = Z[np] * Q[nq]", dnp, {{"BT", BT}, {"Z", Z}, {"Q", Q}});
+  copy_block(ctx, M + (int64_t)p * m, m, B, p, p, p, 1.0);   // lower left:  B
+  copy_block(ctx, M + p, m, BT, p, p, p, -1.0);              // upper right: -B^T
+}
+
+void exp_set_alpha(Ctx& ctx, ExpFrame& fr, double alpha) {
+  const int m = fr.m;
+  const int64_t mm2 = (int64_t)m * m;
+  const double* M = fr.M.as<double>();
+  const double nrm = std::fabs(alpha) * std::sqrt(dot(ctx, VPtr{(void*)M, Prec::F64}, VPtr{(void*)M, Prec::F64}, mm2));
+  MERA_CHECK(std::isfinite(nrm), MERA_ENONFINITE, "exponential retraction: non-finite generator");
+  // scaling and squaring: ||alpha M / 2^s||_F <= 1/2, Taylor polynomial of degree 14 (remainder below 3e-17)
+  int s = 0;
+  while (nrm > 0.5 * std::ldexp(1.0, s) && s < 60) ++s;
+  const double c = alpha * std::ldexp(1.0, -s);
+  double* Bm = tmp(ctx, "ex.Bm", mm2);
+  double* P = tmp(ctx, "ex.P", mm2);
+  double* T = tmp(ctx, "ex.T", mm2);
+  copy(ctx, VPtr{Bm, Prec::F64}, VPtr{(void*)M, Prec::F64}, mm2);
+  scal(ctx, c, VPtr{Bm, Prec::F64}, mm2);
+  const std::initializer_list<std::pair<char, int64_t>> dmm = {{'i', m}, {'j', m}, {'l', m}};
+  constexpr int kDeg = 14;
+  copy(ctx, VPtr{P, Prec::F64}, VPtr{Bm, Prec::F64}, mm2);
+  scal(ctx, 1.0 / kDeg, VPtr{P, Prec::F64}, mm2);
+  add_diag(ctx, VPtr{P, Prec::F64}, m, 1.0);
+  for (int k = kDeg - 1; k >= 1; --k) {  // Horner: P <- 1 + B P / k
+    mm(ctx, "T[ij] = B[il] * P[lj]", dmm, {{"T", T}, {"B", Bm}, {"P", P}});
+    scal(ctx, 1.0 / k, VPtr{T, Prec::F64}, mm2);
+    add_diag(ctx, VPtr{T, Prec::F64}, m, 1.0);
+    std::swap(P, T);
+  }
+  for (int i = 0; i < s; ++i) {
+    mm(ctx, "T[ij] = P[il] * P2[lj]", dmm, {{"T", T}, {"P", P}, {"P2", P}});
+    std::swap(P, T);
+  }
+  copy(ctx, VPtr{fr.E.ptr, Prec::F64}, VPtr{P, Prec::F64}, mm2);
+  fr.alpha = alpha;
+  fr.has_alpha = true;
+}
+
+void exp_apply_one(Ctx& ctx, const MatView& W, const ExpFrame& fr, const MatView& Y, const MatView& out) {
+  const int n = fr.n, p = fr.p, m = fr.m;
+  MERA_CHECK(fr.has_alpha && W.n == n && W.p == p && Y.n == n && Y.p == p, MERA_EINVAL, "exponential transport");
+  const std::initializer_list<std::pair<char, int64_t>> dnp = {{'n', n}, {'p', p}, {'q', p}};
+  double* C = tmp(ctx, "ea.C", (int64_t)m * p);
+  double* D = tmp(ctx, "ea.D", (int64_t)m * p);
+  double* Em = tmp(ctx, "ea.Em", (int64_t)m * m);
+  const bool low = m == 2 * p;
+  // C = U^T Y = [W^T Y; Q^T Y]
+  mm(ctx, "C[pq] = W[np] * Y[nq]", dnp, {{"C", C}, {"W", W.data}, {"Y", Y.data}});
+  if (low) mm(ctx, "C[pq] = Q[np] * Y[nq]", dnp, {{"C", C + (int64_t)p * p}, {"Q", fr.Q.ptr}, {"Y", Y.data}});
+  // D = (E - 1) C
+  copy(ctx, VPtr{Em, Prec::F64}, VPtr{fr.E.ptr, Prec::F64}, (int64_t)m * m);
+  add_diag(ctx, VPtr{Em, Prec::F64}, m, -1.0);
+  mm(ctx, "D[iq] = Em[ij] * C[jq]", {{'i', m}, {'j', m}, {'q', p}}, {{"D", D}, {"Em", Em}, {"C", C}});
+  // out = Y + U D
+  if (out.data != Y.data) copy(ctx, d64(out), d64(Y), (int64_t)n * p);
+  mm(ctx, "O[nq] += W[np] * D[pq]", dnp, {{"O", out.data}, {"W", W.data}, {"D", D}});
+  if (low) mm(ctx, "O[nq] += Q[np] * D[pq]", dnp, {{"O", out.data}, {"Q", fr.Q.ptr}, {"D", D + (int64_t)p * p}});
+}
+
+void exp_retract_one(Ctx& ctx, const MatView& W, const MatView& X, ExpFrame& fr, double alpha, const MatView& Wout,
+                     const MatView* Xout) {
+  const int n = W.n, p = W.p;
+  if (!fr.has_alpha || fr.alpha != alpha) exp_set_alpha(ctx, fr, alpha);
+  if (Xout) exp_apply_one(ctx, W, fr, X, *Xout);
+  double* Wt = tmp(ctx, "er.W", (int64_t)n * p);
+  exp_apply_one(ctx, W, fr, W, MatView{n, p, Wt});
+  // one Newton-Schulz polar refinement: W <- W (3 - W^T W)/2
+  double* S = tmp(ctx, "er.S", (int64_t)p * p);
+  mm(ctx, "S[pq] = Wt[np] * Wt2[nq]", {{'n', n}, {'p', p}, {'q', p}}, {{"S", S}, {"Wt", Wt}, {"Wt2", Wt}});
+  scal(ctx, -0.5, VPtr{S, Prec::F64}, (int64_t)p * p);
+  add_diag(ctx, VPtr{S, Prec::F64}, p, 1.5);
+  mm(ctx, "Wo[nq] = Wt[np] * S[pq]", {{'n', n}, {'p', p}, {'q', p}}, {{"Wo", Wout.data}, {"Wt", Wt}, {"S", S}});
 }
 
 void Metric::compute(Ctx& ctx, const std::vector<MatView>& rho) {
@@ -276,13 +413,19 @@ double Lbfgs::step(Ctx& ctx, const std::vector<MatView>& W, const std::vector<Ma
 
 bool Lbfgs::push(Ctx& ctx, const std::vector<MatView>& Wn, const std::vector<MatView>& d, double alpha,
                  const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew) {
+  const Transport T = [&](int i, const MatView& in, const MatView& out) { stiefel_project_one(ctx, Wn[i], in, out); };
+  return push(ctx, T, d, alpha, Gold, Gnew);
+}
+
+bool Lbfgs::push(Ctx& ctx, const Transport& T, const std::vector<MatView>& d, double alpha,
+                 const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew) {
   const int64_t N = shape.total;
   // transport the stored pairs to the new point
   for (int sl : order) {
     auto sv = views_of(shape, S[sl].as<double>()), yv = views_of(shape, Y[sl].as<double>());
     for (int i = 0; i < shape.count(); ++i) {
-      stiefel_project_one(ctx, Wn[i], sv[i], sv[i]);
-      stiefel_project_one(ctx, Wn[i], yv[i], yv[i]);
+      T(i, sv[i], sv[i]);
+      T(i, yv[i], yv[i]);
     }
   }
   if (m == 0) return false;
@@ -303,8 +446,8 @@ bool Lbfgs::push(Ctx& ctx, const std::vector<MatView>& Wn, const std::vector<Mat
     const int64_t k = (int64_t)shape.n[i] * shape.p[i];
     copy(ctx, d64(sv[i]), d64(d[i]), k);
     scal(ctx, alpha, d64(sv[i]), k);
-    stiefel_project_one(ctx, Wn[i], sv[i], sv[i]);
-    stiefel_project_one(ctx, Wn[i], Gold[i], yv[i]);
+    T(i, sv[i], sv[i]);
+    T(i, Gold[i], yv[i]);
     axpby(ctx, 1.0, d64(Gnew[i]), -1.0, d64(yv[i]), k);
   }
   const double sy = dot(ctx, VPtr{sp, Prec::F64}, VPtr{yp, Prec::F64}, N);
@@ -347,6 +490,9 @@ JobSpec JobSpec::from_c(const mera_job& j) {
   s.max_ls_evals = j.max_ls_evals > 0 ? j.max_ls_evals : 10;
   MERA_CHECK(j.method == 0 || j.method == 1, MERA_EINVAL, "job: method must be 0 (L-BFGS) or 1 (CG)");
   s.method = j.method;
+  MERA_CHECK(j.retraction == 0 || j.retraction == 1, MERA_EINVAL, "job: retraction must be 0 (polar) or 1 (exp)");
+  s.retraction = j.retraction;
+  s.grassmann_w = j.grassmann_w != 0;
   if (j.krylov.krylov_dim > 0) s.krylov.dim = j.krylov.krylov_dim;
   if (j.krylov.max_restarts > 0) s.krylov.max_restarts = j.krylov.max_restarts;
   if (j.krylov.tol > 0) s.krylov.tol = j.krylov.tol;
@@ -375,6 +521,10 @@ void Optimizer::start(Ctx& c, const JobSpec& j, int log_cap_) {
   if (job.method == 1)
     for (Flat* F : {&cg_d, &cg_y, &cg_pg, &cg_py}) F->init(n, p);
   cg_have = false;
+  grass.assign(n.size(), 0);
+  for (size_t i = 1; i < n.size(); i += 2) grass[i] = job.grassmann_w ? 1 : 0;
+  frames.clear();
+  frames.resize(job.retraction == 1 ? n.size() : 0);
   const size_t h3n = job.h3.size();
   h3dev.alloc(h3n * 8);
   MERA_HIP(hipMemcpyAsync(h3dev.ptr, job.h3.data(), h3n * 8, hipMemcpyHostToDevice, c.stream));
@@ -408,8 +558,22 @@ double Optimizer::evaluate(const Flat& X, Flat& Gout, Flat& rvout) {
   EvalOut r = energy_grad(*ctx, job.shape, pt, h3dev.as<double>(), prec, &warm, job.krylov, go);
   evals++;
   krylov_apps += r.app_rho + r.app_ht;
-  for (int i = 0; i < X.count(); ++i) stiefel_project_one(*ctx, X.view(i), D.view(i), Gout.view(i));
+  for (int i = 0; i < X.count(); ++i) project_factor(i, X.view(i), D.view(i), Gout.view(i));
   return r.energy;
+}
+
+void Optimizer::project_factor(int i, const MatView& Wv, const MatView& Dv, const MatView& Gv) {
+  if (grass[i]) grassmann_project_one(*ctx, Wv, Dv, Gv);
+  else stiefel_project_one(*ctx, Wv, Dv, Gv);
+}
+
+void Optimizer::build_frames() {
+  for (int i = 0; i < W.count(); ++i) exp_frame_one(*ctx, W.view(i), dir.view(i), frames[i]);
+}
+
+void Optimizer::transport_factor(int i, const MatView& in, const MatView& out) {
+  if (job.retraction == 1) exp_apply_one(*ctx, W.view(i), frames[i], in, out);
+  else project_factor(i, Wn.view(i), in, out);
 }
 
 bool Optimizer::advance() {
@@ -443,12 +607,15 @@ bool Optimizer::advance() {
   bool momentum = false;
   double alpha0 = 1.0;
   double slope = cg ? cg_direction(mp, momentum, alpha0) : hist.step(c, Wv, G.views(), mp, dir.views());
+  const bool expr = job.retraction == 1;
+  if (expr) build_frames();
 
   double f_trial = 0.0;
   auto phi = [&](double alpha, double& fa, double& dfa) {
     for (int i = 0; i < W.count(); ++i) {
       MatView xo = Xp.view(i);
-      stiefel_retract_one(c, W.view(i), dir.view(i), alpha, Wn.view(i), &xo);
+      if (expr) exp_retract_one(c, W.view(i), dir.view(i), frames[i], alpha, Wn.view(i), &xo);
+      else stiefel_retract_one(c, W.view(i), dir.view(i), alpha, Wn.view(i), &xo);
     }
     fa = evaluate(Wn, Gn, rvn);
     dfa = inner(c, Gn.views(), Xp.views());
@@ -504,10 +671,12 @@ bool Optimizer::advance() {
   if (!ok && !cg && hist.size() > 0) {
     hist.reset();
     slope = hist.step(c, Wv, G.views(), mp, dir.views());
+    if (expr) build_frames();
     ok = line_search(f, slope, 1.0, alpha);
   } else if (!ok && cg && momentum) {
     cg_restart(mp);
     slope = inner(c, G.views(), dir.views());
+    if (expr) build_frames();
     ok = line_search(f, slope, 1.0, alpha);
   }
   if (!ok) {
@@ -516,12 +685,13 @@ bool Optimizer::advance() {
     return true;
   }
   // Wn, Gn, rvn hold the accepted (last evaluated) point
+  // exponential transport uses E of the accepted alpha, the last one evaluated
+  const Lbfgs::Transport T = [&](int i, const MatView& in, const MatView& out) { transport_factor(i, in, out); };
   if (cg) {
     // previous direction and gradient carried to the new point by the transport; y = G_new - T(G_old)
     for (int i = 0; i < W.count(); ++i) {
-      MatView dv = cg_d.view(i), yv = cg_y.view(i);
-      stiefel_project_one(c, Wn.view(i), dir.view(i), dv);
-      stiefel_project_one(c, Wn.view(i), G.view(i), yv);
+      T(i, dir.view(i), cg_d.view(i));
+      T(i, G.view(i), cg_y.view(i));
     }
     axpby(c, 1.0, VPtr{Gn.ptr(), Prec::F64}, -1.0, VPtr{cg_y.ptr(), Prec::F64}, cg_y.total);
     cg_gold = gnorm;
@@ -529,7 +699,7 @@ bool Optimizer::advance() {
     cg_slope_prev = slope;
     cg_have = true;
   } else {
-    hist.push(c, Wn.views(), dir.views(), alpha, G.views(), Gn.views());
+    hist.push(c, T, dir.views(), alpha, G.views(), Gn.views());
   }
   std::swap(W.buf, Wn.buf);
   std::swap(G.buf, Gn.buf);

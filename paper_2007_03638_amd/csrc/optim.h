@@ -3,6 +3,7 @@
 // handles scalars (inner products, line-search decisions).
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "common.h"
@@ -36,6 +37,28 @@ void stiefel_project_one(Ctx& ctx, const MatView& W, const MatView& D, const Mat
 void stiefel_retract_one(Ctx& ctx, const MatView& W, const MatView& X, double alpha, const MatView& Wout,
                          const MatView* Xout);
 
+// G = (1 - W W^T) D: Grassmann tangent projection (eq. grassmann_gradient, real case)
+void grassmann_project_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& G);
+
+// Low-rank form of the generator Q_X of the exponential retraction and transport (Sec. 2.3, eqs. retraction and
+// transport): Q_X = U M U^T with U = [W Q], M = [[A, -B^T], [B, 0]], A = W^T X, Z = (1 - W W^T) X = Q B. Q spans
+// range(Z) (n x p, columns without a component of Z are zero and have zero rows of B); square W has no Q (m = p).
+// E = exp(alpha M) is set per alpha.
+struct ExpFrame {
+  int n = 0, p = 0, m = 0;
+  DevBuf Q, M, E;
+  double alpha = 0;
+  bool has_alpha = false;
+};
+void exp_frame_one(Ctx& ctx, const MatView& W, const MatView& X, ExpFrame& fr);
+void exp_set_alpha(Ctx& ctx, ExpFrame& fr, double alpha);
+// out = exp(alpha Q_X) Y = Y + U (E - 1) U^T Y  (out may alias Y)
+void exp_apply_one(Ctx& ctx, const MatView& W, const ExpFrame& fr, const MatView& Y, const MatView& out);
+// W_out = exp(alpha Q_X) W with one Newton-Schulz polar refinement (removes accumulated rounding), X_out (nullable)
+// = exp(alpha Q_X) X, the curve derivative. The frame must be built for (W, X).
+void exp_retract_one(Ctx& ctx, const MatView& W, const MatView& X, ExpFrame& fr, double alpha, const MatView& Wout,
+                     const MatView* Xout);
+
 // Eigendecompositions of the preconditioner metrics rho_v (one per factor).
 struct Metric {
   std::vector<DevBuf> V, lam, f, g;
@@ -61,6 +84,12 @@ struct Lbfgs {
   // two-loop recursion; returns slope <G, d>
   double step(Ctx& ctx, const std::vector<MatView>& W, const std::vector<MatView>& G, Metric* met,
               const std::vector<MatView>& dout);
+  // After an accepted step: transport the stored pairs with T, form s = T(alpha d), y = G_new - T(G_old), store the
+  // pair if <s, y> > 1e-12 |s||y|. T(i, in, out) transports factor i (out may alias in).
+  using Transport = std::function<void(int, const MatView&, const MatView&)>;
+  bool push(Ctx& ctx, const Transport& T, const std::vector<MatView>& d, double alpha,
+            const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew);
+  // Same with the projection transport onto the tangent spaces at Wn.
   bool push(Ctx& ctx, const std::vector<MatView>& Wn, const std::vector<MatView>& d, double alpha,
             const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew);
 };
@@ -82,6 +111,8 @@ struct JobSpec {
   double grad_tol = 1e-10, polish_tol = 0.0;
   bool precondition = true;
   int method = 0;                          // 0: L-BFGS, 1: nonlinear CG (Hager-Zhang)
+  int retraction = 0;                      // 0: polar + projection transport, 1: exponential (Sec. 2.3)
+  bool grassmann_w = false;                // isometries w on Grassmann manifolds (Sec. 4)
   KrylovOpts krylov;
   static JobSpec from_c(const mera_job& j);
 };
@@ -102,6 +133,8 @@ struct Optimizer {
   Metric met;
   // nonlinear CG state: previous direction transported to the current point, y = G - T(G_prev), scratch
   Flat cg_d, cg_y, cg_pg, cg_py;
+  std::vector<char> grass;        // factor i is a Grassmann point
+  std::vector<ExpFrame> frames;   // exponential retraction: generator of the current direction, per factor
   bool cg_have = false;
   double cg_gold = 0, cg_alpha_prev = 0, cg_slope_prev = 0;
   Prec prec = Prec::F64;
@@ -123,6 +156,10 @@ struct Optimizer {
   // the previous direction was used and `alpha0` to the first trial step
   double cg_direction(Metric* met, bool& momentum, double& alpha0);
   void cg_restart(Metric* met);   // dir = -P G
+  void project_factor(int i, const MatView& W, const MatView& D, const MatView& G);
+  void build_frames();            // exponential retraction frames for (W, dir)
+  // vector transport from W to the accepted point Wn (polar: projection at Wn; exponential: exp(alpha Q_dir))
+  void transport_factor(int i, const MatView& in, const MatView& out);
 };
 
 }  // namespace mera

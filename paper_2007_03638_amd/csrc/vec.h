@@ -35,6 +35,8 @@ int jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol
 void scale_sylvester(Ctx& ctx, double* m, const double* f, int dim);
 //   M_ij <- M_ij * s_j   (column scaling)
 void scale_cols(Ctx& ctx, double* m, const double* s, int64_t rows, int cols);
+//   dst[i * ldd + j] = a * src[i * lds + j] for a rows x cols block (row-major, strided)
+void copy_block(Ctx& ctx, double* dst, int64_t ldd, const double* src, int64_t lds, int rows, int cols, double a);
 //   f_i <- sqrt(lam_i^2 + delta^2), g_i <- 1/f_i
 void reg_spectrum(Ctx& ctx, const double* lam, double delta, double* f, double* g, int dim);
 

@@ -218,6 +218,15 @@ __global__ void scale_cols_kernel(double* m, const double* s, int64_t rows, int 
     m[t] *= s[t % cols];
 }
 
+__global__ void copy_block_kernel(double* dst, int64_t ldd, const double* src, int64_t lds, int rows, int cols,
+                                  double a) {
+  const int64_t n = (int64_t)rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t / cols, j = t - i * cols;
+    dst[i * ldd + j] = a * src[i * lds + j];
+  }
+}
+
 __global__ void reg_spectrum_kernel(const double* lam, double delta, double* f, double* g, int dim) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < dim) {
@@ -448,6 +457,13 @@ void scale_sylvester(Ctx& ctx, double* m, const double* f, int dim) {
 
 void scale_cols(Ctx& ctx, double* m, const double* s, int64_t rows, int cols) {
   hipLaunchKernelGGL(scale_cols_kernel, dim3(grid_for(rows * cols)), dim3(TPB), 0, ctx.stream, m, s, rows, cols);
+  MERA_HIP(hipGetLastError());
+}
+
+void copy_block(Ctx& ctx, double* dst, int64_t ldd, const double* src, int64_t lds, int rows, int cols, double a) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(copy_block_kernel, dim3(grid_for((int64_t)rows * cols)), dim3(TPB), 0, ctx.stream, dst, ldd, src,
+                     lds, rows, cols, a);
   MERA_HIP(hipGetLastError());
 }
 

@@ -27,6 +27,8 @@ def main():
     ap.add_argument("--grad-tol", type=float, default=1e-10)
     ap.add_argument("--m", type=int, default=8)
     ap.add_argument("--method", default="lbfgs", choices=["lbfgs", "cg"])
+    ap.add_argument("--retraction", default="polar", choices=["polar", "exp"])
+    ap.add_argument("--grassmann-w", action="store_true")
     ap.add_argument("--progress", type=int, default=0)
     ap.add_argument("--save", default="", help="write the final tensors to this .npz")
     a = ap.parse_args()
@@ -38,7 +40,8 @@ def main():
     h3 = api.h3_tfim(a.param) if a.model == "tfim" else api.h3_xxz(a.param)
     t0 = time.perf_counter()
     opt = ctx.optimizer(T=a.T, chi=a.chi, h3=h3, init=init, prec=a.prec, m=a.m, max_iter=a.iters,
-                        grad_tol=a.grad_tol, polish_tol=a.polish, method=a.method)
+                        grad_tol=a.grad_tol, polish_tol=a.polish, method=a.method, retraction=a.retraction,
+                        grassmann_w=a.grassmann_w)
     done, st = False, None
     history = []
     while not done:
@@ -51,7 +54,8 @@ def main():
     final = opt.final()
     if a.save:
         np.savez(a.save, *final)
-    out = dict(chi=a.chi, T=a.T, prec=a.prec, method=a.method, seed=a.seed, model=a.model, param=a.param,
+    out = dict(chi=a.chi, T=a.T, prec=a.prec, method=a.method, retraction=a.retraction, grassmann_w=a.grassmann_w,
+               seed=a.seed, model=a.model, param=a.param,
                energy=st["energy"], energy_per_spin=st["energy"] / 2, gnorm=st["gnorm"],
                iterations=st["iterations"], evaluations=st["evaluations"], status=st["status"],
                polish_iter=st["polish_iter"], seconds=dt, tflops=2 * st["macs"] / dt / 1e12,

@@ -89,3 +89,30 @@ def test_fp64_cg_trajectory_matches_oracle(ctx, precondition):
     W = got["final"]
     params = [(W[2 * i], W[2 * i + 1]) for i in range(T + 1)]
     assert abs(om.energy_only(params, h3, chi, T) - got["energy"]) <= 1e-12 * abs(got["energy"])
+
+
+@pytest.mark.parametrize("method,retraction,grassmann", [("lbfgs", "exp", False), ("cg", "exp", False),
+                                                          ("lbfgs", "exp", True), ("lbfgs", "polar", True)])
+def test_fp64_paper_geometry_trajectory_matches_oracle(ctx, method, retraction, grassmann):
+    """The paper's own geometry (exponential retraction and transport, Sec. 2.3; Grassmann isometries, Sec. 4)
+    against the oracle's drivers with the same options."""
+    chi, T, iters = 4, 2, 6
+    W0 = _init(2, chi, T)
+    h3 = model.tfim_h3(1.0)
+    prob = optim.Problem(h3, chi, T, grassmann_w=grassmann)
+    log = []
+    run = optim.optimize if method == "lbfgs" else optim.optimize_cg
+    _, f_ref, g_ref, info = run(W0, prob, max_iter=iters, log=log, retraction=retraction)
+    got = ctx.run_optimize(2, 4, h3, W0, prec="fp64", max_iter=iters, grad_tol=0.0, log_cap=64, want_final=True,
+                           method=method, retraction=retraction, grassmann_w=grassmann)
+    print("gpu", [(r["iter"], r["evals"], r["energy"]) for r in got["log"]], flush=True)
+    print("ref", [(r["iter"], r["evals"], r["energy"]) for r in log], flush=True)
+    assert len(got["log"]) >= len(log)
+    for a, b in zip(got["log"], log):
+        assert a["evals"] == b["evals"]
+        assert abs(a["energy"] - b["energy"]) <= 1e-10 * abs(b["energy"])
+        assert abs(a["gnorm"] - b["gnorm"]) <= 1e-7 * b["gnorm"]
+    assert abs(got["energy"] - f_ref) <= 1e-10 * abs(f_ref)
+    W = got["final"]
+    for w in W:
+        assert np.max(np.abs(w.T @ w - np.eye(w.shape[1]))) < 1e-13

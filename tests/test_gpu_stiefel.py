@@ -76,3 +76,47 @@ def test_precondition(ctx, delta):
 def test_inner(ctx):
     W, D = _case(5)
     assert abs(ctx.inner(W, D) - mf.inner(W, D)) < 1e-12 * max(1.0, abs(mf.inner(W, D)))
+
+
+EXP_SHAPES = SHAPES + [(12, 5), (9, 6)]   # adds 0 < n - p < p cases
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.37, 1.0, 3.0, -2.2])
+def test_exponential_retraction(ctx, alpha):
+    """eq. retraction (Sec. 2.3) on the GPU against the oracle's QR-based low-rank evaluation."""
+    W = [inputs.haar_params(20 + i, [s])[0] for i, s in enumerate(EXP_SHAPES)]
+    X = [mf.project(w, d) / np.linalg.norm(d) for w, d in zip(W, inputs.normal_like(21, W))]
+    Wo, Xo = ctx.stiefel_retract_exp(W, X, alpha)
+    for w, x, wo, xo in zip(W, X, Wo, Xo):
+        rw, rx = mf.retract_exp(w, x, alpha)
+        wo, xo = to_np(wo), to_np(xo)
+        print(f"exp retract {w.shape} alpha={alpha}: W err {rel(wo, rw):.2e} X' err {rel(xo, rx):.2e} "
+              f"orth {np.max(np.abs(wo.T @ wo - np.eye(w.shape[1]))):.2e}", flush=True)
+        assert np.max(np.abs(wo.T @ wo - np.eye(w.shape[1]))) < 1e-13
+        assert rel(wo, rw) < 1e-12
+        assert rel(xo, rx) < 1e-12
+
+
+def test_exponential_transport(ctx):
+    """eq. transport (Sec. 2.3): element-wise against the oracle, and inner products are preserved."""
+    W = [inputs.haar_params(30 + i, [s])[0] for i, s in enumerate(EXP_SHAPES)]
+    X = [mf.project(w, d) for w, d in zip(W, inputs.normal_like(31, W))]
+    Y = [mf.project(w, d) for w, d in zip(W, inputs.normal_like(32, W))]
+    T = ctx.stiefel_transport_exp(W, X, 0.8, Y)
+    for w, x, y, t in zip(W, X, Y, T):
+        t = to_np(t)
+        assert rel(t, mf.transport_exp(w, x, 0.8, y)) < 1e-12
+        assert abs(np.sum(t * t) - np.sum(y * y)) <= 1e-12 * np.sum(y * y)
+
+
+def test_grassmann_projection_and_geodesic(ctx):
+    W = [inputs.haar_params(40 + i, [s])[0] for i, s in enumerate(EXP_SHAPES) if s[0] > s[1]]
+    D = inputs.normal_like(41, W)
+    G = ctx.grassmann_project(W, D)
+    for w, d, g in zip(W, D, G):
+        assert rel(to_np(g), mf.grassmann_project(w, d)) < 1e-13
+    # a horizontal direction (A = 0): the GPU curve is the oracle's Grassmann geodesic
+    X = [mf.grassmann_project(w, d) / np.linalg.norm(d) for w, d in zip(W, D)]
+    Wo = ctx.stiefel_retract_exp(W, X, 1.3, tangent=False)
+    for w, x, wo in zip(W, X, Wo):
+        assert rel(to_np(wo), mf.retract_exp(w, x, 1.3)[0]) < 1e-12
