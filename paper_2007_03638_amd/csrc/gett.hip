@@ -193,33 +193,9 @@ __global__ void __launch_bounds__(256, 2) gett_kernel(Args g) {
 
   auto kloop = [&](auto mask_tag) {
     constexpr bool MASK = decltype(mask_tag)::value;
-    int buf = 0;
-    if (kb < ke) {
-      la.fetch_k(g.a_k, kb);
-      lb.fetch_k(g.b_k, kb);
-      la.template load<MASK>(A, kb, ke);
-      lb.template load<MASK>(B, kb, ke);
-      if (kb + BK < ke) {
-        la.fetch_k(g.a_k, kb + BK);
-        lb.fetch_k(g.b_k, kb + BK);
-      }
-    }
-    for (int64_t kt = kb; kt < ke; kt += BK) {
-      la.template store<LDA, MASK>(As[buf]);
-      lb.template store<LDB, MASK>(Bs[buf]);
-      __syncthreads();
-      if (kt + BK < ke) {
-        la.template load<MASK>(A, kt + BK, ke);
-        lb.template load<MASK>(B, kt + BK, ke);
-        if (kt + 2 * BK < ke) {
-          la.fetch_k(g.a_k, kt + 2 * BK);
-          lb.fetch_k(g.b_k, kt + 2 * BK);
-        }
-      }
-      const T* as = As[buf];
-      const T* bs = Bs[buf];
+    auto mfma_steps = [&](const T* as, const T* bs, int k_lo, int k_hi) {
 #pragma unroll
-      for (int ks = 0; ks < BK; ks += F::KT) {
+      for (int ks = k_lo; ks < k_hi; ks += F::KT) {
         T af[FM], bf[FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i) af[i] = as[(ks + lane / F::MT) * LDA + wm + i * F::MT + lane % F::MT];
@@ -230,6 +206,47 @@ __global__ void __launch_bounds__(256, 2) gett_kernel(Args g) {
 #pragma unroll
           for (int j = 0; j < FN; ++j) acc[i][j] = F::mma(af[i], bf[j], acc[i][j]);
       }
+    };
+    int buf = 0;
+    if (kb < ke) {
+      la.fetch_k(g.a_k, kb);
+      lb.fetch_k(g.b_k, kb);
+      la.template load<MASK>(A, kb, ke);
+      lb.template load<MASK>(B, kb, ke);
+      la.template store<LDA, MASK>(As[0]);
+      lb.template store<LDB, MASK>(Bs[0]);
+      if (kb + BK < ke) {
+        la.fetch_k(g.a_k, kb + BK);
+        lb.fetch_k(g.b_k, kb + BK);
+        la.template load<MASK>(A, kb + BK, ke);
+        lb.template load<MASK>(B, kb + BK, ke);
+        if (kb + 2 * BK < ke) {
+          la.fetch_k(g.a_k, kb + 2 * BK);
+          lb.fetch_k(g.b_k, kb + 2 * BK);
+        }
+      }
+    }
+    __syncthreads();
+    // tile t is read from LDS buffer t&1 while tile t+1 (in registers) is stored to the other buffer halfway
+    // through, and tile t+2 is fetched into registers; one barrier per tile
+    for (int64_t kt = kb; kt < ke; kt += BK) {
+      const T* as = As[buf];
+      const T* bs = Bs[buf];
+      mfma_steps(as, bs, 0, BK / 2);
+      if (kt + BK < ke) {
+        la.template store<LDA, MASK>(As[buf ^ 1]);
+        lb.template store<LDB, MASK>(Bs[buf ^ 1]);
+        if (kt + 2 * BK < ke) {
+          la.template load<MASK>(A, kt + 2 * BK, ke);
+          lb.template load<MASK>(B, kt + 2 * BK, ke);
+          if (kt + 3 * BK < ke) {
+            la.fetch_k(g.a_k, kt + 3 * BK);
+            lb.fetch_k(g.b_k, kt + 3 * BK);
+          }
+        }
+      }
+      mfma_steps(as, bs, BK / 2, BK);
+      __syncthreads();
       buf ^= 1;
     }
   };

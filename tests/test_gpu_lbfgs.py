@@ -48,7 +48,7 @@ def test_two_loop_sequence_matches_oracle(ctx, precondition):
         Gn = [mf.project(w, x) for w, x in zip(Wn, inputs.normal_like(100 + k, Wn))]
         s = [mf.transport(w, alpha * x) for w, x in zip(Wn, d_ref)]
         y = [gn - mf.transport(w, g) for w, gn, g in zip(Wn, Gn, G)]
-        hist.transport(Wn)
+        hist.transport(lambda X, _Wn=Wn: [mf.transport(w, x) for w, x in zip(_Wn, X)])
         acc_ref = hist.push(s, y)
         acc = lb.push(Wn, d_ref, alpha, G, Gn)
         assert acc == acc_ref
