@@ -292,14 +292,18 @@ __global__ void __launch_bounds__(256, 2) gett_kernel(Args g) {
       rv[r] = row < g.M;
     }
     if (g.beta != 0.0) {
+      // all reads of C first, unconditionally (padded table entries address element 0 of a valid row or
+      // column), so they are in flight together; then the masked read-modify-write stores
+      T cold[FN][F::NACC];
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < F::NACC; ++r) cold[j][r] = C[cm[r] + cn[j]];
 #pragma unroll
       for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int r = 0; r < F::NACC; ++r)
-          if (cv[j] && rv[r]) {
-            const int64_t o = cm[r] + cn[j];
-            C[o] = alpha * acc[i][j][r] + beta * C[o];
-          }
+          if (cv[j] && rv[r]) C[cm[r] + cn[j]] = alpha * acc[i][j][r] + beta * cold[j][r];
     } else {
 #pragma unroll
       for (int j = 0; j < FN; ++j)
@@ -447,15 +451,22 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
       cm[r] = g.c_m[row];
       rv[r] = row < g.M;
     }
+    float cold[FN][4];
+    if (g.beta != 0.0) {
+      // unconditional reads first (padded table entries address a valid element), then the masked stores
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cold[j][r] = C[cm[r] + cn[j]];
+    }
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (cv[j] && rv[r]) {
-          const int64_t o = cm[r] + cn[j];
           float v = alpha * acc[i][j][r];
-          if (g.beta != 0.0) v += beta * C[o];
-          C[o] = v;
+          if (g.beta != 0.0) v += beta * cold[j][r];
+          C[cm[r] + cn[j]] = v;
         }
   }
 }

@@ -33,7 +33,9 @@ namespace {
 // Leg orders of the intermediates are chosen so that in every chi^9 step each operand is read along a
 // unit-stride run: an operand read along M (or N) has its M (N) legs innermost, and when both operands are
 // read along K their K legs appear in the same order in both (UWb is the bra composite stored in the order
-// the descending step needs).
+// the descending step needs). The same holds for the K = chi^4 environment reductions of the derivative
+// programs (Du, dW1, dW3): T1 and dT5 are stored with their contracted legs in the order and unit-stride leg
+// of the other operand.
 // The steps between "@loop" and "@end" may run in chunks of a spectator leg (h for the L diagram, e for the R
 // diagram: neither is contracted by a chi^9 step) to bound the two 7-leg intermediates at large chi.
 const char* const kAscL[] = {
@@ -98,20 +100,20 @@ const char* const kGradL[] = {
     "UWb[dAGEQ] = u[dAEF] * w[FGQ]",
     "@zero dW1 dUW",
     "@loop h",
-    "T1[aABCgh] = h[abcABC] * u[bcgh]",
-    "T2[aghHAG] = T1[aABCgh] * u[BCGH]",
+    "T1[BChAag] = h[abcABC] * u[bcgh]",
+    "T2[aghHAG] = T1[BChAag] * u[BCGH]",
     "T3[hHAGdeq] = T2[aghHAG] * UW[daegq]",
     "T4[hHeqEQ] = T3[hHAGdeq] * UW[dAEGQ]",
     "T5[hHqQpP] = T4[hHeqEQ] * W1[epEP]",
-    "dT5[pqPQhH] = rho[pqrPQR] * W3[hrHR]",
+    "dT5[pPhHqQ] = rho[pqrPQR] * W3[hrHR]",
     "dW3[hHrR] = T5[hHqQpP] * rho[pqrPQR]",
-    "dT4[qhHeEQ] = dT5[pqPQhH] * W1[epEP]",
-    "dW1[eEpP] += T4[hHeqEQ] * dT5[pqPQhH]",
+    "dT4[qhHeEQ] = dT5[pPhHqQ] * W1[epEP]",
+    "dW1[eEpP] += T4[hHeqEQ] * dT5[pPhHqQ]",
     "dT3[qhHedAG] = dT4[qhHeEQ] * UWb[dAGEQ]",
     "dUW[agqed] += T2[aghHAG] * dT3[qhHedAG]",
     "dT2[hHAGag] = dT3[qhHedAG] * UW[daegq]",
     "dT1[hAagBC] = dT2[hHAGag] * u[BCGH]",
-    "Du[BCGH] += T1[aABCgh] * dT2[hHAGag]",
+    "Du[BCGH] += T1[BChAag] * dT2[hHAGag]",
     "rhoout[abcABC] += 0.5 * dT1[hAagBC] * u[bcgh]",
     "Dw[hyr] += dW3[hHrR] * w[HyR]",
     "@end",
@@ -131,10 +133,10 @@ const char* const kGradR[] = {
     "T3[eECFdhq] = T2[cfeECF] * UW[cdhfq]",
     "T4[eEhqHQ] = T3[eECFdhq] * UW[CdHFQ]",
     "T5[eEqQrR] = T4[eEhqHQ] * W3[hrHR]",
-    "dT5[qrQReE] = rho[pqrPQR] * W1[epEP]",
+    "dT5[rReEqQ] = rho[pqrPQR] * W1[epEP]",
     "dW1[eEpP] = T5[eEqQrR] * rho[pqrPQR]",
-    "dT4[qeEhHQ] = dT5[qrQReE] * W3[hrHR]",
-    "dW3[hHrR] += T4[eEhqHQ] * dT5[qrQReE]",
+    "dT4[qeEhHQ] = dT5[rReEqQ] * W3[hrHR]",
+    "dW3[hHrR] += T4[eEhqHQ] * dT5[rReEqQ]",
     "dT3[qeEhdCF] = dT4[qeEhHQ] * UWb[dCFHQ]",
     "dUW[cfqhd] += T2[cfeECF] * dT3[qeEhdCF]",
     "dT2[eECFcf] = dT3[qeEhdCF] * UW[cdhfq]",
