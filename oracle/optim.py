@@ -12,6 +12,10 @@ Sec. 3 of the paper. Readings where the paper leaves details open (constants are
     Hessian gamma * P with P the preconditioner and gamma = <s, y> / <y, P y> from the newest pair;
     s_k = T(alpha d_k), y_k = G_{k+1} - T(G_k); a pair with <s, y> <= 1e-12 |s| |y| is not stored; if the
     direction is not a descent direction the history is dropped and d = -P(G).
+  * Evenbly-Vidal update (App. A) as the comparator: for one tensor W with environment D (the Euclidean
+    derivative) and rho its reduced density matrix on the top legs, the shifted environment D_gamma = D - gamma W rho
+    and W <- polar(-D_gamma); gamma is the free shift of the Hamiltonian, acting as an inverse step size. A sweep
+    updates u_1, w_1, ..., u_s, w_s in turn, each with a fresh environment.
   * Nonlinear conjugate gradient (Sec. 3, with the Hager-Zhang coefficient the paper uses): d_{k+1} = -P G_{k+1}
     + beta_k T(d_k), inner products in the metric, the previous direction carried over by the transport; beta_k in
     the preconditioned Hager-Zhang form <y, P g>/<d, y> - 2 <y, P y> <d, g>/<d, y>^2 (y = G_{k+1} - T(G_k), d the
@@ -137,6 +141,7 @@ class Problem:
         G = [self.project(i, w, dd) for i, (w, dd) in enumerate(zip(W, D))]
         rdms = om.preconditioner_rdms(ev['rhos'], params, self.dims)
         rv = [m for pair in rdms for m in pair]
+        self.last_D = D
         return ev['energy'], G, rv
 
 
@@ -288,6 +293,36 @@ def optimize_cg(W0, problem, max_iter=200, grad_tol=1e-10, use_precond=True, ls_
         g_old_norm = gnorm
         alpha_prev, slope_prev = alpha, slope
         W, f, G, rv = Wn, fn, Gn, rvn
+    else:
+        it = max_iter
+    gnorm = math.sqrt(mf.inner(G, G))
+    return W, f, gnorm, dict(iterations=it, evals=problem.evals, status=status)
+
+
+def ev_update(W, D, rho, gamma):
+    """Evenbly-Vidal local update (App. A): the polar factor of -D_gamma = gamma W rho - D."""
+    return mf.polar_factor(gamma * W @ rho - D)
+
+
+def optimize_ev(W0, problem, gamma, max_iter=20, grad_tol=0.0, log=None):
+    """Evenbly-Vidal sweeps (App. A): each iteration updates every tensor in turn (u_1, w_1, ..., u_s, w_s), each
+    from a fresh evaluation of its environment. Returns (W, energy, |G|, info)."""
+    W = [w.copy() for w in W0]
+    f, G, rv = problem.evaluate(W)
+    it = 0
+    status = 'maxiter'
+    for it in range(max_iter):
+        gnorm = math.sqrt(mf.inner(G, G))
+        if log is not None:
+            log.append(dict(iter=it, energy=f, gnorm=gnorm, evals=problem.evals))
+        if gnorm <= grad_tol:
+            status = 'converged'
+            break
+        for i in range(len(W)):
+            if i > 0:
+                f, G, rv = problem.evaluate(W)
+            W[i] = ev_update(W[i], problem.last_D[i], rv[i], gamma)
+        f, G, rv = problem.evaluate(W)
     else:
         it = max_iter
     gnorm = math.sqrt(mf.inner(G, G))

@@ -188,3 +188,37 @@ def test_exponential_retraction_runs(method, grassmann):
         _, G, _ = prob.evaluate(W)
         for i in range(1, len(W), 2):
             assert np.max(np.abs(W[i].T @ G[i])) < 1e-12
+
+
+def test_ev_update_fixed_point_and_small_step_limit():
+    """App. A: W is a fixed point when D = W P (P symmetric, gamma rho - P positive definite); for large gamma the
+    update is preconditioned gradient descent, W' = W - G~/gamma + O(1/gamma^2), with G~ the gradient G = P_W(D)
+    preconditioned by rho (eq. preconditioner_solution with delta = 0)."""
+    rng = np.random.default_rng(8)
+    n, p = 14, 5
+    W = inputs.haar_params(8, [(n, p)])[0]
+    rho = inputs.density_matrix(9, p) + 0.05 * np.eye(p)
+    R = rng.standard_normal((p, p))
+    P = 5.0 * rho - (R @ R.T + 0.1 * np.eye(p))             # gamma rho - P symmetric positive definite
+    assert np.allclose(optim.ev_update(W, W @ P, rho, 5.0), W, atol=1e-13)
+    G = mf.project(W, rng.standard_normal((n, p)))          # a pure gradient, W^T G skew
+    Gt = mf.precondition(W, G, rho, delta=0.0)
+    errs = []
+    for gamma in (1e3, 2e3, 4e3):
+        errs.append(np.linalg.norm(optim.ev_update(W, G, rho, gamma) - (W - Gt / gamma)))
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5   # second order in 1/gamma
+
+
+def test_ev_sweeps_decrease_energy():
+    chi, T = 4, 2
+    dims = mera.layer_dims(chi, T)
+    W0 = [m for pair in inputs.mera_init(0, dims) for m in pair]
+    prob = optim.Problem(model.tfim_h3(1.0), chi, T)
+    log = []
+    W, f, gnorm, info = optim.optimize_ev(W0, prob, gamma=20.0, max_iter=3, log=log)
+    energies = [r['energy'] for r in log] + [f]
+    assert all(b <= a + 1e-12 for a, b in zip(energies, energies[1:]))
+    assert f / 2 > model.tfim_exact_energy_per_spin(1.0)
+    assert info['evals'] == 1 + 3 * 2 * (T + 1)
+    for w in W:
+        assert np.max(np.abs(w.T @ w - np.eye(w.shape[1]))) < 1e-13
