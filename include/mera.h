@@ -178,6 +178,12 @@ mera_status stiefel_retract_exp(mera_ctx* ctx, int count, const mera_mat* W, con
  * X by alpha; it preserves inner products. Y_out may alias Y. */
 mera_status stiefel_transport_exp(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* X, double alpha,
                                   const mera_mat* Y, mera_mat* Y_out);
+/* Evenbly-Vidal local update (App. A): W_out = polar(gamma W rho - D) = polar(-D_gamma), D the Euclidean derivative
+ * (environment) of the energy with respect to W, rho its p x p reduced density matrix on the top legs, gamma > 0 the
+ * shift of H - gamma. The polar factor is Y (Y^T Y)^{-1/2} from the FP64 Jacobi eigendecomposition, refined by one
+ * Newton-Schulz step. MERA_ENONFINITE when gamma W rho - D is rank deficient. W_out must not alias W or D. */
+mera_status mera_ev_update(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, const mera_mat* rho,
+                           double gamma, mera_mat* W_out);
 /* Grassmann tangent projection (Sec. 2.2, eq. grassmann_gradient, real case): G = (1 - W W^T) D. G may alias D. */
 mera_status grassmann_project(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, mera_mat* G);
 /* Hilbert-space preconditioner (Sec. 3 eqs. preconditioner / preconditioner_solution): X = W A + W_perp B
@@ -221,11 +227,14 @@ typedef struct {
   mera_krylov_opts krylov;
   int method;                      /* 0: L-BFGS (Sec. 3); 1: nonlinear conjugate gradient with the           */
                                    /* preconditioned Hager-Zhang coefficient (Sec. 3), the previous         */
-                                   /* direction carried over by the transport; lbfgs_m is then ignored     */
+                                   /* direction carried over by the transport; lbfgs_m is then ignored;     */
+                                   /* 2: Evenbly-Vidal sweeps (App. A), one iteration = one sweep updating   */
+                                   /* u_1, w_1, ..., u_s, w_s in turn from fresh environments                */
   int retraction;                  /* 0: polar retraction + projection transport; 1: the paper's            */
                                    /* exponential retraction and transport (Sec. 2.3)                       */
   int grassmann_w;                 /* 1: isometries w on Grassmann manifolds (Sec. 4): Grassmann gradient    */
                                    /* projection and projection transport for the w factors                 */
+  double ev_gamma;                 /* method 2: shift gamma of H - gamma (inverse step size, App. A), > 0    */
 } mera_job;
 
 typedef struct {

@@ -31,7 +31,7 @@ class Job(ctypes.Structure):
                 ("init_host", ctypes.POINTER(ctypes.POINTER(c_double))), ("prec", c_int), ("lbfgs_m", c_int),
                 ("max_iter", c_int), ("grad_tol", c_double), ("polish_tol", c_double), ("precondition", c_int),
                 ("max_ls_evals", c_int), ("krylov", KrylovOpts), ("method", c_int), ("retraction", c_int),
-                ("grassmann_w", c_int)]
+                ("grassmann_w", c_int), ("ev_gamma", c_double)]
 
 
 class Result(ctypes.Structure):
@@ -82,6 +82,7 @@ SIGNATURES = {
     "stiefel_retract_exp": (c_int, [c_void_p, c_int, MAT_P, MAT_P, c_double, MAT_P, MAT_P]),
     "stiefel_transport_exp": (c_int, [c_void_p, c_int, MAT_P, MAT_P, c_double, MAT_P, MAT_P]),
     "grassmann_project": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P]),
+    "mera_ev_update": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P, c_double, MAT_P]),
     "stiefel_precondition": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P, c_double, MAT_P]),
     "mera_inner": (c_int, [c_void_p, c_int, MAT_P, MAT_P, ctypes.POINTER(c_double)]),
     "lbfgs_create": (c_int, [c_void_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int), c_int,

@@ -224,6 +224,15 @@ class Context:
                                                     _mats(Yo)), "stiefel_transport_exp")
         return Yo
 
+    def ev_update(self, W, D, rho, gamma):
+        W = [self._dev(x) for x in W]
+        D = [self._dev(x) for x in D]
+        R = [self._dev(x) for x in rho]
+        Wo = [torch.empty_like(x) for x in W]
+        self._check(self._lib.mera_ev_update(self.ptr, len(W), _mats(W), _mats(D), _mats(R), float(gamma),
+                                             _mats(Wo)), "mera_ev_update")
+        return Wo
+
     def grassmann_project(self, W, D):
         W = [self._dev(x) for x in W]
         D = [self._dev(x) for x in D]
@@ -254,9 +263,9 @@ class Context:
     # ---- whole optimisation -------------------------------------------------------------------------------
     def run_optimize(self, T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, polish_tol=0.0,
                      precondition=True, max_ls_evals=10, krylov=None, d=4, log_cap=0, want_final=False,
-                     method="lbfgs", retraction="polar", grassmann_w=False):
+                     method="lbfgs", retraction="polar", grassmann_w=False, ev_gamma=0.0):
         job, keep = make_job(T, chi, h3, init, prec, m, max_iter, grad_tol, polish_tol, precondition,
-                             max_ls_evals, krylov, d, method, retraction, grassmann_w)
+                             max_ls_evals, krylov, d, method, retraction, grassmann_w, ev_gamma)
         res = L.Result()
         logs = (L.IterLog * max(log_cap, 1))()
         nlog = ctypes.c_int(0)
@@ -285,7 +294,8 @@ def result_dict(res):
 
 
 def make_job(T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, polish_tol=0.0, precondition=True,
-             max_ls_evals=10, krylov=None, d=4, method="lbfgs", retraction="polar", grassmann_w=False):
+             max_ls_evals=10, krylov=None, d=4, method="lbfgs", retraction="polar", grassmann_w=False,
+             ev_gamma=0.0):
     """Build a mera_job; returns (job, keepalive) — keep the second item alive while the job is in use."""
     h3c = np.ascontiguousarray(h3, dtype=np.float64)
     mats = [np.ascontiguousarray(x, dtype=np.float64) for x in init]
@@ -295,7 +305,8 @@ def make_job(T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, p
     job = L.Job(_shape(T, chi, d), h3c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ptrs, _prec(prec), m,
                 max_iter, grad_tol, polish_tol, 1 if precondition else 0, max_ls_evals,
                 L.KrylovOpts(kr.get("dim", 0), kr.get("max_restarts", 0), kr.get("tol", 0.0)),
-                {"lbfgs": 0, "cg": 1}[method], {"polar": 0, "exp": 1}[retraction], 1 if grassmann_w else 0)
+                {"lbfgs": 0, "cg": 1, "ev": 2}[method], {"polar": 0, "exp": 1}[retraction],
+                1 if grassmann_w else 0, float(ev_gamma))
     return job, (h3c, mats, ptrs)
 
 

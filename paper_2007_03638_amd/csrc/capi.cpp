@@ -395,6 +395,30 @@ mera_status stiefel_transport_exp(mera_ctx* ctx, int count, const mera_mat* W, c
   });
 }
 
+mera_status mera_ev_update(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, const mera_mat* rho,
+                           double gamma, mera_mat* W_out) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(count >= 0 && std::isfinite(gamma) && gamma > 0.0, MERA_EINVAL, "count/gamma");
+    check_isometry_shapes(W, count, "mera_ev_update W");
+    check_mats(D, count, "mera_ev_update D");
+    check_mats(rho, count, "mera_ev_update rho");
+    check_mats(W_out, count, "mera_ev_update W_out");
+    same_shapes(W, D, count, "mera_ev_update");
+    same_shapes(W, W_out, count, "mera_ev_update");
+    for (int i = 0; i < count; ++i) {
+      MERA_CHECK(rho[i].n == W[i].p && rho[i].p == W[i].p, MERA_EINVAL, "rho must be p x p");
+      MERA_CHECK(W_out[i].data != W[i].data && W_out[i].data != D[i].data, MERA_EINVAL,
+                 "mera_ev_update: W_out aliases an input");
+    }
+    DeviceGuard g(ctx->c.device);
+    for (int i = 0; i < count; ++i)
+      ev_update_one(ctx->c, MatView{W[i].n, W[i].p, W[i].data}, MatView{D[i].n, D[i].p, D[i].data},
+                    MatView{rho[i].n, rho[i].p, rho[i].data}, gamma, MatView{W_out[i].n, W_out[i].p, W_out[i].data});
+    ctx->c.sync();
+  });
+}
+
 mera_status grassmann_project(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, mera_mat* G) {
   if (!ctx) return MERA_EINVAL;
   return guarded(ctx, [&] {

@@ -261,6 +261,50 @@ void exp_retract_one(Ctx& ctx, const MatView& W, const MatView& X, ExpFrame& fr,
   mm(ctx, "Wo[nq] = Wt[np] * S[pq]", {{'n', n}, {'p', p}, {'q', p}}, {{"Wo", Wout.data}, {"Wt", Wt}, {"S", S}});
 }
 
+// ---- Evenbly-Vidal update (App. A) ------------------------------------------------------------------------
+
+void ev_update_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& rho, double gamma,
+                   const MatView& Wout) {
+  const int n = W.n, p = W.p;
+  const int64_t np_ = (int64_t)n * p, pp = (int64_t)p * p;
+  const std::initializer_list<std::pair<char, int64_t>> dnp = {{'n', n}, {'p', p}, {'q', p}};
+  const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', p}, {'q', p}, {'r', p}};
+  double* Y = tmp(ctx, "ev.Y", np_);
+  mm(ctx, "Y[nq] = W[np] * R[pq]", dnp, {{"Y", Y}, {"W", W.data}, {"R", rho.data}});
+  axpby(ctx, -1.0, d64(D), gamma, VPtr{Y, Prec::F64}, np_);   // Y = gamma W rho - D
+  double* K = tmp(ctx, "ev.K", pp);
+  mm(ctx, "K[pq] = Y[np] * Y2[nq]", dnp, {{"K", K}, {"Y", Y}, {"Y2", Y}});
+  symmetrize(ctx, VPtr{K, Prec::F64}, p);
+  double* lam = tmp(ctx, "ev.lam", p);
+  double* V = tmp(ctx, "ev.V", pp);
+  jacobi_eigh(ctx, K, lam, V, p);
+  std::vector<double> hl(p);
+  MERA_HIP(hipMemcpyAsync(hl.data(), lam, (size_t)p * 8, hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  double lmax = 0.0;
+  for (double x : hl) lmax = std::max(lmax, x);
+  for (double& x : hl) {
+    MERA_CHECK(std::isfinite(x) && x > 1e-28 * lmax && x > 0.0, MERA_ENONFINITE,
+               "Evenbly-Vidal update: gamma W rho - D is rank deficient");
+    x = 1.0 / std::sqrt(x);
+  }
+  double* sdev = tmp(ctx, "ev.s", p);
+  MERA_HIP(hipMemcpyAsync(sdev, hl.data(), (size_t)p * 8, hipMemcpyHostToDevice, ctx.stream));
+  double* T = tmp(ctx, "ev.T", pp);
+  double* Z = tmp(ctx, "ev.Z", pp);
+  copy(ctx, VPtr{T, Prec::F64}, VPtr{V, Prec::F64}, pp);
+  scale_cols(ctx, T, sdev, p, p);
+  ctx.sync();  // hl is host memory read by the copy above
+  mm(ctx, "Z[pq] = T[pr] * V[qr]", dpp, {{"Z", Z}, {"T", T}, {"V", V}});   // (Y^T Y)^{-1/2}
+  double* Wt = tmp(ctx, "ev.W", np_);
+  mm(ctx, "Wt[nq] = Y[np] * Z[pq]", dnp, {{"Wt", Wt}, {"Y", Y}, {"Z", Z}});
+  // one Newton-Schulz polar refinement: W <- W (3 - W^T W)/2
+  mm(ctx, "S[pq] = Wt[np] * Wt2[nq]", dnp, {{"S", T}, {"Wt", Wt}, {"Wt2", Wt}});
+  scal(ctx, -0.5, VPtr{T, Prec::F64}, pp);
+  add_diag(ctx, VPtr{T, Prec::F64}, p, 1.5);
+  mm(ctx, "Wo[nq] = Wt[np] * S[pq]", dnp, {{"Wo", Wout.data}, {"Wt", Wt}, {"S", T}});
+}
+
 void Metric::compute(Ctx& ctx, const std::vector<MatView>& rho) {
   const size_t k = rho.size();
   V.resize(k);
@@ -488,8 +532,11 @@ JobSpec JobSpec::from_c(const mera_job& j) {
   s.polish_tol = j.polish_tol;
   s.precondition = j.precondition != 0;
   s.max_ls_evals = j.max_ls_evals > 0 ? j.max_ls_evals : 10;
-  MERA_CHECK(j.method == 0 || j.method == 1, MERA_EINVAL, "job: method must be 0 (L-BFGS) or 1 (CG)");
+  MERA_CHECK(j.method >= 0 && j.method <= 2, MERA_EINVAL, "job: method must be 0 (L-BFGS), 1 (CG) or 2 (EV)");
   s.method = j.method;
+  MERA_CHECK(j.method != 2 || (std::isfinite(j.ev_gamma) && j.ev_gamma > 0.0), MERA_EINVAL,
+             "job: Evenbly-Vidal needs a positive ev_gamma");
+  s.ev_gamma = j.ev_gamma;
   MERA_CHECK(j.retraction == 0 || j.retraction == 1, MERA_EINVAL, "job: retraction must be 0 (polar) or 1 (exp)");
   s.retraction = j.retraction;
   s.grassmann_w = j.grassmann_w != 0;
@@ -550,7 +597,7 @@ double Optimizer::evaluate(const Flat& X, Flat& Gout, Flat& rvout) {
     pt.w.push_back(X.view(2 * t + 1).data);
     go.Du.push_back(D.view(2 * t).data);
     go.Dw.push_back(D.view(2 * t + 1).data);
-    if (job.precondition) {
+    if (need_rv()) {
       go.rho_u.push_back(rvout.view(2 * t).data);
       go.rho_w.push_back(rvout.view(2 * t + 1).data);
     }
@@ -600,6 +647,10 @@ bool Optimizer::advance() {
     f = evaluate(W, G, rv);
     if (job.precondition) met.compute(c, rv.views());
     return false;  // the iteration restarts from the re-evaluated point
+  }
+  if (job.method == 2) {
+    ev_sweep();
+    return false;
   }
   Metric* mp = job.precondition ? &met : nullptr;
   const auto Wv = W.views();
@@ -709,6 +760,20 @@ bool Optimizer::advance() {
   iter++;
   if (job.precondition) met.compute(c, rv.views());
   return false;
+}
+
+void Optimizer::ev_sweep() {
+  Ctx& c = *ctx;
+  // u_1, w_1, ..., u_s, w_s in turn, each from a fresh environment (the first reuses the current evaluation)
+  for (int i = 0; i < W.count(); ++i) {
+    if (i > 0) f = evaluate(W, G, rv);
+    ev_update_one(c, W.view(i), D.view(i), rv.view(i), job.ev_gamma, Wn.view(i));
+    copy(c, d64(W.view(i)), d64(Wn.view(i)), (int64_t)W.view(i).n * W.view(i).p);
+  }
+  f = evaluate(W, G, rv);
+  if (job.precondition) met.compute(c, rv.views());
+  last_alpha = 0.0;
+  iter++;
 }
 
 void Optimizer::cg_restart(Metric* met) {

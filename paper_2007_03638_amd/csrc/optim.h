@@ -59,6 +59,12 @@ void exp_apply_one(Ctx& ctx, const MatView& W, const ExpFrame& fr, const MatView
 void exp_retract_one(Ctx& ctx, const MatView& W, const MatView& X, ExpFrame& fr, double alpha, const MatView& Wout,
                      const MatView* Xout);
 
+// Evenbly-Vidal local update (App. A): W_out = polar(gamma W rho - D), the polar factor of minus the environment
+// of the shifted Hamiltonian H - gamma; polar(Y) = Y (Y^T Y)^{-1/2} from the FP64 Jacobi eigendecomposition of
+// Y^T Y, then one Newton-Schulz refinement. W_out must not alias W or D.
+void ev_update_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& rho, double gamma,
+                   const MatView& Wout);
+
 // Eigendecompositions of the preconditioner metrics rho_v (one per factor).
 struct Metric {
   std::vector<DevBuf> V, lam, f, g;
@@ -110,7 +116,8 @@ struct JobSpec {
   int m = 8, max_iter = 100, max_ls_evals = 10;
   double grad_tol = 1e-10, polish_tol = 0.0;
   bool precondition = true;
-  int method = 0;                          // 0: L-BFGS, 1: nonlinear CG (Hager-Zhang)
+  int method = 0;                          // 0: L-BFGS, 1: nonlinear CG (Hager-Zhang), 2: Evenbly-Vidal sweeps
+  double ev_gamma = 0.0;                   // Evenbly-Vidal shift (inverse step size)
   int retraction = 0;                      // 0: polar + projection transport, 1: exponential (Sec. 2.3)
   bool grassmann_w = false;                // isometries w on Grassmann manifolds (Sec. 4)
   KrylovOpts krylov;
@@ -152,6 +159,8 @@ struct Optimizer {
 
  private:
   double evaluate(const Flat& X, Flat& Gout, Flat& rvout);   // energy; fills G = P(D) and metrics
+  bool need_rv() const { return job.precondition || job.method == 2; }
+  void ev_sweep();                // one Evenbly-Vidal sweep over all tensors
   // CG direction into `dir` (Sec. 3, Hager-Zhang coefficient); returns the slope <G, dir>, sets `momentum` when
   // the previous direction was used and `alpha0` to the first trial step
   double cg_direction(Metric* met, bool& momentum, double& alpha0);

@@ -26,7 +26,8 @@ def main():
     ap.add_argument("--polish", type=float, default=0.0)
     ap.add_argument("--grad-tol", type=float, default=1e-10)
     ap.add_argument("--m", type=int, default=8)
-    ap.add_argument("--method", default="lbfgs", choices=["lbfgs", "cg"])
+    ap.add_argument("--method", default="lbfgs", choices=["lbfgs", "cg", "ev"])
+    ap.add_argument("--ev-gamma", type=float, default=20.0, help="Evenbly-Vidal shift (method ev)")
     ap.add_argument("--retraction", default="polar", choices=["polar", "exp"])
     ap.add_argument("--grassmann-w", action="store_true")
     ap.add_argument("--progress", type=int, default=0)
@@ -41,7 +42,7 @@ def main():
     t0 = time.perf_counter()
     opt = ctx.optimizer(T=a.T, chi=a.chi, h3=h3, init=init, prec=a.prec, m=a.m, max_iter=a.iters,
                         grad_tol=a.grad_tol, polish_tol=a.polish, method=a.method, retraction=a.retraction,
-                        grassmann_w=a.grassmann_w)
+                        grassmann_w=a.grassmann_w, ev_gamma=a.ev_gamma)
     done, st = False, None
     history = []
     while not done:

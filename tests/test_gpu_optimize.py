@@ -116,3 +116,24 @@ def test_fp64_paper_geometry_trajectory_matches_oracle(ctx, method, retraction, 
     W = got["final"]
     for w in W:
         assert np.max(np.abs(w.T @ w - np.eye(w.shape[1]))) < 1e-13
+
+
+def test_fp64_ev_sweeps_match_oracle(ctx):
+    """Evenbly-Vidal sweeps (App. A) against the oracle's driver: same energies after every sweep."""
+    chi, T, sweeps, gamma = 4, 2, 3, 20.0
+    W0 = _init(0, chi, T)
+    h3 = model.tfim_h3(1.0)
+    prob = optim.Problem(h3, chi, T)
+    log = []
+    _, f_ref, g_ref, info = optim.optimize_ev(W0, prob, gamma, max_iter=sweeps, log=log)
+    got = ctx.run_optimize(2, 4, h3, W0, prec="fp64", max_iter=sweeps, grad_tol=0.0, log_cap=64, want_final=True,
+                           method="ev", ev_gamma=gamma)
+    print("gpu", [(r["iter"], r["evals"], r["energy"]) for r in got["log"]], flush=True)
+    print("ref", [(r["iter"], r["evals"], r["energy"]) for r in log], flush=True)
+    for a, b in zip(got["log"], log):
+        assert a["evals"] == b["evals"]
+        assert abs(a["energy"] - b["energy"]) <= 1e-10 * abs(b["energy"])
+    assert abs(got["energy"] - f_ref) <= 1e-10 * abs(f_ref)
+    assert got["evaluations"] == info["evals"]
+    for w in got["final"]:
+        assert np.max(np.abs(w.T @ w - np.eye(w.shape[1]))) < 1e-13

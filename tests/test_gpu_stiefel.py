@@ -4,6 +4,7 @@ import pytest
 
 from gpu_helpers import rel, require_gpu, to_np
 from oracle import manifold as mf
+from oracle import optim
 from paper_2007_03638_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -120,3 +121,17 @@ def test_grassmann_projection_and_geodesic(ctx):
     Wo = ctx.stiefel_retract_exp(W, X, 1.3, tangent=False)
     for w, x, wo in zip(W, X, Wo):
         assert rel(to_np(wo), mf.retract_exp(w, x, 1.3)[0]) < 1e-12
+
+
+@pytest.mark.parametrize("gamma", [2.0, 20.0])
+def test_ev_update(ctx, gamma):
+    """Evenbly-Vidal local update (App. A) element-wise against the oracle's SVD polar factor."""
+    shapes = [s for s in SHAPES if s[1] > 1]
+    W = [inputs.haar_params(50 + i, [s])[0] for i, s in enumerate(shapes)]
+    D = inputs.normal_like(51, W)
+    rho = [inputs.density_matrix(52 + i, s[1]) + 0.01 * np.eye(s[1]) for i, s in enumerate(shapes)]
+    Wo = ctx.ev_update(W, D, rho, gamma)
+    for w, d, r, wo in zip(W, D, rho, Wo):
+        wo = to_np(wo)
+        assert np.max(np.abs(wo.T @ wo - np.eye(w.shape[1]))) < 1e-13
+        assert rel(wo, optim.ev_update(w, d, r, gamma)) < 1e-11
