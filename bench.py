@@ -99,6 +99,29 @@ def counter_traffic(kernel_variant):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def precision_check(a, ctx, opt, h3):
+    """Energy and Riemannian-gradient error of the contraction precision at the final point of the timed steps,
+    against the plain FP64 evaluation of the same tensors (the FP64 GPU path, itself checked against the FP64
+    oracle element by element in the parity tests)."""
+    import torch
+    from paper_2007_03638_amd import api
+    fin = opt.final()
+    u, w = fin[0::2], fin[1::2]
+    r = {}
+    for prec in (a.prec, "fp64"):
+        ev = ctx.energy_grad(a.T, a.chi, u, w, h3, prec=prec)
+        D = [x for pair in zip(ev["Du"], ev["Dw"]) for x in pair]
+        W = [torch.as_tensor(x, dtype=torch.float64, device="cuda") for x in fin]
+        G = ctx.stiefel_project(W, D)
+        r[prec] = (ev["energy"], G)
+    e_lo, G_lo = r[a.prec]
+    e_hi, G_hi = r["fp64"]
+    num = sum(float(torch.sum((x - y) ** 2)) for x, y in zip(G_lo, G_hi)) ** 0.5
+    den = sum(float(torch.sum(y ** 2)) for y in G_hi) ** 0.5
+    return {"energy": e_lo, "energy_fp64": e_hi, "energy_rel_error": abs(e_lo - e_hi) / abs(e_hi),
+            "gradient_rel_error": num / den, "gnorm_fp64": den}
+
+
 def fp64_rate(a):
     """Evaluations/s of the plain FP64 form on the same workload (same seed and start point)."""
     import torch
@@ -196,6 +219,9 @@ def run_eval_bench(a):
         "kernels": [{"kernel": s["kernel"], "launches": s["launches"], "ms": 1000.0 * s["seconds"],
                      "tflops": s["flops"] / s["seconds"] / 1e12} for s in stats[:6]],
     }
+    if a.prec != "fp64":
+        out["precision_vs_fp64"] = precision_check(a, ctx, opt, h3)
+        print(f"[bench] precision check: {out['precision_vs_fp64']}", file=sys.stderr, flush=True)
     if a.fp64_steps > 0 and a.prec != "fp64":
         r64 = fp64_rate(a)
         out["fp64_form_evals_per_s"] = r64

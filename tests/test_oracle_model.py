@@ -53,3 +53,14 @@ def test_exact_energy_below_finite_ring_ground_state_gap():
     e12 = np.linalg.eigvalsh(H)[0] / 12
     e_inf = model.tfim_exact_energy_per_spin(1.0)
     assert abs(e12 - e_inf) / abs(e_inf) < 1e-2
+
+
+def test_closed_forms_from_golden_fixture():
+    """The oracle's ground-state energy functions against the closed forms stored in tests/golden (with sources)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "closed_form_energies.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 5
+    for kind, par, val, *_ in rows:
+        f = model.tfim_exact_energy_per_spin if kind == "tfim" else model.xxz_exact_energy_per_spin
+        assert abs(f(float(par)) - float(val)) < 1e-9, (kind, par)
