@@ -28,6 +28,7 @@ import numpy as np
 
 from . import manifold as mf
 from . import mera as om
+from . import ternary as tm
 
 
 def _axpy(a, X, Y):
@@ -124,9 +125,11 @@ class Problem:
     grassmann_w the isometries w are treated as points of Grassmann manifolds (the paper's choice, Sec. 4): their
     gradient and projection transport use the Grassmann projection (1 - W W^T)."""
 
-    def __init__(self, h3, chi, T, d=4, grassmann_w=False):
+    def __init__(self, h3, chi, T, d=4, grassmann_w=False, geometry='binary'):
+        """h3: the local term (3-site for the binary geometry, 2-site for the ternary one, Sec. 4)."""
         self.h3, self.chi, self.T, self.d = h3, chi, T, d
-        self.dims = om.layer_dims(chi, T, d)
+        self.geo = om if geometry == 'binary' else tm
+        self.dims = self.geo.layer_dims(chi, T, d)
         self.evals = 0
         self.grassmann = [grassmann_w and i % 2 == 1 for i in range(2 * len(self.dims))]
 
@@ -135,11 +138,11 @@ class Problem:
 
     def evaluate(self, W):
         params = [(W[2 * i], W[2 * i + 1]) for i in range(len(self.dims))]
-        ev = om.evaluate(params, self.h3, self.chi, self.T, self.d)
+        ev = self.geo.evaluate(params, self.h3, self.chi, self.T, self.d)
         self.evals += 1
         D = [m for pair in ev['grads'] for m in pair]
         G = [self.project(i, w, dd) for i, (w, dd) in enumerate(zip(W, D))]
-        rdms = om.preconditioner_rdms(ev['rhos'], params, self.dims)
+        rdms = self.geo.preconditioner_rdms(ev['rhos'], params, self.dims)
         rv = [m for pair in rdms for m in pair]
         self.last_D = D
         return ev['energy'], G, rv
