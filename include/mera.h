@@ -49,9 +49,12 @@ typedef enum { MERA_FP64 = 0, MERA_FP32 = 1, MERA_BF16X3 = 2 } mera_prec;
 typedef struct { int n, p; double* data; } mera_mat;
 
 typedef struct {
-  int T;    /* number of transition layers (>= 1)                         */
-  int d;    /* physical (blocked-site) dimension, 4 for two spins per site */
-  int chi;  /* bond dimension of the scale-invariant layer                 */
+  int T;         /* number of transition layers (>= 1)                                                  */
+  int d;         /* physical site dimension: 4 for two blocked spins (binary), 2 for one spin (ternary)  */
+  int chi;       /* bond dimension of the scale-invariant layer                                          */
+  int geometry;  /* 0: binary MERA with three-site operators (u a^2 x a^2, w a^2 x b, b = min(chi, a^2));  */
+                 /* 1: ternary MERA with two-site operators, the paper's benchmark geometry (Sec. 4):      */
+                 /*    u a^2 x a^2, w a^3 x b, b = min(chi, a^3); operators are b^2 x b^2                  */
 } mera_shape;
 
 typedef struct mera_ctx mera_ctx;
@@ -101,6 +104,11 @@ mera_status mera_layer_dims(const mera_shape* shape, int* a_out, int* b_out);
  * h3 = (hb (x) 1 + 1 (x) hb) / 2, so that the sum of h3 over a ring is the spin Hamiltonian. */
 mera_status mera_h3_tfim(double h, double* h3_host);
 mera_status mera_h3_xxz(double delta, double* h3_host);
+/* Two-site terms on unblocked spins (d = 2) for the ternary geometry (Sec. 4): TFIM -X X - h (Z 1 + 1 Z)/2,
+ * XXZ X X + Y Y + delta Z Z (Pauli units); summed over the bonds of a chain they give the chain Hamiltonian.
+ * Output: 4 x 4 row-major host FP64, basis |s0 s1> with s0 the more significant bit. */
+mera_status mera_h2_tfim(double h, double* h2_host);
+mera_status mera_h2_xxz(double delta, double* h2_host);
 
 /* ---- energy and Euclidean gradient (Sec. 4, App. B) --------------------------------------------------- */
 

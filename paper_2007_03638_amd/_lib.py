@@ -14,7 +14,7 @@ class MeraMat(ctypes.Structure):
 
 
 class MeraShape(ctypes.Structure):
-    _fields_ = [("T", c_int), ("d", c_int), ("chi", c_int)]
+    _fields_ = [("T", c_int), ("d", c_int), ("chi", c_int), ("geometry", c_int)]
 
 
 class KrylovOpts(ctypes.Structure):
@@ -69,6 +69,8 @@ SIGNATURES = {
     "mera_layer_dims": (c_int, [ctypes.POINTER(MeraShape), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "mera_h3_tfim": (c_int, [c_double, ctypes.POINTER(c_double)]),
     "mera_h3_xxz": (c_int, [c_double, ctypes.POINTER(c_double)]),
+    "mera_h2_tfim": (c_int, [c_double, ctypes.POINTER(c_double)]),
+    "mera_h2_xxz": (c_int, [c_double, ctypes.POINTER(c_double)]),
     "mera_warm_create": (c_int, [c_void_p, ctypes.POINTER(MeraShape), ctypes.POINTER(c_void_p)]),
     "mera_warm_destroy": (None, [c_void_p]),
     "mera_energy_grad": (c_int, [c_void_p, ctypes.POINTER(MeraShape), MAT_P, MAT_P, c_void_p, c_int, c_void_p,

@@ -36,8 +36,15 @@ def _mats(ts):
     return arr
 
 
-def _shape(T, chi, d=4):
-    return L.MeraShape(T, d, chi)
+GEOMETRIES = {"binary": 0, "ternary": 1}
+
+
+def _shape(T, chi, d=4, geometry="binary"):
+    return L.MeraShape(T, d, chi, GEOMETRIES[geometry])
+
+
+def _sites(geometry):
+    return 3 if geometry == "binary" else 2
 
 
 def h3_tfim(h=1.0):
@@ -45,6 +52,23 @@ def h3_tfim(h=1.0):
     st = L.load().mera_h3_tfim(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     if st != 0:
         raise MeraError(st, "mera_h3_tfim")
+    return out
+
+
+def h2_tfim(h=1.0):
+    """Two-site TFIM term on unblocked spins (ternary geometry)."""
+    out = np.zeros((4, 4))
+    st = L.load().mera_h2_tfim(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if st != 0:
+        raise MeraError(st, "mera_h2_tfim")
+    return out
+
+
+def h2_xxz(delta):
+    out = np.zeros((4, 4))
+    st = L.load().mera_h2_xxz(delta, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if st != 0:
+        raise MeraError(st, "mera_h2_xxz")
     return out
 
 
@@ -56,10 +80,10 @@ def h3_xxz(delta):
     return out
 
 
-def layer_dims(T, chi, d=4):
+def layer_dims(T, chi, d=4, geometry="binary"):
     a = (ctypes.c_int * (T + 1))()
     b = (ctypes.c_int * (T + 1))()
-    sh = _shape(T, chi, d)
+    sh = _shape(T, chi, d, geometry)
     st = L.load().mera_layer_dims(ctypes.byref(sh), a, b)
     if st != 0:
         raise MeraError(st, "mera_layer_dims")
@@ -67,10 +91,10 @@ def layer_dims(T, chi, d=4):
 
 
 class Warm:
-    def __init__(self, ctx, T, chi, d=4):
+    def __init__(self, ctx, T, chi, d=4, geometry="binary"):
         self._lib = L.load()
         self.ptr = ctypes.c_void_p()
-        sh = _shape(T, chi, d)
+        sh = _shape(T, chi, d, geometry)
         ctx._check(self._lib.mera_warm_create(ctx.ptr, ctypes.byref(sh), ctypes.byref(self.ptr)), "warm_create")
 
     def __del__(self):
@@ -133,8 +157,9 @@ class Context:
         return torch.as_tensor(x, dtype=torch.float64).to(self.device).contiguous()
 
     # ---- energy and gradient ---------------------------------------------------------------------------
-    def energy_grad(self, T, chi, u, w, h3, prec="fp64", warm=None, krylov=None, rdms=False, d=4):
-        dims = layer_dims(T, chi, d)
+    def energy_grad(self, T, chi, u, w, h3, prec="fp64", warm=None, krylov=None, rdms=False, d=4,
+                    geometry="binary"):
+        dims = layer_dims(T, chi, d, geometry)
         u = [self._dev(x) for x in u]
         w = [self._dev(x) for x in w]
         h3d = self._dev(h3)
@@ -149,7 +174,7 @@ class Context:
         ko = None
         if krylov is not None:
             ko = L.KrylovOpts(krylov.get("dim", 0), krylov.get("max_restarts", 0), krylov.get("tol", 0.0))
-        sh = _shape(T, chi, d)
+        sh = _shape(T, chi, d, geometry)
         st = self._lib.mera_energy_grad(self.ptr, ctypes.byref(sh), _mats(u), _mats(w), h3d.data_ptr(),
                                         _prec(prec), warm.ptr if warm else None,
                                         ctypes.byref(ko) if ko else None, ctypes.byref(e), _mats(Du), _mats(Dw),
@@ -163,20 +188,22 @@ class Context:
             out["rho_u"], out["rho_w"] = ru, rw
         return out
 
-    def ascend(self, T, chi, layer, u, w, h_in, prec="fp64", d=4):
-        a, b = layer_dims(T, chi, d)[layer]
+    def ascend(self, T, chi, layer, u, w, h_in, prec="fp64", d=4, geometry="binary"):
+        a, b = layer_dims(T, chi, d, geometry)[layer]
         u, w, hi = self._dev(u), self._dev(w), self._dev(h_in)
-        ho = torch.empty((b ** 3, b ** 3), dtype=torch.float64, device=self.device)
-        sh = _shape(T, chi, d)
+        k = _sites(geometry)
+        ho = torch.empty((b ** k, b ** k), dtype=torch.float64, device=self.device)
+        sh = _shape(T, chi, d, geometry)
         self._check(self._lib.mera_ascend(self.ptr, ctypes.byref(sh), layer, _mats([u]), _mats([w]), _prec(prec),
                                           hi.data_ptr(), ho.data_ptr()), "mera_ascend")
         return ho
 
-    def descend(self, T, chi, layer, u, w, rho_in, prec="fp64", d=4):
-        a, b = layer_dims(T, chi, d)[layer]
+    def descend(self, T, chi, layer, u, w, rho_in, prec="fp64", d=4, geometry="binary"):
+        a, b = layer_dims(T, chi, d, geometry)[layer]
         u, w, ri = self._dev(u), self._dev(w), self._dev(rho_in)
-        ro = torch.empty((a ** 3, a ** 3), dtype=torch.float64, device=self.device)
-        sh = _shape(T, chi, d)
+        k = _sites(geometry)
+        ro = torch.empty((a ** k, a ** k), dtype=torch.float64, device=self.device)
+        sh = _shape(T, chi, d, geometry)
         self._check(self._lib.mera_descend(self.ptr, ctypes.byref(sh), layer, _mats([u]), _mats([w]), _prec(prec),
                                            ri.data_ptr(), ro.data_ptr()), "mera_descend")
         return ro
@@ -263,9 +290,9 @@ class Context:
     # ---- whole optimisation -------------------------------------------------------------------------------
     def run_optimize(self, T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, polish_tol=0.0,
                      precondition=True, max_ls_evals=10, krylov=None, d=4, log_cap=0, want_final=False,
-                     method="lbfgs", retraction="polar", grassmann_w=False, ev_gamma=0.0):
+                     method="lbfgs", retraction="polar", grassmann_w=False, ev_gamma=0.0, geometry="binary"):
         job, keep = make_job(T, chi, h3, init, prec, m, max_iter, grad_tol, polish_tol, precondition,
-                             max_ls_evals, krylov, d, method, retraction, grassmann_w, ev_gamma)
+                             max_ls_evals, krylov, d, method, retraction, grassmann_w, ev_gamma, geometry)
         res = L.Result()
         logs = (L.IterLog * max(log_cap, 1))()
         nlog = ctypes.c_int(0)
@@ -295,14 +322,14 @@ def result_dict(res):
 
 def make_job(T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, polish_tol=0.0, precondition=True,
              max_ls_evals=10, krylov=None, d=4, method="lbfgs", retraction="polar", grassmann_w=False,
-             ev_gamma=0.0):
+             ev_gamma=0.0, geometry="binary"):
     """Build a mera_job; returns (job, keepalive) — keep the second item alive while the job is in use."""
     h3c = np.ascontiguousarray(h3, dtype=np.float64)
     mats = [np.ascontiguousarray(x, dtype=np.float64) for x in init]
     ptrs = (ctypes.POINTER(ctypes.c_double) * len(mats))(
         *[x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for x in mats])
     kr = krylov or {}
-    job = L.Job(_shape(T, chi, d), h3c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ptrs, _prec(prec), m,
+    job = L.Job(_shape(T, chi, d, geometry), h3c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ptrs, _prec(prec), m,
                 max_iter, grad_tol, polish_tol, 1 if precondition else 0, max_ls_evals,
                 L.KrylovOpts(kr.get("dim", 0), kr.get("max_restarts", 0), kr.get("tol", 0.0)),
                 {"lbfgs": 0, "cg": 1, "ev": 2}[method], {"polar": 0, "exp": 1}[retraction],
@@ -433,6 +460,6 @@ class Server:
             pass
 
 
-def job_footprint(T, chi, prec="fp32", d=4):
-    sh = _shape(T, chi, d)
+def job_footprint(T, chi, prec="fp32", d=4, geometry="binary"):
+    sh = _shape(T, chi, d, geometry)
     return L.load().mera_job_footprint(ctypes.byref(sh), _prec(prec))

@@ -63,11 +63,12 @@ void check_layer_mats(const mera_shape& s, const mera_mat* u, const mera_mat* w,
   check_mats(w, s.T + 1, what);
   for (int t = 0; t <= s.T; ++t) {
     const int a2 = dims[t].a * dims[t].a;
+    const int wn = (int)dims[t].wrows();
     MERA_CHECK(u[t].n == a2 && u[t].p == a2, MERA_EINVAL,
                std::string(what) + ": u[" + std::to_string(t) + "] must be " + std::to_string(a2) + "x" +
                    std::to_string(a2));
-    MERA_CHECK(w[t].n == a2 && w[t].p == dims[t].b, MERA_EINVAL,
-               std::string(what) + ": w[" + std::to_string(t) + "] must be " + std::to_string(a2) + "x" +
+    MERA_CHECK(w[t].n == wn && w[t].p == dims[t].b, MERA_EINVAL,
+               std::string(what) + ": w[" + std::to_string(t) + "] must be " + std::to_string(wn) + "x" +
                    std::to_string(dims[t].b));
   }
 }
@@ -157,6 +158,18 @@ mera_status mera_h3_xxz(double delta, double* h3_host) {
   return MERA_OK;
 }
 
+mera_status mera_h2_tfim(double h, double* h2_host) {
+  if (!h2_host || !std::isfinite(h)) return MERA_EINVAL;
+  build_h2_tfim(h, h2_host);
+  return MERA_OK;
+}
+
+mera_status mera_h2_xxz(double delta, double* h2_host) {
+  if (!h2_host || !std::isfinite(delta)) return MERA_EINVAL;
+  build_h2_xxz(delta, h2_host);
+  return MERA_OK;
+}
+
 mera_status mera_warm_create(mera_ctx* ctx, const mera_shape* shape, mera_warm** out) {
   if (!ctx || !shape || !out) return MERA_EINVAL;
   return guarded(ctx, [&] {
@@ -236,7 +249,8 @@ mera_status mera_ascend(mera_ctx* ctx, const mera_shape* shape, int layer, const
     auto dims = layer_dims(*shape);
     MERA_CHECK(layer >= 0 && layer <= shape->T, MERA_EINVAL, "layer out of range");
     const int a2 = dims[layer].a * dims[layer].a;
-    MERA_CHECK(u->data && u->n == a2 && u->p == a2 && w->data && w->n == a2 && w->p == dims[layer].b,
+    MERA_CHECK(u->data && u->n == a2 && u->p == a2 && w->data && w->n == (int)dims[layer].wrows() &&
+                   w->p == dims[layer].b,
                MERA_EINVAL, "tensor shape");
     DeviceGuard g(ctx->c.device);
     ascend_op(ctx->c, dims[layer], u->data, w->data, to_prec(prec), h_in, h_out);
@@ -252,7 +266,8 @@ mera_status mera_descend(mera_ctx* ctx, const mera_shape* shape, int layer, cons
     auto dims = layer_dims(*shape);
     MERA_CHECK(layer >= 0 && layer <= shape->T, MERA_EINVAL, "layer out of range");
     const int a2 = dims[layer].a * dims[layer].a;
-    MERA_CHECK(u->data && u->n == a2 && u->p == a2 && w->data && w->n == a2 && w->p == dims[layer].b,
+    MERA_CHECK(u->data && u->n == a2 && u->p == a2 && w->data && w->n == (int)dims[layer].wrows() &&
+                   w->p == dims[layer].b,
                MERA_EINVAL, "tensor shape");
     DeviceGuard g(ctx->c.device);
     descend_op(ctx->c, dims[layer], u->data, w->data, to_prec(prec), rho_in, rho_out);

@@ -157,6 +157,117 @@ const char* const kRhoU[] = {
     "rhou[efEF] = R1[eEqQ] * Z3[fqFQ]",
 };
 
+// ---- ternary MERA with two-site operators (Sec. 4, the paper's benchmark geometry) ---------------------------
+// w[x y z t] covers the sites (3k, 3k+1, 3k+2) below and maps to site k above; u[bl br tl tr] acts on
+// (3k+2, 3k+3). A two-site operator h[ab AB] on (3k, 3k+1), (3k+1, 3k+2) or (3k+2, 3k+3) rises through the L, C or R
+// diagram; A = (A_L + A_C + A_R)/3. Legs p, q, P, Q are top legs (b), all others bottom legs (a). Each diagram
+// costs O(a^8).
+const char* const kTAscL[] = {
+    "Wl[fpFP] = w[xyfp] * w[xyFP]",
+    "Wr[cbqCBQ] = w[cbzq] * w[CBzQ]",
+    "U[afcAFC] = u[eafc] * u[eAFC]",
+    "T1[bBfcFC] = h[abAB] * U[afcAFC]",
+    "T2[bBcCpP] = T1[bBfcFC] * Wl[fpFP]",
+    "out[pqPQ] += 0.3333333333333333 * T2[bBcCpP] * Wr[cbqCBQ]",
+};
+const char* const kTAscC[] = {
+    "Wl[acpACP] = w[xacp] * w[xACP]",
+    "Wr[fqFQ] = w[fyzq] * w[FyzQ]",
+    "U[bcfBCF] = u[becf] * u[BeCF]",
+    "T1[aAcfCF] = h[abAB] * U[bcfBCF]",
+    "T2[aAcCqQ] = T1[aAcfCF] * Wr[fqFQ]",
+    "out[pqPQ] += 0.3333333333333333 * T2[aAcCqQ] * Wl[acpACP]",
+};
+const char* const kTAscR[] = {
+    "Wl[cpCP] = w[xycp] * w[xyCP]",
+    "Wr[dqDQ] = w[dzvq] * w[DzvQ]",
+    "T1[ABcd] = h[abAB] * u[abcd]",
+    "T2[cdCD] = T1[ABcd] * u[ABCD]",
+    "T3[dDpP] = T2[cdCD] * Wl[cpCP]",
+    "out[pqPQ] += 0.3333333333333333 * T3[dDpP] * Wr[dqDQ]",
+};
+const char* const kTDesL[] = {
+    "Wl[fpFP] = w[xyfp] * w[xyFP]",
+    "Wr[cbqCBQ] = w[cbzq] * w[CBzQ]",
+    "U[afcAFC] = u[eafc] * u[eAFC]",
+    "R1[pPcbCB] = rho[pqPQ] * Wr[cbqCBQ]",
+    "R2[cbCBfF] = R1[pPcbCB] * Wl[fpFP]",
+    "out[abAB] += 0.3333333333333333 * R2[cbCBfF] * U[afcAFC]",
+};
+const char* const kTDesC[] = {
+    "Wl[acpACP] = w[xacp] * w[xACP]",
+    "Wr[fqFQ] = w[fyzq] * w[FyzQ]",
+    "U[bcfBCF] = u[becf] * u[BeCF]",
+    "R1[qQacAC] = rho[pqPQ] * Wl[acpACP]",
+    "R2[acACfF] = R1[qQacAC] * Wr[fqFQ]",
+    "out[abAB] += 0.3333333333333333 * R2[acACfF] * U[bcfBCF]",
+};
+const char* const kTDesR[] = {
+    "Wl[cpCP] = w[xycp] * w[xyCP]",
+    "Wr[dqDQ] = w[dzvq] * w[DzvQ]",
+    "R1[qQcC] = rho[pqPQ] * Wl[cpCP]",
+    "R2[cCdD] = R1[qQcC] * Wr[dqDQ]",
+    "R3[cdAB] = R2[cCdD] * u[ABCD]",
+    "out[abAB] += 0.3333333333333333 * R3[cdAB] * u[abcd]",
+};
+// Environments of the ket copies of u, of the left and of the right isometry (the bra copies give the same by the
+// symmetry of h and rho, hence the weight 2/3), and the descended rho, for one diagram.
+const char* const kTGradL[] = {
+    "Wl[fpFP] = w[xyfp] * w[xyFP]",
+    "Wr[cbqCBQ] = w[cbzq] * w[CBzQ]",
+    "U[afcAFC] = u[eafc] * u[eAFC]",
+    "T1[bBfcFC] = h[abAB] * U[afcAFC]",
+    "T2[bBcCpP] = T1[bBfcFC] * Wl[fpFP]",
+    "R1[pPcbCB] = rho[pqPQ] * Wr[cbqCBQ]",
+    "R2[cbCBfF] = R1[pPcbCB] * Wl[fpFP]",
+    "X1[aAcCfF] = h[abAB] * R2[cbCBfF]",
+    "Du[eafc] += 0.6666666666666666 * X1[aAcCfF] * u[eAFC]",
+    "Mwl[fFpP] = T1[bBfcFC] * R1[pPcbCB]",
+    "Dw[xyfp] += 0.6666666666666666 * w[xyFP] * Mwl[fFpP]",
+    "Mwr[bBcCqQ] = T2[bBcCpP] * rho[pqPQ]",
+    "Dw[cbzq] += 0.6666666666666666 * Mwr[bBcCqQ] * w[CBzQ]",
+    "rhoout[abAB] += 0.3333333333333333 * R2[cbCBfF] * U[afcAFC]",
+};
+const char* const kTGradC[] = {
+    "Wl[acpACP] = w[xacp] * w[xACP]",
+    "Wr[fqFQ] = w[fyzq] * w[FyzQ]",
+    "U[bcfBCF] = u[becf] * u[BeCF]",
+    "R1[qQacAC] = rho[pqPQ] * Wl[acpACP]",
+    "R2[acACfF] = R1[qQacAC] * Wr[fqFQ]",
+    "rhoout[abAB] += 0.3333333333333333 * R2[acACfF] * U[bcfBCF]",
+    "X1[bBcCfF] = h[abAB] * R2[acACfF]",
+    "Du[becf] += 0.6666666666666666 * X1[bBcCfF] * u[BeCF]",
+    "T1[aAcfCF] = h[abAB] * U[bcfBCF]",
+    "T2[aAcCqQ] = T1[aAcfCF] * Wr[fqFQ]",
+    "Mwl[aAcCpP] = T2[aAcCqQ] * rho[pqPQ]",
+    "Dw[xacp] += 0.6666666666666666 * w[xACP] * Mwl[aAcCpP]",
+    "Mwr[fFqQ] = T1[aAcfCF] * R1[qQacAC]",
+    "Dw[fyzq] += 0.6666666666666666 * Mwr[fFqQ] * w[FyzQ]",
+};
+const char* const kTGradR[] = {
+    "Wl[cpCP] = w[xycp] * w[xyCP]",
+    "Wr[dqDQ] = w[dzvq] * w[DzvQ]",
+    "R1[qQcC] = rho[pqPQ] * Wl[cpCP]",
+    "R2[cCdD] = R1[qQcC] * Wr[dqDQ]",
+    "R3[cdAB] = R2[cCdD] * u[ABCD]",
+    "rhoout[abAB] += 0.3333333333333333 * R3[cdAB] * u[abcd]",
+    "Du[abcd] += 0.6666666666666666 * h[abAB] * R3[cdAB]",
+    "T1[ABcd] = h[abAB] * u[abcd]",
+    "T2[cdCD] = T1[ABcd] * u[ABCD]",
+    "T3[cCqQ] = T2[cdCD] * Wr[dqDQ]",
+    "Mwl[cCpP] = T3[cCqQ] * rho[pqPQ]",
+    "Dw[xycp] += 0.6666666666666666 * w[xyCP] * Mwl[cCpP]",
+    "Mwr[dDqQ] = T2[cdCD] * R1[qQcC]",
+    "Dw[dzvq] += 0.6666666666666666 * Mwr[dDqQ] * w[DzvQ]",
+};
+// density matrix on the two top legs of u: the top two-site rho pushed down through w_k (x) w_{k+1}
+const char* const kTRhoU[] = {
+    "Wl[cpCP] = w[xycp] * w[xyCP]",
+    "Wr[dqDQ] = w[dzvq] * w[DzvQ]",
+    "R1[qQcC] = rho2[pqPQ] * Wl[cpCP]",
+    "rhou[cdCD] = R1[qQcC] * Wr[dqDQ]",
+};
+
 template <size_t N>
 std::vector<std::string> lines(const char* const (&a)[N]) {
   return std::vector<std::string>(a, a + N);
@@ -164,6 +275,7 @@ std::vector<std::string> lines(const char* const (&a)[N]) {
 
 struct Programs {
   Program asc[2], des[2], grad[2], rhou;
+  Program tasc[3], tdes[3], tgrad[3], trhou;  // ternary geometry
   Programs() {
     const std::vector<std::string> ext = {"h", "u", "w", "rho", "out", "Du", "Dw", "rhoout", "rho2", "rhou"};
     asc[0] = Program::parse("ascL", lines(kAscL), ext);
@@ -173,8 +285,20 @@ struct Programs {
     grad[0] = Program::parse("gradL", lines(kGradL), ext);
     grad[1] = Program::parse("gradR", lines(kGradR), ext);
     rhou = Program::parse("rhou", lines(kRhoU), ext);
-    // the chi^9 networks are worth grouping across concurrent jobs
-    for (Program* p : {&asc[0], &asc[1], &des[0], &des[1], &grad[0], &grad[1]}) p->batch = true;
+    tasc[0] = Program::parse("tascL", lines(kTAscL), ext);
+    tasc[1] = Program::parse("tascC", lines(kTAscC), ext);
+    tasc[2] = Program::parse("tascR", lines(kTAscR), ext);
+    tdes[0] = Program::parse("tdesL", lines(kTDesL), ext);
+    tdes[1] = Program::parse("tdesC", lines(kTDesC), ext);
+    tdes[2] = Program::parse("tdesR", lines(kTDesR), ext);
+    tgrad[0] = Program::parse("tgradL", lines(kTGradL), ext);
+    tgrad[1] = Program::parse("tgradC", lines(kTGradC), ext);
+    tgrad[2] = Program::parse("tgradR", lines(kTGradR), ext);
+    trhou = Program::parse("trhou", lines(kTRhoU), ext);
+    // the chi^9 (binary) and chi^8 (ternary) networks are worth grouping across concurrent jobs
+    for (Program* p : {&asc[0], &asc[1], &des[0], &des[1], &grad[0], &grad[1], &tasc[0], &tasc[1], &tasc[2],
+                       &tdes[0], &tdes[1], &tdes[2], &tgrad[0], &tgrad[1], &tgrad[2]})
+      p->batch = true;
   }
 };
 
@@ -193,9 +317,21 @@ LegDims legs(int a, int b) {
 
 int64_t p6(int64_t x) { return x * x * x * x * x * x; }
 
+// leg extents of the ternary programs: p, q, P, Q are top legs
+LegDims legs_ternary(int a, int b) {
+  LegDims d;
+  d.fill(0);
+  for (char c : std::string("abcdefvxyzABCDF")) d[(unsigned char)c] = a;
+  for (char c : std::string("pqPQ")) d[(unsigned char)c] = b;
+  return d;
+}
+
+LegDims legs_of(const LayerDim& L) { return L.ternary ? legs_ternary(L.a, L.b) : legs(L.a, L.b); }
+
 // Chunk of the loop leg for the 7-leg intermediates (a^6 b elements each): whole when they fit the context's
 // limit, else the largest divisor of a keeping each chunked one within half of it.
 int64_t loop_chunk(const Ctx& ctx, const LayerDim& L, size_t eb) {
+  if (L.ternary) return 0;  // the ternary networks have no loop; their intermediates are at most a^6
   const double full = (double)p6(L.a) * L.b * eb;
   const double lim = (double)ctx.inter_limit;
   if (full <= lim) return 0;
@@ -215,37 +351,46 @@ struct LayerTensors {
 
 std::vector<LayerDim> layer_dims(const mera_shape& s) {
   MERA_CHECK(s.T >= 1 && s.d >= 2 && s.chi >= 2, MERA_EINVAL, "shape: need T >= 1, d >= 2, chi >= 2");
+  MERA_CHECK(s.geometry == 0 || s.geometry == 1, MERA_EINVAL, "shape: geometry must be 0 (binary) or 1 (ternary)");
+  const bool ter = s.geometry == 1;
   std::vector<LayerDim> out;
   int a = s.d;
   for (int t = 0; t < s.T; ++t) {
-    int b = (int)std::min<int64_t>((int64_t)s.chi, (int64_t)a * a);
-    out.push_back({a, b});
+    const int64_t fan = ter ? (int64_t)a * a * a : (int64_t)a * a;
+    int b = (int)std::min<int64_t>((int64_t)s.chi, fan);
+    out.push_back({a, b, ter});
     a = b;
   }
   MERA_CHECK(a == s.chi, MERA_EINVAL,
              "top transition dimension " + std::to_string(a) + " != chi " + std::to_string(s.chi));
-  out.push_back({s.chi, s.chi});
+  out.push_back({s.chi, s.chi, ter});
   return out;
 }
 
 namespace {
 
+// diagrams of one layer map: the L/R pair (binary) or L/C/R (ternary)
+int n_diagrams(const LayerDim& L) { return L.ternary ? 3 : 2; }
+const Program& asc_prog(const LayerDim& L, int s) { return L.ternary ? programs().tasc[s] : programs().asc[s]; }
+const Program& des_prog(const LayerDim& L, int s) { return L.ternary ? programs().tdes[s] : programs().des[s]; }
+const Program& grad_prog(const LayerDim& L, int s) { return L.ternary ? programs().tgrad[s] : programs().grad[s]; }
+
 void ascend_raw(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr in, VPtr out, Prec prec) {
-  fill(ctx, out, p6(L.b), 0.0);
-  const LegDims d = legs(L.a, L.b);
+  fill(ctx, out, L.opsize(L.b), 0.0);
+  const LegDims d = legs_of(L);
   const int64_t ch = loop_chunk(ctx, L, elem_bytes(prec));
-  for (int s = 0; s < 2; ++s)
-    run_program(ctx, programs().asc[s], d, {{"h", in.p}, {"u", t.u}, {"w", t.w}, {"out", out.p}}, prec, ch);
-  symmetrize(ctx, out, (int64_t)L.b * L.b * L.b);
+  for (int s = 0; s < n_diagrams(L); ++s)
+    run_program(ctx, asc_prog(L, s), d, {{"h", in.p}, {"u", t.u}, {"w", t.w}, {"out", out.p}}, prec, ch);
+  symmetrize(ctx, out, L.opdim(L.b));
 }
 
 void descend_raw(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr in, VPtr out, Prec prec) {
-  fill(ctx, out, p6(L.a), 0.0);
-  const LegDims d = legs(L.a, L.b);
+  fill(ctx, out, L.opsize(L.a), 0.0);
+  const LegDims d = legs_of(L);
   const int64_t ch = loop_chunk(ctx, L, elem_bytes(prec));
-  for (int s = 0; s < 2; ++s)
-    run_program(ctx, programs().des[s], d, {{"rho", in.p}, {"u", t.u}, {"w", t.w}, {"out", out.p}}, prec, ch);
-  symmetrize(ctx, out, (int64_t)L.a * L.a * L.a);
+  for (int s = 0; s < n_diagrams(L); ++s)
+    run_program(ctx, des_prog(L, s), d, {{"rho", in.p}, {"u", t.u}, {"w", t.w}, {"out", out.p}}, prec, ch);
+  symmetrize(ctx, out, L.opdim(L.a));
 }
 
 // D_u, D_w (+)= derivative of Tr[A(h) rho]; rhoout = D(rho). Du, Dw, rhoout are overwritten.
@@ -253,16 +398,16 @@ void layer_grad(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr h, VPtr rho, V
                 Prec prec) {
   const int64_t a2 = (int64_t)L.a * L.a;
   fill(ctx, Du, a2 * a2, 0.0);
-  fill(ctx, Dw, a2 * L.b, 0.0);
-  fill(ctx, rhoout, p6(L.a), 0.0);
-  const LegDims d = legs(L.a, L.b);
+  fill(ctx, Dw, L.wrows() * L.b, 0.0);
+  fill(ctx, rhoout, L.opsize(L.a), 0.0);
+  const LegDims d = legs_of(L);
   const int64_t ch = loop_chunk(ctx, L, elem_bytes(prec));
-  for (int s = 0; s < 2; ++s)
-    run_program(ctx, programs().grad[s], d,
+  for (int s = 0; s < n_diagrams(L); ++s)
+    run_program(ctx, grad_prog(L, s), d,
                 {{"h", h.p}, {"rho", rho.p}, {"u", t.u}, {"w", t.w}, {"Du", Du.p}, {"Dw", Dw.p},
                  {"rhoout", rhoout.p}},
                 prec, ch);
-  symmetrize(ctx, rhoout, (int64_t)L.a * L.a * L.a);
+  symmetrize(ctx, rhoout, L.opdim(L.a));
 }
 
 struct KStat {
@@ -368,14 +513,14 @@ void ascend_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, Pr
     return;
   }
   void* us = ctx.buf("op.u", a2 * a2 * 4);
-  void* ws = ctx.buf("op.w", a2 * L.b * 4);
-  void* hi = ctx.buf("op.in", p6(L.a) * 4);
-  void* ho = ctx.buf("op.out", p6(L.b) * 4);
+  void* ws = ctx.buf("op.w", L.wrows() * L.b * 4);
+  void* hi = ctx.buf("op.in", L.opsize(L.a) * 4);
+  void* ho = ctx.buf("op.out", L.opsize(L.b) * 4);
   copy(ctx, VPtr{us, prec}, VPtr{(void*)u, Prec::F64}, a2 * a2);
-  copy(ctx, VPtr{ws, prec}, VPtr{(void*)w, Prec::F64}, a2 * L.b);
-  copy(ctx, VPtr{hi, prec}, VPtr{(void*)hin, Prec::F64}, p6(L.a));
+  copy(ctx, VPtr{ws, prec}, VPtr{(void*)w, Prec::F64}, L.wrows() * L.b);
+  copy(ctx, VPtr{hi, prec}, VPtr{(void*)hin, Prec::F64}, L.opsize(L.a));
   ascend_raw(ctx, L, {us, ws}, VPtr{hi, prec}, VPtr{ho, prec}, prec);
-  copy(ctx, VPtr{hout, Prec::F64}, VPtr{ho, prec}, p6(L.b));
+  copy(ctx, VPtr{hout, Prec::F64}, VPtr{ho, prec}, L.opsize(L.b));
 }
 
 void descend_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, Prec prec, const double* rin,
@@ -386,14 +531,14 @@ void descend_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, P
     return;
   }
   void* us = ctx.buf("op.u", a2 * a2 * 4);
-  void* ws = ctx.buf("op.w", a2 * L.b * 4);
-  void* ri = ctx.buf("op.in", p6(L.b) * 4);
-  void* ro = ctx.buf("op.out", p6(L.a) * 4);
+  void* ws = ctx.buf("op.w", L.wrows() * L.b * 4);
+  void* ri = ctx.buf("op.in", L.opsize(L.b) * 4);
+  void* ro = ctx.buf("op.out", L.opsize(L.a) * 4);
   copy(ctx, VPtr{us, prec}, VPtr{(void*)u, Prec::F64}, a2 * a2);
-  copy(ctx, VPtr{ws, prec}, VPtr{(void*)w, Prec::F64}, a2 * L.b);
-  copy(ctx, VPtr{ri, prec}, VPtr{(void*)rin, Prec::F64}, p6(L.b));
+  copy(ctx, VPtr{ws, prec}, VPtr{(void*)w, Prec::F64}, L.wrows() * L.b);
+  copy(ctx, VPtr{ri, prec}, VPtr{(void*)rin, Prec::F64}, L.opsize(L.b));
   descend_raw(ctx, L, {us, ws}, VPtr{ri, prec}, VPtr{ro, prec}, prec);
-  copy(ctx, VPtr{rout, Prec::F64}, VPtr{ro, prec}, p6(L.a));
+  copy(ctx, VPtr{rout, Prec::F64}, VPtr{ro, prec}, L.opsize(L.a));
 }
 
 EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const double* h3, Prec prec, Warm* warm,
@@ -401,7 +546,9 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
   const std::vector<LayerDim> dims = layer_dims(shape);
   const int T = shape.T;
   const int chi = shape.chi;
-  const int64_t chi3 = (int64_t)chi * chi * chi, n6 = chi3 * chi3;
+  const LayerDim& S = dims[T];
+  // operator side and element count at the scale-invariant layer (chi^3, chi^6 binary; chi^2, chi^4 ternary)
+  const int64_t chi3 = S.opdim(chi), n6 = S.opsize(chi);
   const size_t eb = elem_bytes(prec);
   const double macs0 = ctx.macs;
   EvalOut res;
@@ -415,23 +562,23 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
     if (prec == Prec::F64) {
       lt[t] = {(void*)pt.u[t], (void*)pt.w[t]};
     } else {
+      const int64_t wn = dims[t].wrows() * dims[t].b;
       lt[t].u = ctx.buf("shadow.u" + std::to_string(t), a2 * a2 * 4);
-      lt[t].w = ctx.buf("shadow.w" + std::to_string(t), a2 * dims[t].b * 4);
+      lt[t].w = ctx.buf("shadow.w" + std::to_string(t), wn * 4);
       copy(ctx, VPtr{lt[t].u, prec}, VPtr{(void*)pt.u[t], Prec::F64}, a2 * a2);
-      copy(ctx, VPtr{lt[t].w, prec}, VPtr{(void*)pt.w[t], Prec::F64}, a2 * dims[t].b);
+      copy(ctx, VPtr{lt[t].w, prec}, VPtr{(void*)pt.w[t], Prec::F64}, wn);
     }
   }
 
   // ascend the Hamiltonian through the transition layers
   std::vector<VPtr> hs(T + 1);
-  hs[0] = VPtr{ctx.buf("hs0", p6(shape.d) * eb), prec};
-  copy(ctx, hs[0], VPtr{(void*)h3, Prec::F64}, p6(shape.d));
+  hs[0] = VPtr{ctx.buf("hs0", S.opsize(shape.d) * eb), prec};
+  copy(ctx, hs[0], VPtr{(void*)h3, Prec::F64}, S.opsize(shape.d));
   for (int t = 0; t < T; ++t) {
-    hs[t + 1] = VPtr{ctx.buf("hs" + std::to_string(t + 1), p6(dims[t].b) * eb), prec};
+    hs[t + 1] = VPtr{ctx.buf("hs" + std::to_string(t + 1), S.opsize(dims[t].b) * eb), prec};
     ascend_raw(ctx, dims[t], lt[t], hs[t], hs[t + 1], prec);
   }
 
-  const LayerDim& S = dims[T];
   const double tol = ko.tol > 0 ? ko.tol : (prec == Prec::F64 ? 1e-13 : 1e-7);
   const int kdim = ko.dim > 0 ? ko.dim : 4;
   const int kres = ko.max_restarts > 0 ? ko.max_restarts : 200;
@@ -510,19 +657,19 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
       Dw = VPtr{out.Dw[t], prec};
     } else {
       Du = VPtr{ctx.buf("Dacc.u", a2 * a2 * 4), prec};
-      Dw = VPtr{ctx.buf("Dacc.w", a2 * L.b * 4), prec};
+      Dw = VPtr{ctx.buf("Dacc.w", L.wrows() * L.b * 4), prec};
     }
     const VPtr hin = (t == T) ? ht : hs[t];
     const VPtr rtop = (t == T) ? rho : rl[t + 1];
     // the descended matrix is the top of layer t-1; it is not needed below layer 0 or for the
     // scale-invariant layer, whose bottom is rho_s itself
     const bool keep = (t >= 1 && t < T);
-    VPtr rdown{ctx.buf(keep ? "rl" + std::to_string(t) : std::string("rl.discard"), p6(L.a) * eb), prec};
+    VPtr rdown{ctx.buf(keep ? "rl" + std::to_string(t) : std::string("rl.discard"), L.opsize(L.a) * eb), prec};
     layer_grad(ctx, L, lt[t], hin, rtop, Du, Dw, rdown, prec);
     if (keep) rl[t] = rdown;
     if (prec != Prec::F64) {
       copy(ctx, VPtr{out.Du[t], Prec::F64}, Du, a2 * a2);
-      copy(ctx, VPtr{out.Dw[t], Prec::F64}, Dw, a2 * L.b);
+      copy(ctx, VPtr{out.Dw[t], Prec::F64}, Dw, L.wrows() * L.b);
     }
   }
 
@@ -533,9 +680,15 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
       const LayerDim& L = dims[t];
       VPtr rtop = (t == T) ? rho : rl[t + 1];
       double* r2 = static_cast<double*>(ctx.buf("rdm.rho2", (size_t)L.b * L.b * L.b * L.b * 8));
-      rho_marginals(ctx, rtop, L.b, out.rho_w[t], r2);
+      if (L.ternary) {
+        // the top two-site rho itself (FP64) feeds rho_u; rho_w averages its two one-site marginals
+        copy(ctx, VPtr{r2, Prec::F64}, rtop, L.opsize(L.b));
+        rho_marginal_pair(ctx, VPtr{r2, Prec::F64}, L.b, out.rho_w[t]);
+      } else {
+        rho_marginals(ctx, rtop, L.b, out.rho_w[t], r2);
+      }
       symmetrize(ctx, VPtr{out.rho_w[t], Prec::F64}, L.b);
-      run_program(ctx, programs().rhou, legs(L.a, L.b),
+      run_program(ctx, L.ternary ? programs().trhou : programs().rhou, legs_of(L),
                   {{"w", (void*)pt.w[t]}, {"rho2", r2}, {"rhou", out.rho_u[t]}}, Prec::F64);
       symmetrize(ctx, VPtr{out.rho_u[t], Prec::F64}, (int64_t)L.a * L.a);
     }

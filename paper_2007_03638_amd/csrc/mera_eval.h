@@ -1,4 +1,5 @@
-// Binary-MERA energy and Euclidean gradient (Sec. 4 and App. B of arXiv:2007.03638).
+// Energy and Euclidean gradient of the binary (three-site operators) and ternary (two-site operators) infinite
+// MERA (Sec. 4 and App. B of arXiv:2007.03638).
 #pragma once
 
 #include <vector>
@@ -9,13 +10,19 @@
 namespace mera {
 
 struct LayerDim {
-  int a, b;  // bottom and top leg dimension of the layer
+  int a, b;           // bottom and top leg dimension of the layer
+  bool ternary = false;  // ternary geometry: w has three bottom legs, operators act on two sites
+  int sites() const { return ternary ? 2 : 3; }
+  int64_t wrows() const { return ternary ? (int64_t)a * a * a : (int64_t)a * a; }   // rows of w
+  static int64_t pw(int64_t x, int k) { int64_t r = 1; while (k-- > 0) r *= x; return r; }
+  int64_t opdim(int x) const { return pw(x, sites()); }          // operator side on x-dimensional sites
+  int64_t opsize(int x) const { return pw(x, 2 * sites()); }     // operator element count
 };
 
 // Transition layers 0..T-1 then the scale-invariant layer T (a = b = chi). Throws MERA_EINVAL if b_T != chi.
 std::vector<LayerDim> layer_dims(const mera_shape& s);
 
-// Device views of one evaluation point, all FP64 row-major (u: a^2 x a^2, w: a^2 x b).
+// Device views of one evaluation point, all FP64 row-major (u: a^2 x a^2, w: a^2 x b or a^3 x b).
 struct Point {
   std::vector<const double*> u, w;
 };
@@ -23,7 +30,7 @@ struct Point {
 struct Warm {
   int chi = 0;
   bool has_rho = false, has_ht = false;
-  DevBuf rho, ht;  // FP64 chi^6
+  DevBuf rho, ht;  // FP64 operators (chi^6 binary, chi^4 ternary)
 };
 
 struct KrylovOpts {

@@ -62,4 +62,22 @@ void build_h3_xxz(double delta, double* out) {
   add_hb(out, 2, 0.5, pair, field);
 }
 
+void build_h2_tfim(double h, double* out) {
+  std::memset(out, 0, sizeof(double) * 16);
+  for (int y = 0; y < 4; ++y) {
+    const int b0 = (y >> 1) & 1, b1 = y & 1;
+    out[(y ^ 3) * 4 + y] += -1.0;                                     // -X X
+    out[y * 4 + y] += -0.5 * h * ((b0 ? -1.0 : 1.0) + (b1 ? -1.0 : 1.0));  // -h (Z 1 + 1 Z)/2
+  }
+}
+
+void build_h2_xxz(double delta, double* out) {
+  std::memset(out, 0, sizeof(double) * 16);
+  for (int y = 0; y < 4; ++y) {
+    const int b0 = (y >> 1) & 1, b1 = y & 1;
+    out[(y ^ 3) * 4 + y] += 1.0 + ((b0 == b1) ? -1.0 : 1.0);          // X X + Y Y
+    out[y * 4 + y] += delta * ((b0 == b1) ? 1.0 : -1.0);               // delta Z Z
+  }
+}
+
 }  // namespace mera

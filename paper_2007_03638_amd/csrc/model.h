@@ -9,5 +9,9 @@ namespace mera {
 // blocks (0,1) and (1,2). out: 64 x 64 row-major.
 void build_h3_tfim(double h, double* out);
 void build_h3_xxz(double delta, double* out);
+// Two-site terms on unblocked spins for the ternary geometry: TFIM -X X - h (Z 1 + 1 Z)/2 (each site's field
+// shared by its two bonds), XXZ X X + Y Y + delta Z Z. out: 4 x 4 row-major, s0 the more significant bit.
+void build_h2_tfim(double h, double* out);
+void build_h2_xxz(double delta, double* out);
 
 }  // namespace mera

@@ -512,17 +512,17 @@ JobSpec JobSpec::from_c(const mera_job& j) {
   JobSpec s;
   s.shape = j.shape;
   auto dims = layer_dims(j.shape);
-  const int d3 = j.shape.d * j.shape.d * j.shape.d;
+  const int64_t hsize = dims[0].opsize(j.shape.d);  // d^6 (three-site, binary) or d^4 (two-site, ternary)
   MERA_CHECK(j.h3_host != nullptr, MERA_EINVAL, "job: null h3");
   MERA_CHECK(j.init_host != nullptr, MERA_EINVAL, "job: null initial tensors");
-  s.h3.assign(j.h3_host, j.h3_host + (size_t)d3 * d3);
+  s.h3.assign(j.h3_host, j.h3_host + (size_t)hsize);
   for (int t = 0; t <= j.shape.T; ++t) {
     const int a2 = dims[t].a * dims[t].a;
     const double* u = j.init_host[2 * t];
     const double* w = j.init_host[2 * t + 1];
     MERA_CHECK(u && w, MERA_EINVAL, "job: null initial tensor");
     s.init.emplace_back(u, u + (size_t)a2 * a2);
-    s.init.emplace_back(w, w + (size_t)a2 * dims[t].b);
+    s.init.emplace_back(w, w + (size_t)dims[t].wrows() * dims[t].b);
   }
   MERA_CHECK(j.prec == MERA_FP64 || j.prec == MERA_FP32 || j.prec == MERA_BF16X3, MERA_EINVAL, "job: precision");
   s.prec = j.prec == MERA_FP64 ? Prec::F64 : (j.prec == MERA_FP32 ? Prec::F32 : Prec::BF16X3);
@@ -556,7 +556,7 @@ void Optimizer::start(Ctx& c, const JobSpec& j, int log_cap_) {
   for (const LayerDim& L : dims) {
     n.push_back(L.a * L.a);
     p.push_back(L.a * L.a);
-    n.push_back(L.a * L.a);
+    n.push_back((int)L.wrows());
     p.push_back(L.b);
     rp.push_back(L.a * L.a);
     rp.push_back(L.b);

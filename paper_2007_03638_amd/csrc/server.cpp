@@ -27,18 +27,24 @@ size_t job_footprint(const mera_shape& s, Prec prec) {
   double bytes = 0;
   for (const LayerDim& L : dims) {
     const double a = L.a, b = L.b;
-    // largest intermediates of one layer's derivative program: two a^6 b, three a^6, operators b^6
-    double layer = eb * (2 * a * a * a * a * a * a * b + 3 * a * a * a * a * a * a + 4 * b * b * b * b * b * b);
-    // split-K partial sums of the a^4 b environment reductions (up to 64 splits)
-    layer += eb * 64.0 * a * a * a * a * b;
+    double layer;
+    if (L.ternary) {
+      // ternary derivative programs: about ten a^6 / a^4 b^2 intermediates, operators b^4
+      layer = eb * (10 * a * a * a * a * a * a + 10 * a * a * a * a * b * b + 4 * b * b * b * b);
+    } else {
+      // largest intermediates of one layer's derivative program: two a^6 b, three a^6, operators b^6
+      layer = eb * (2 * a * a * a * a * a * a * b + 3 * a * a * a * a * a * a + 4 * b * b * b * b * b * b);
+      // split-K partial sums of the a^4 b environment reductions (up to 64 splits)
+      layer += eb * 64.0 * a * a * a * a * b;
+    }
     bytes = std::max(bytes, layer);
   }
-  const double chi = s.chi, chi6 = chi * chi * chi * chi * chi * chi;
+  const double chi6 = (double)dims.back().opsize(s.chi);
   // Krylov basis (dim 4 + residual), fixed point, h~, sigma, scratch, hs/rho levels, FP64 warm starts
   bytes += eb * chi6 * (6 + 6 + 2 * (s.T + 1)) + 16.0 * chi6;
   // tensors, gradients, history (FP64)
   double params = 0;
-  for (const LayerDim& L : dims) params += (double)L.a * L.a * (L.a * L.a + L.b);
+  for (const LayerDim& L : dims) params += (double)L.a * L.a * L.a * L.a + (double)L.wrows() * L.b;
   bytes += 8.0 * params * (9 + 2 * 8);
   return (size_t)(bytes * 1.1) + ((size_t)64 << 20);
 }

@@ -45,5 +45,8 @@ void reg_spectrum(Ctx& ctx, const double* lam, double delta, double* f, double* 
 //   rho2[x y, X Y]    = ( sum_r rho[x y r, X Y r] + sum_p rho[p x y, p X Y] ) / 2
 // outputs FP64 device, b x b and b^2 x b^2.
 void rho_marginals(Ctx& ctx, VPtr rho, int b, double* rho1, double* rho2);
+// One-site marginal of a two-site density matrix rho[p q, P Q] (b^2 x b^2, FP64), averaged over both sites:
+//   rho1[x, X] = ( sum_q rho[x q, X q] + sum_p rho[p x, p X] ) / 2                     (b x b, FP64 device)
+void rho_marginal_pair(Ctx& ctx, VPtr rho, int b, double* rho1);
 
 }  // namespace mera

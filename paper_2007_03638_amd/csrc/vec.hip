@@ -227,6 +227,17 @@ __global__ void copy_block_kernel(double* dst, int64_t ldd, const double* src, i
   }
 }
 
+// rho1[i, j] = ( sum_k rho[(i k), (j k)] + sum_k rho[(k i), (k j)] ) / 2 for a two-site rho (b^2 x b^2, FP64)
+__global__ void marginal_pair_kernel(const double* __restrict__ rho, int b, double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= b * b) return;
+  const int i = t / b, j = t - i * b;
+  const int64_t n = (int64_t)b * b;
+  double s = 0.0;
+  for (int k = 0; k < b; ++k) s += rho[(int64_t)(i * b + k) * n + (j * b + k)] + rho[(int64_t)(k * b + i) * n + (k * b + j)];
+  out[t] = 0.5 * s;
+}
+
 __global__ void reg_spectrum_kernel(const double* lam, double delta, double* f, double* g, int dim) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < dim) {
@@ -464,6 +475,13 @@ void copy_block(Ctx& ctx, double* dst, int64_t ldd, const double* src, int64_t l
   if (rows <= 0 || cols <= 0) return;
   hipLaunchKernelGGL(copy_block_kernel, dim3(grid_for((int64_t)rows * cols)), dim3(TPB), 0, ctx.stream, dst, ldd, src,
                      lds, rows, cols, a);
+  MERA_HIP(hipGetLastError());
+}
+
+void rho_marginal_pair(Ctx& ctx, VPtr rho, int b, double* rho1) {
+  MERA_CHECK(rho.dbl(), MERA_EINVAL, "rho_marginal_pair expects an FP64 matrix");
+  hipLaunchKernelGGL(marginal_pair_kernel, dim3((b * b + TPB - 1) / TPB), dim3(TPB), 0, ctx.stream,
+                     static_cast<const double*>(rho.p), b, rho1);
   MERA_HIP(hipGetLastError());
 }
 

@@ -20,18 +20,19 @@ def haar_params(seed, shapes):
     return [haar_isometry(rng, n, p) for (n, p) in shapes]
 
 
-def mera_shapes(dims):
-    """[(n_u, p_u), (n_w, p_w)] per layer for the (a, b) layer dimensions: u is a^2 x a^2, w is a^2 x b."""
+def mera_shapes(dims, w_legs=2):
+    """[(n_u, p_u), (n_w, p_w)] per layer for the (a, b) layer dimensions: u is a^2 x a^2, w is a^w_legs x b
+    (w_legs = 2 for the binary geometry, 3 for the ternary one)."""
     out = []
     for a, b in dims:
         out.append((a * a, a * a))
-        out.append((a * a, b))
+        out.append((a ** w_legs, b))
     return out
 
 
-def mera_init(seed, dims):
+def mera_init(seed, dims, w_legs=2):
     """Haar initial tensors in the order u_1, w_1, ..., u_T, w_T, u_s, w_s, grouped as [(u, w)] per layer."""
-    mats = haar_params(seed, mera_shapes(dims))
+    mats = haar_params(seed, mera_shapes(dims, w_legs))
     return [(mats[2 * i], mats[2 * i + 1]) for i in range(len(dims))]
 
 

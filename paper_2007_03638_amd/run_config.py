@@ -22,6 +22,8 @@ def main():
     ap.add_argument("--iters", type=int, default=200)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--model", default="tfim", choices=["tfim", "xxz"])
+    ap.add_argument("--geometry", default="binary", choices=["binary", "ternary"],
+                    help="binary: three-site terms on blocked spins (d = 4); ternary: two-site terms on spins (d = 2)")
     ap.add_argument("--param", type=float, default=1.0)
     ap.add_argument("--polish", type=float, default=0.0)
     ap.add_argument("--grad-tol", type=float, default=1e-10)
@@ -36,13 +38,18 @@ def main():
 
     from . import api, inputs
     ctx = api.Context(0)
-    dims = api.layer_dims(a.T, a.chi)
-    init = [m for pair in inputs.mera_init(a.seed, dims) for m in pair]
-    h3 = api.h3_tfim(a.param) if a.model == "tfim" else api.h3_xxz(a.param)
+    ter = a.geometry == "ternary"
+    d = 2 if ter else 4
+    dims = api.layer_dims(a.T, a.chi, d, a.geometry)
+    init = [m for pair in inputs.mera_init(a.seed, dims, w_legs=3 if ter else 2) for m in pair]
+    if ter:
+        h3 = api.h2_tfim(a.param) if a.model == "tfim" else api.h2_xxz(a.param)
+    else:
+        h3 = api.h3_tfim(a.param) if a.model == "tfim" else api.h3_xxz(a.param)
     t0 = time.perf_counter()
     opt = ctx.optimizer(T=a.T, chi=a.chi, h3=h3, init=init, prec=a.prec, m=a.m, max_iter=a.iters,
                         grad_tol=a.grad_tol, polish_tol=a.polish, method=a.method, retraction=a.retraction,
-                        grassmann_w=a.grassmann_w, ev_gamma=a.ev_gamma)
+                        grassmann_w=a.grassmann_w, ev_gamma=a.ev_gamma, d=d, geometry=a.geometry)
     done, st = False, None
     history = []
     while not done:
@@ -57,7 +64,8 @@ def main():
         np.savez(a.save, *final)
     out = dict(chi=a.chi, T=a.T, prec=a.prec, method=a.method, retraction=a.retraction, grassmann_w=a.grassmann_w,
                seed=a.seed, model=a.model, param=a.param,
-               energy=st["energy"], energy_per_spin=st["energy"] / 2, gnorm=st["gnorm"],
+               geometry=a.geometry, energy=st["energy"], energy_per_spin=st["energy"] / (1 if ter else 2),
+               gnorm=st["gnorm"],
                iterations=st["iterations"], evaluations=st["evaluations"], status=st["status"],
                polish_iter=st["polish_iter"], seconds=dt, tflops=2 * st["macs"] / dt / 1e12,
                krylov_applications=st["krylov_applications"],
