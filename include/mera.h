@@ -11,12 +11,15 @@
  *   - Matrices (mera_mat) are REAL, FP64, ROW-MAJOR n x p, in DEVICE memory of the context's GPU, and are
  *     owned by the caller. For an isometry the rows index the bottom (incoming) legs and the columns the top
  *     (outgoing) legs: a disentangler u is a^2 x a^2 with rows (bl, br) and columns (tl, tr); an isometry w is
- *     a^2 x b with rows (bl, br) and column t. Leg indices are row-major (first leg slowest).
- *   - 3-site operators are d^3 x d^3 matrices (rows = ket legs abc, columns = bra legs ABC), row-major FP64.
+ *     a^2 x b with rows (bl, br) and column t (ternary geometry: a^3 x b, rows (bl, bc, br)). Leg indices are
+ *     row-major (first leg slowest).
+ *   - Local operators are row-major FP64 matrices on the sites a term covers: d^3 x d^3 for the binary geometry's
+ *     three-site terms (rows = ket legs abc, columns = bra legs ABC), d^2 x d^2 for the ternary geometry's two-site
+ *     terms (rows ab, columns AB). "h3" arguments below take whichever the shape's geometry uses.
  *   - All device work is ordered on the context's HIP stream. Calls that return host scalars synchronise it.
  *   - The library owns only what its *_create calls allocate and frees it in the matching *_destroy.
  *   - Layer geometry: T transition layers and one scale-invariant layer. Layer 1 has bottom dimension a_1 = d;
- *     layer tau has top dimension b_tau = min(chi, a_tau^2) and a_{tau+1} = b_tau; the scale-invariant layer
+ *     layer tau has top dimension b_tau = min(chi, a_tau^2) (binary) or min(chi, a_tau^3) (ternary), a_{tau+1} = b_tau; the scale-invariant layer
  *     has a = b = chi, so b_T must equal chi (MERA_EINVAL otherwise). Tensor arrays are indexed by layer,
  *     0..T-1 for the transition layers and T for the scale-invariant one.
  */
@@ -138,8 +141,8 @@ typedef struct {
  *   invariant density matrix as the fixed point of the descending map; derivative through the fixed point by
  *   the deflated series h~ = sum_i <h'|A'^i, A' = A - |rho><1|, h' = h_T - e 1, solved by a Krylov method).
  *   u[0..T], w[0..T]     tensors (device, FP64, see conventions), isometric.
- *   h3                   device d^3 x d^3 FP64 symmetric 3-site term.
- *   warm                 in/out warm starts, or NULL (then the solves start from 1/chi^3 and h').
+ *   h3                   device FP64 symmetric local term: d^3 x d^3 (binary) or d^2 x d^2 (ternary).
+ *   warm                 in/out warm starts, or NULL (then the solves start from 1/chi^k and h', k sites).
  *   energy               host double out.
  *   Du[0..T], Dw[0..T]   caller-allocated device outputs, same shapes as u, w. The scale-invariant D is fixed
  *                        in the gauge Tr[h~ rho_s] = 0 (terms along W S, S symmetric, are not determined).
@@ -154,7 +157,8 @@ mera_status mera_energy_grad(mera_ctx* ctx, const mera_shape* shape, const mera_
                              mera_eval_info* info);
 
 /* Single superoperator applications, for tests and tools (App. B: <h|A raises, A|rho> lowers).
- * layer = 0..T; in/out are device operators of the layer's bottom (a^3 x a^3) or top (b^3 x b^3) sites. */
+ * layer = 0..T; in/out are device operators of the layer's bottom (a^k x a^k) or top (b^k x b^k) sites, k = 3
+ * for the binary and 2 for the ternary geometry. */
 mera_status mera_ascend(mera_ctx* ctx, const mera_shape* shape, int layer, const mera_mat* u, const mera_mat* w,
                         mera_prec prec, const double* h_in, double* h_out);
 mera_status mera_descend(mera_ctx* ctx, const mera_shape* shape, int layer, const mera_mat* u, const mera_mat* w,
@@ -223,7 +227,7 @@ mera_status lbfgs_push(mera_ctx* ctx, mera_lbfgs* lb, const mera_mat* W_new, con
 
 typedef struct {
   mera_shape shape;
-  const double* h3_host;           /* d^3 x d^3 host FP64                                                   */
+  const double* h3_host;           /* host FP64 local term, d^3 x d^3 (binary) or d^2 x d^2 (ternary)       */
   const double* const* init_host;  /* 2(T+1) host FP64 matrices: u_1, w_1, ..., u_T, w_T, u_s, w_s          */
   mera_prec prec;                  /* contraction arithmetic before polishing                               */
   int lbfgs_m;                     /* memory (8)                                                            */
