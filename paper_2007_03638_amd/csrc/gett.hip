@@ -1,6 +1,6 @@
-// Permute-fused GETT kernels for gfx950: LDS-staged, register-prefetched tile loads through offset tables,
-// MFMA inner products (f32 32x32x2, f64 16x16x4, bf16 16x16x32 for the split-bf16 form), split-K partials
-// reduced in FP64.
+// Permute-fused GETT kernels for gfx950: LDS-staged, register-prefetched tile loads (16-byte vectors where the
+// layouts allow; row offsets from tables, k offsets computed from the contracted legs), MFMA inner products
+// (f32 32x32x2, f64 16x16x4, bf16 16x16x32 for the split-bf16 form), split-K partials reduced in FP64.
 #include "gett.h"
 
 #include <algorithm>
@@ -18,11 +18,10 @@ struct Args {
   void* C[kGettMaxGroup];
   void* partial[kGettMaxGroup];  // splits x M x N partial sums per set (accumulator type); used when split != 0
   const int64_t* a_m;
-  const int64_t* a_k;
-  const int64_t* b_k;
   const int64_t* b_n;
   const int64_t* c_m;
   const int64_t* c_n;
+  GettKLegs kl;
   int64_t M, N, K;
   int64_t kchunk;  // K range per split, a multiple of BK
   double alpha, beta;
@@ -61,13 +60,29 @@ template <> struct Mma<double> {
   __device__ static inline int col(int lane) { return lane & 15; }
 };
 
-// Tile loader: BMN x BK tile of an operand whose element (r, k) lives at base + off_r[r] + off_k[k].
+// Offset of the k-th index along the contracted legs (fastest leg first; see GettKLegs): NKL digit extractions
+// by reciprocal multiplication, no memory access. Entries past kl.n are zero and contribute nothing.
+template <int NKL>
+__device__ inline int64_t k_offset(uint32_t k, const GettKLegs& kl, const int64_t* stride) {
+  int64_t off = 0;
+  uint32_t q = k;
+#pragma unroll
+  for (int l = 0; l + 1 < NKL; ++l) {
+    const uint32_t qn = __umulhi(q, kl.mag[l]);
+    off += (int64_t)(q - qn * kl.ext[l]) * stride[l];
+    q = qn;
+  }
+  return off + (int64_t)q * stride[NKL - 1];
+}
+
+// Tile loader: BMN x BK tile of an operand whose element (r, k) lives at base + off_r[r] + k_offset(k).
 // KFAST: consecutive threads walk k (the operand's unit-stride leg is a K leg); each thread then owns one k
-// and PER rows. Otherwise consecutive threads walk r in groups of 64; each thread owns NR rows and NK k's.
-// Row offsets are read once per tile row; k offsets for the next tile are fetched one tile ahead (fetch_k),
-// so the data loads of a tile never wait on a table lookup. Loads are unconditional (tables are padded with
-// offset 0, which addresses a valid element) and masked afterwards, keeping the loads in one batch.
-template <typename T, int BMN, int BK, bool KFAST>
+// and PER rows. Otherwise consecutive threads walk r in groups of 64; each thread owns NR rows and NK k's, and
+// a wave's k's are the same for all its lanes, so their offsets are formed once per wave in scalar registers.
+// Rows past the extent are not masked: their table entries are padded with offset 0, so they read a valid
+// element and only feed accumulator rows that are never stored. k past the end of the range is clamped for the
+// address and masked (zero) when the tile is staged, which only the last tile of a range needs (KMASK).
+template <typename T, int BMN, int BK, bool KFAST, int NKL>
 struct Loader {
   static constexpr int PER = BMN * BK / 256;
   static_assert(PER >= 1 && (BMN * BK) % 256 == 0, "tile too small for 256 threads");
@@ -77,54 +92,107 @@ struct Loader {
   static constexpr int RSTEP = KFAST ? 256 / BK : 64;
   static constexpr int KSTEP = KFAST ? 1 : 4;         // 256 threads / 64 rows per group
   static_assert(KFAST || NK * KSTEP == BK, "k coverage");
-  int64_t roff[NR];
-  bool rval[NR];
-  int64_t koff[NK];
-  int r0, k0;
+  const T* rowp[NR];
+  int r0;
+  uint32_t k0;
   T reg[PER];
-  bool okm[PER];  // element in range; applied when staging so the mask does not wait on the loads
 
-  __device__ inline void init(const int64_t* off_r, int64_t rbase, int64_t R, int tid) {
+  __device__ inline void init(const T* base, const int64_t* off_r, int64_t rbase, int tid) {
     if (KFAST) {
       k0 = tid % BK;
       r0 = tid / BK;
     } else {
       r0 = tid % 64;
-      k0 = tid / 64;
+      k0 = __builtin_amdgcn_readfirstlane(tid / 64);
     }
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      int64_t r = rbase + r0 + i * RSTEP;
-      roff[i] = off_r[r];
-      rval[i] = r < R;
+    for (int i = 0; i < NR; ++i) rowp[i] = base + off_r[rbase + r0 + i * RSTEP];
+  }
+  // loads the tile starting at kt; element (i): row index i % NR, k index i / NR
+  __device__ inline void load(int64_t kt, int64_t K, const GettKLegs& kl, const int64_t* stride) {
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+      const int64_t k = kt + k0 + j * KSTEP;
+      const int64_t o = k_offset<NKL>((uint32_t)(k < K ? k : K - 1), kl, stride);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) reg[j * NR + r] = rowp[r][o];
     }
   }
-  // k offsets of tile kt (kt < padded K)
-  __device__ inline void fetch_k(const int64_t* __restrict__ off_k, int64_t kt) {
-#pragma unroll
-    for (int j = 0; j < NK; ++j) koff[j] = off_k[kt + k0 + j * KSTEP];
+  // value of element i of the tile starting at kt, zero past kend when KMASK
+  template <bool KMASK>
+  __device__ inline T value(int i, int64_t kt, int64_t kend) const {
+    return (KMASK && kt + k0 + (i / NR) * KSTEP >= kend) ? T(0) : reg[i];
   }
-  // element (i): row index i % NR, k index i / NR. MASK = false on interior tiles, where every row and k
-  // is in range and no mask is formed.
-  template <bool MASK>
-  __device__ inline void load(const T* __restrict__ base, int64_t kt, int64_t kend) {
-#pragma unroll
-    for (int i = 0; i < PER; ++i) reg[i] = base[roff[i % NR] + koff[i / NR]];
-    if (MASK) {
-#pragma unroll
-      for (int i = 0; i < PER; ++i) okm[i] = rval[i % NR] && (kt + k0 + (i / NR) * KSTEP < kend);
-    }
-  }
-  template <bool MASK>
-  __device__ inline T value(int i) const { return MASK ? (okm[i] ? reg[i] : T(0)) : reg[i]; }
   __device__ inline int lds_index(int i, int LD) const {
     return (k0 + (i / NR) * KSTEP) * LD + r0 + (i % NR) * RSTEP;
   }
   // LDS tile stored k-major: lds[k * LD + r]
-  template <int LD, bool MASK>
-  __device__ inline void store(T* lds) const {
+  template <int LD, bool KMASK>
+  __device__ inline void store(T* lds, int64_t kt, int64_t kend) const {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) lds[lds_index(i, LD)] = value<MASK>(i);
+    for (int i = 0; i < PER; ++i) lds[lds_index(i, LD)] = value<KMASK>(i, kt, kend);
+  }
+  template <int LD>
+  __device__ inline void store_tile(T* lds, int64_t kt, int64_t kend) const {
+    if (kt + BK <= kend) store<LD, false>(lds, kt, kend);
+    else store<LD, true>(lds, kt, kend);
+  }
+};
+
+// Vectorised tile loader: each global load moves VW consecutive elements along the operand's unit-stride leg
+// (VW = 4 for FP32, 2 for FP64: 16 bytes). Used when that leg is the fastest index the loader walks, its extent
+// and every other stride are multiples of VW and the base is 16-byte aligned, so that every vector lies within
+// one run of the unit-stride leg. KFAST: the vectors run along k (VW k's of one row; staged as VW scalar LDS
+// writes); otherwise along rows (VW rows at one k; one vector LDS write). Vector i of a thread is the tile's
+// vector number tid + 256 i; padded rows (offset 0) and clamped k read valid elements, as in Loader.
+template <typename T, int BMN, int BK, bool KFAST, int NKL, int VW>
+struct VecLoader {
+  typedef T V __attribute__((ext_vector_type(VW)));
+  static constexpr int G = KFAST ? BK / VW : BMN / VW;  // vectors along the walked dimension
+  static constexpr int NV = BMN * BK / VW / 256;        // vectors per thread
+  static_assert(NV >= 1 && (BMN * BK / VW) % 256 == 0, "tile too small for 256 threads");
+  const T* rowp[NV];
+  int rr[NV], kk[NV];
+  V reg[NV];
+
+  __device__ inline void init(const T* base, const int64_t* off_r, int64_t rbase, int tid) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = tid + 256 * i;
+      rr[i] = KFAST ? e / G : (e % G) * VW;
+      kk[i] = KFAST ? (e % G) * VW : e / G;
+      rowp[i] = base + off_r[rbase + rr[i]];
+    }
+  }
+  __device__ inline void load(int64_t kt, int64_t K, const GettKLegs& kl, const int64_t* stride) {
+    const int64_t klast = KFAST ? K - VW : K - 1;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int64_t k = kt + kk[i];
+      const int64_t o = k_offset<NKL>((uint32_t)(k < klast ? k : klast), kl, stride);
+      reg[i] = *reinterpret_cast<const V*>(rowp[i] + o);
+    }
+  }
+  template <int LD, bool KMASK>
+  __device__ inline void store(T* lds, int64_t kt, int64_t kend) const {
+    static_assert(KFAST || LD % VW == 0, "vector LDS rows");
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      if (KFAST) {
+#pragma unroll
+        for (int j = 0; j < VW; ++j)
+          lds[(kk[i] + j) * LD + rr[i]] = (KMASK && kt + kk[i] + j >= kend) ? T(0) : reg[i][j];
+      } else {
+        V v = reg[i];
+        if (KMASK && kt + kk[i] >= kend) v = V(T(0));
+        *reinterpret_cast<V*>(&lds[kk[i] * LD + rr[i]]) = v;
+      }
+    }
+  }
+  template <int LD>
+  __device__ inline void store_tile(T* lds, int64_t kt, int64_t kend) const {
+    if (kt + BK <= kend) store<LD, false>(lds, kt, kend);
+    else store<LD, true>(lds, kt, kend);
   }
 };
 
@@ -150,12 +218,14 @@ __device__ inline void tile_origin(int64_t tile, int64_t M, int64_t N, int64_t& 
   }
 }
 
-template <typename T, int BM, int BN, int BK, bool AKF, bool BKF>
+template <typename T, int BM, int BN, int BK, bool AKF, bool BKF, int NKL, bool VEC>
 // At most 256 registers per lane (2 waves per SIMD) for every tile; the register allocator then keeps the
 // accumulators in VGPRs and the 128 x 128 FP32 and 128 x 64 FP64 tiles reach 3 waves per SIMD.
 __global__ void __launch_bounds__(256, 2) gett_kernel(Args g) {
   using F = Mma<T>;
-  constexpr int PAD = sizeof(T) == 4 ? 2 : 1;
+  // vector width of the tile loads (VEC: both operands qualify); LDS rows padded to a multiple of it
+  constexpr int VW = VEC ? 16 / (int)sizeof(T) : 1;
+  constexpr int PAD = VEC ? VW : (sizeof(T) == 4 ? 2 : 1);
   constexpr int LDA = BM + PAD, LDB = BN + PAD;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / F::MT, FN = WN / F::NT;
@@ -178,10 +248,10 @@ __global__ void __launch_bounds__(256, 2) gett_kernel(Args g) {
   const T* __restrict__ A = static_cast<const T*>(g.A[grp]);
   const T* __restrict__ B = static_cast<const T*>(g.B[grp]);
 
-  Loader<T, BM, BK, AKF> la;
-  Loader<T, BN, BK, BKF> lb;
-  la.init(g.a_m, m0, g.M, tid);
-  lb.init(g.b_n, n0, g.N, tid);
+  std::conditional_t<VEC, VecLoader<T, BM, BK, AKF, NKL, VW>, Loader<T, BM, BK, AKF, NKL>> la;
+  std::conditional_t<VEC, VecLoader<T, BN, BK, BKF, NKL, VW>, Loader<T, BN, BK, BKF, NKL>> lb;
+  la.init(A, g.a_m, m0, tid);
+  lb.init(B, g.b_n, n0, tid);
 
   typename F::acc_t acc[FM][FN];
 #pragma unroll
@@ -191,69 +261,81 @@ __global__ void __launch_bounds__(256, 2) gett_kernel(Args g) {
 #pragma unroll
       for (int r = 0; r < F::NACC; ++r) acc[i][j][r] = T(0);
 
-  auto kloop = [&](auto mask_tag) {
-    constexpr bool MASK = decltype(mask_tag)::value;
-    auto mfma_steps = [&](const T* as, const T* bs, int k_lo, int k_hi) {
+  // MFMA operand fragments, double-buffered: the fragments of k-step s+1 are read from LDS while the MFMAs of
+  // step s run
+  constexpr int NKS = BK / F::KT;
+  static_assert(NKS % 2 == 0, "even number of k-steps per tile");
+  T af[2][FM], bf[2][FN];
+  auto read_frag = [&](int slot, const T* as, const T* bs, int ks) {
 #pragma unroll
-      for (int ks = k_lo; ks < k_hi; ks += F::KT) {
-        T af[FM], bf[FN];
+    for (int i = 0; i < FM; ++i) af[slot][i] = as[(ks + lane / F::MT) * LDA + wm + i * F::MT + lane % F::MT];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) af[i] = as[(ks + lane / F::MT) * LDA + wm + i * F::MT + lane % F::MT];
+    for (int j = 0; j < FN; ++j) bf[slot][j] = bs[(ks + lane / F::NT) * LDB + wn + j * F::NT + lane % F::NT];
+  };
+  auto mma = [&](int slot) {
 #pragma unroll
-        for (int j = 0; j < FN; ++j) bf[j] = bs[(ks + lane / F::NT) * LDB + wn + j * F::NT + lane % F::NT];
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) acc[i][j] = F::mma(af[i], bf[j], acc[i][j]);
-      }
-    };
-    int buf = 0;
-    if (kb < ke) {
-      la.fetch_k(g.a_k, kb);
-      lb.fetch_k(g.b_k, kb);
-      la.template load<MASK>(A, kb, ke);
-      lb.template load<MASK>(B, kb, ke);
-      la.template store<LDA, MASK>(As[0]);
-      lb.template store<LDB, MASK>(Bs[0]);
-      if (kb + BK < ke) {
-        la.fetch_k(g.a_k, kb + BK);
-        lb.fetch_k(g.b_k, kb + BK);
-        la.template load<MASK>(A, kb + BK, ke);
-        lb.template load<MASK>(B, kb + BK, ke);
-        if (kb + 2 * BK < ke) {
-          la.fetch_k(g.a_k, kb + 2 * BK);
-          lb.fetch_k(g.b_k, kb + 2 * BK);
+      for (int j = 0; j < FN; ++j) acc[i][j] = F::mma(af[slot][i], bf[slot][j], acc[i][j]);
+  };
+
+  // Pipeline per tile t (one barrier): the MFMAs read tile t from LDS buffer t&1; at the start of the tile,
+  // tile t+1 (in registers since the start of tile t-1) is staged into the other buffer, whose last reads ended
+  // at the previous barrier, and tile t+2 is loaded into registers, a whole tile ahead of its use. The barrier
+  // sits before the last k-step, after which the first fragments of tile t+1 are read. FULL: tiles t+1 and t+2
+  // exist and t+1 is complete (the steady state, without branches).
+  auto tile = [&](auto full_tag, int64_t kt, int buf) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    const T* as = As[buf];
+    const T* bs = Bs[buf];
+    if (FULL) {
+      // the staging and the global reads stay in the first k-step's scheduling region (the fence keeps the
+      // compiler from sinking the reads towards the end of the tile, which would shorten their lead)
+      read_frag(1, as, bs, F::KT);
+      mma(0);
+      la.template store<LDA, false>(As[buf ^ 1], kt + BK, ke);
+      lb.template store<LDB, false>(Bs[buf ^ 1], kt + BK, ke);
+      la.load(kt + 2 * BK, g.K, g.kl, g.kl.sa);
+      lb.load(kt + 2 * BK, g.K, g.kl, g.kl.sb);
+      __builtin_amdgcn_sched_barrier(0);
+    } else {
+      if (kt + BK < ke) {
+        la.template store_tile<LDA>(As[buf ^ 1], kt + BK, ke);
+        lb.template store_tile<LDB>(Bs[buf ^ 1], kt + BK, ke);
+        if (kt + 2 * BK < ke) {
+          la.load(kt + 2 * BK, g.K, g.kl, g.kl.sa);
+          lb.load(kt + 2 * BK, g.K, g.kl, g.kl.sb);
         }
       }
+      read_frag(1, as, bs, F::KT);
+      mma(0);
+    }
+#pragma unroll
+    for (int ks = 1; ks + 1 < NKS; ++ks) {
+      read_frag((ks + 1) & 1, as, bs, (ks + 1) * F::KT);
+      mma(ks & 1);
     }
     __syncthreads();
-    // tile t is read from LDS buffer t&1 while tile t+1 (in registers) is stored to the other buffer halfway
-    // through, and tile t+2 is fetched into registers; one barrier per tile
-    for (int64_t kt = kb; kt < ke; kt += BK) {
-      const T* as = As[buf];
-      const T* bs = Bs[buf];
-      mfma_steps(as, bs, 0, BK / 2);
-      if (kt + BK < ke) {
-        la.template store<LDA, MASK>(As[buf ^ 1]);
-        lb.template store<LDB, MASK>(Bs[buf ^ 1]);
-        if (kt + 2 * BK < ke) {
-          la.template load<MASK>(A, kt + 2 * BK, ke);
-          lb.template load<MASK>(B, kt + 2 * BK, ke);
-          if (kt + 3 * BK < ke) {
-            la.fetch_k(g.a_k, kt + 3 * BK);
-            lb.fetch_k(g.b_k, kt + 3 * BK);
-          }
-        }
-      }
-      mfma_steps(as, bs, BK / 2, BK);
-      __syncthreads();
-      buf ^= 1;
-    }
+    if (FULL || kt + BK < ke) read_frag(0, As[buf ^ 1], Bs[buf ^ 1], 0);
+    mma((NKS - 1) & 1);
   };
-  // interior tiles (all rows, columns and k in range) skip the range masks
-  const bool interior = (m0 + BM <= g.M) && (n0 + BN <= g.N) && ((ke - kb) % BK == 0);
-  if (interior) kloop(std::false_type{});
-  else kloop(std::true_type{});
+
+  if (kb < ke) {
+    la.load(kb, g.K, g.kl, g.kl.sa);
+    lb.load(kb, g.K, g.kl, g.kl.sb);
+    la.template store_tile<LDA>(As[0], kb, ke);
+    lb.template store_tile<LDB>(Bs[0], kb, ke);
+    if (kb + BK < ke) {
+      la.load(kb + BK, g.K, g.kl, g.kl.sa);
+      lb.load(kb + BK, g.K, g.kl, g.kl.sb);
+    }
+  }
+  __syncthreads();
+  if (kb < ke) read_frag(0, As[0], Bs[0], 0);
+  int64_t kt = kb;
+  int buf = 0;
+  for (; kt + 2 * BK < ke; kt += BK, buf ^= 1) tile(std::true_type{}, kt, buf);
+  for (; kt < ke; kt += BK, buf ^= 1) tile(std::false_type{}, kt, buf);
 
   // epilogue
   if (g.split) {
@@ -323,7 +405,7 @@ __device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
 
 // FP32 tiles are split into bf16 hi and lo planes when staged in LDS. Each plane is stored row-major with k
 // contiguous (row pitch BK + 8 bf16 = 80 bytes), so a lane's 8-element MFMA fragment is one 16-byte LDS read.
-template <int BM, int BN, int BK, bool AKF, bool BKF>
+template <int BM, int BN, int BK, bool AKF, bool BKF, int NKL>
 __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
   static_assert(BK == 32, "one bf16 MFMA step per tile");
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -347,10 +429,10 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
   const float* __restrict__ A = static_cast<const float*>(g.A[grp]);
   const float* __restrict__ B = static_cast<const float*>(g.B[grp]);
 
-  Loader<float, BM, BK, AKF> la;
-  Loader<float, BN, BK, BKF> lb;
-  la.init(g.a_m, m0, g.M, tid);
-  lb.init(g.b_n, n0, g.N, tid);
+  Loader<float, BM, BK, AKF, NKL> la;
+  Loader<float, BN, BK, BKF, NKL> lb;
+  la.init(A, g.a_m, m0, tid);
+  lb.init(B, g.b_n, n0, tid);
 
   f32x4 acc[FM][FN];
 #pragma unroll
@@ -359,21 +441,15 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
     for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   if (kb < ke) {
-    la.fetch_k(g.a_k, kb);
-    lb.fetch_k(g.b_k, kb);
-    la.template load<true>(A, kb, ke);
-    lb.template load<true>(B, kb, ke);
-    if (kb + BK < ke) {
-      la.fetch_k(g.a_k, kb + BK);
-      lb.fetch_k(g.b_k, kb + BK);
-    }
+    la.load(kb, g.K, g.kl, g.kl.sa);
+    lb.load(kb, g.K, g.kl, g.kl.sb);
   }
   const int kq = 8 * (lane >> 4);
   for (int64_t kt = kb; kt < ke; kt += BK) {
 #pragma unroll
     for (int i = 0; i < la.PER; ++i) {
       __bf16 h, l;
-      split_bf16(la.template value<true>(i), h, l);
+      split_bf16(la.template value<true>(i, kt, ke), h, l);
       const int r = la.r0 + (i % la.NR) * la.RSTEP, k = la.k0 + (i / la.NR) * la.KSTEP;
       Ah[r * LDK + k] = h;
       Al[r * LDK + k] = l;
@@ -381,19 +457,15 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
 #pragma unroll
     for (int i = 0; i < lb.PER; ++i) {
       __bf16 h, l;
-      split_bf16(lb.template value<true>(i), h, l);
+      split_bf16(lb.template value<true>(i, kt, ke), h, l);
       const int r = lb.r0 + (i % lb.NR) * lb.RSTEP, k = lb.k0 + (i / lb.NR) * lb.KSTEP;
       Bh[r * LDK + k] = h;
       Bl[r * LDK + k] = l;
     }
     __syncthreads();
     if (kt + BK < ke) {
-      la.template load<true>(A, kt + BK, ke);
-      lb.template load<true>(B, kt + BK, ke);
-      if (kt + 2 * BK < ke) {
-        la.fetch_k(g.a_k, kt + 2 * BK);
-        lb.fetch_k(g.b_k, kt + 2 * BK);
-      }
+      la.load(kt + BK, g.K, g.kl, g.kl.sa);
+      lb.load(kt + BK, g.K, g.kl, g.kl.sb);
     }
     bf16x8 bh[FN], bl[FN];
 #pragma unroll
@@ -494,24 +566,45 @@ __global__ void splitk_reduce_kernel(RedArgs r, int splits, int64_t M, int64_t N
   }
 }
 
+template <typename T, int BM, int BN, int BK, int NKL, bool VEC>
+void launch_tile_k(const Args& a, dim3 grid, hipStream_t s, bool akf, bool bkf) {
+  const dim3 block(256);
+  if (akf && bkf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, true, true, NKL, VEC>), grid, block, 0, s, a);
+  else if (akf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, true, false, NKL, VEC>), grid, block, 0, s, a);
+  else if (bkf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, false, true, NKL, VEC>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, false, false, NKL, VEC>), grid, block, 0, s, a);
+}
+
+// Kernels are instantiated for 2 and for 4 contracted legs (fewer legs run with zero entries), with scalar or
+// vector tile loads.
 template <typename T, int BM, int BN, int BK>
-void launch_tile(const Args& a, int groups, int splits, hipStream_t s, bool akf, bool bkf) {
+void launch_tile(const Args& a, int groups, int splits, hipStream_t s, bool akf, bool bkf, bool vec) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
-  dim3 grid((unsigned)tiles, (unsigned)groups, (unsigned)splits), block(256);
-  if (akf && bkf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, true, true>), grid, block, 0, s, a);
-  else if (akf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, true, false>), grid, block, 0, s, a);
-  else if (bkf) hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, false, true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((gett_kernel<T, BM, BN, BK, false, false>), grid, block, 0, s, a);
+  const dim3 grid((unsigned)tiles, (unsigned)groups, (unsigned)splits);
+  if (vec) {
+    if (a.kl.n <= 2) launch_tile_k<T, BM, BN, BK, 2, true>(a, grid, s, akf, bkf);
+    else launch_tile_k<T, BM, BN, BK, 4, true>(a, grid, s, akf, bkf);
+  } else {
+    if (a.kl.n <= 2) launch_tile_k<T, BM, BN, BK, 2, false>(a, grid, s, akf, bkf);
+    else launch_tile_k<T, BM, BN, BK, 4, false>(a, grid, s, akf, bkf);
+  }
+}
+
+template <int BM, int BN, int BK, int NKL>
+void launch_bf16x3_k(const Args& a, dim3 grid, hipStream_t s, bool akf, bool bkf) {
+  const dim3 block(256);
+  if (akf && bkf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, true, true, NKL>), grid, block, 0, s, a);
+  else if (akf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, true, false, NKL>), grid, block, 0, s, a);
+  else if (bkf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, false, true, NKL>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, false, false, NKL>), grid, block, 0, s, a);
 }
 
 template <int BM, int BN, int BK>
 void launch_bf16x3(const Args& a, int groups, int splits, hipStream_t s, bool akf, bool bkf) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
-  dim3 grid((unsigned)tiles, (unsigned)groups, (unsigned)splits), block(256);
-  if (akf && bkf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, true, true>), grid, block, 0, s, a);
-  else if (akf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, true, false>), grid, block, 0, s, a);
-  else if (bkf) hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, false, true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, false, false>), grid, block, 0, s, a);
+  const dim3 grid((unsigned)tiles, (unsigned)groups, (unsigned)splits);
+  if (a.kl.n <= 2) launch_bf16x3_k<BM, BN, BK, 2>(a, grid, s, akf, bkf);
+  else launch_bf16x3_k<BM, BN, BK, 4>(a, grid, s, akf, bkf);
 }
 
 struct Tile {
@@ -553,9 +646,8 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
     a.C[g] = l.C[g];
   }
   a.a_m = t.a_m;
-  a.a_k = t.a_k;
-  a.b_k = t.b_k;
   a.b_n = t.b_n;
+  a.kl = t.kl;
   a.c_m = t.c_m;
   a.c_n = t.c_n;
   a.M = t.M;
@@ -590,12 +682,18 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
     a.split = 1;
   }
   if (l.prepare_only) return;
+  // vector tile loads when both operands' layouts allow them (planned) and every base is 16-byte aligned
+  const int vw = l.prec == Prec::F64 ? 2 : 4;
+  bool vec = t.a_vw >= vw && t.b_vw >= vw && l.prec != Prec::BF16X3;
+  for (int g = 0; g < G; ++g)
+    vec = vec && ((uintptr_t)l.A[g] % 16 == 0) && ((uintptr_t)l.B[g] % 16 == 0);
   hipStream_t s = ctx.stream;
   LaunchRecord rec;
   if (ctx.profiling) {
     rec.kernel = std::string("gett<") + (l.prec == Prec::F64 ? "f64" : (l.prec == Prec::F32 ? "f32" : "bf16x3")) +
                  "," + std::to_string(BMsel) + "x" + std::to_string(BNsel) + (t.a_kfast ? ",Ak" : ",Am") +
-                 (t.b_kfast ? ",Bk" : ",Bn") + (splits > 1 ? ",splitk" : "") + (G > 1 ? ",grouped" : "") + ">";
+                 (t.b_kfast ? ",Bk" : ",Bn") + (vec ? ",v" : "") +
+                 (splits > 1 ? ",splitk" : "") + (G > 1 ? ",grouped" : "") + ">";
     rec.flops = 2.0 * G * (double)t.M * (double)t.N * (double)t.K;
     rec.bytes = G * (double)eb * ((double)t.M * t.K + (double)t.K * t.N + (double)t.M * t.N * (l.beta != 0.0 ? 2 : 1));
     rec.start = ctx.take_event();
@@ -604,17 +702,18 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
   }
   const int sel = BMsel * 1000 + BNsel;
   const bool akf = t.a_kfast, bkf = t.b_kfast;
+
   if (l.prec == Prec::F64) {
-    if (sel == 128064) launch_tile<double, 128, 64, 16>(a, G, splits, s, akf, bkf);
-    else launch_tile<double, 64, 64, 16>(a, G, splits, s, akf, bkf);
+    if (sel == 128064) launch_tile<double, 128, 64, 16>(a, G, splits, s, akf, bkf, vec);
+    else launch_tile<double, 64, 64, 16>(a, G, splits, s, akf, bkf, vec);
   } else if (l.prec == Prec::F32) {
     switch (sel) {
-      case 128192: launch_tile<float, 128, 192, 16>(a, G, splits, s, akf, bkf); break;
-      case 192128: launch_tile<float, 192, 128, 16>(a, G, splits, s, akf, bkf); break;
-      case 128128: launch_tile<float, 128, 128, 16>(a, G, splits, s, akf, bkf); break;
-      case 128064: launch_tile<float, 128, 64, 16>(a, G, splits, s, akf, bkf); break;
-      case 64128: launch_tile<float, 64, 128, 16>(a, G, splits, s, akf, bkf); break;
-      default: launch_tile<float, 64, 64, 16>(a, G, splits, s, akf, bkf); break;
+      case 128192: launch_tile<float, 128, 192, 16>(a, G, splits, s, akf, bkf, vec); break;
+      case 192128: launch_tile<float, 192, 128, 16>(a, G, splits, s, akf, bkf, vec); break;
+      case 128128: launch_tile<float, 128, 128, 16>(a, G, splits, s, akf, bkf, vec); break;
+      case 128064: launch_tile<float, 128, 64, 16>(a, G, splits, s, akf, bkf, vec); break;
+      case 64128: launch_tile<float, 64, 128, 16>(a, G, splits, s, akf, bkf, vec); break;
+      default: launch_tile<float, 64, 64, 16>(a, G, splits, s, akf, bkf, vec); break;
     }
   } else {
     switch (sel) {

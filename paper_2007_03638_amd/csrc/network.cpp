@@ -157,6 +157,72 @@ void fill_table(std::vector<int64_t>& out, const std::string& legs, const LegDim
   }
 }
 
+// Contracted legs as a mixed-radix k index for the kernels, fastest first (the last leg of `Kl` is the fastest):
+// legs of extent 1 are dropped, and a leg that continues the previous one contiguously in both operands is merged
+// into it. Each leg's reciprocal multiplier is checked exact for every quotient the kernels will form; the slowest
+// leg gets none (its digit is the remaining quotient).
+GettKLegs k_legs(const std::string& prog, const std::string& Kl, const LegDims& dims, const std::string& LA,
+                 const std::vector<int64_t>& sa, const std::string& LB, const std::vector<int64_t>& sb, int64_t K) {
+  struct Leg {
+    int64_t ext, xa, xb;
+  };
+  std::vector<Leg> legs;
+  for (int i = (int)Kl.size() - 1; i >= 0; --i) {
+    const char c = Kl[i];
+    const int64_t e = dims[(unsigned char)c];
+    if (e == 1) continue;
+    const int64_t xa = stride_of(LA, sa, c), xb = stride_of(LB, sb, c);
+    if (!legs.empty() && legs.back().xa * legs.back().ext == xa && legs.back().xb * legs.back().ext == xb)
+      legs.back().ext *= e;
+    else
+      legs.push_back(Leg{e, xa, xb});
+  }
+  if ((int)legs.size() > kGettMaxKLegs)
+    throw Error(MERA_EINVAL, prog + ": more than " + std::to_string(kGettMaxKLegs) + " contracted legs");
+  if (K >= (int64_t(1) << 31)) throw Error(MERA_EINVAL, prog + ": contracted extent too large");
+  GettKLegs kl;
+  kl.n = (int)legs.size();
+  int64_t below = 1;  // product of the faster extents
+  for (int l = 0; l < kl.n; ++l) {
+    const uint64_t e = (uint64_t)legs[l].ext;
+    kl.ext[l] = (uint32_t)e;
+    if (l + 1 < kl.n) {
+      const uint64_t qmax = (uint64_t)(K - 1) / (uint64_t)below;  // largest quotient entering leg l
+      if (qmax * e > (uint64_t(1) << 32)) throw Error(MERA_EINVAL, prog + ": contracted leg too large");
+      kl.mag[l] = (uint32_t)(((uint64_t(1) << 32) + e - 1) / e);
+    }  // the slowest leg takes the whole remaining quotient: mag 0 (no division)
+    kl.sa[l] = legs[l].xa;
+    kl.sb[l] = legs[l].xb;
+    below *= (int64_t)e;
+  }
+  return kl;
+}
+
+// The kernels' k offset (digit extraction by reciprocal multiplication over NKL legs), on the host.
+int64_t host_k_offset(uint32_t k, const GettKLegs& kl, const int64_t* stride, int nkl) {
+  int64_t off = 0;
+  uint32_t q = k;
+  for (int l = 0; l + 1 < nkl; ++l) {
+    const uint32_t qn = (uint32_t)(((uint64_t)q * kl.mag[l]) >> 32);
+    off += (int64_t)(q - qn * kl.ext[l]) * stride[l];
+    q = qn;
+  }
+  return off + (int64_t)q * stride[nkl - 1];
+}
+
+// Checks the arithmetic k offsets against the explicit offset tables of A and B, once per planned step.
+void check_k_legs(const std::string& prog, const GettKLegs& kl, const std::string& Kl, const LegDims& dims,
+                  const std::string& LA, const std::vector<int64_t>& sa, const std::string& LB,
+                  const std::vector<int64_t>& sb, int64_t K) {
+  std::vector<int64_t> ta, tb;
+  fill_table(ta, Kl, dims, LA, sa, K);
+  fill_table(tb, Kl, dims, LB, sb, K);
+  const int nkl = kl.n <= 2 ? 2 : kGettMaxKLegs;
+  for (int64_t k = 0; k < K; ++k)
+    if (host_k_offset((uint32_t)k, kl, kl.sa, nkl) != ta[k] || host_k_offset((uint32_t)k, kl, kl.sb, nkl) != tb[k])
+      throw Error(MERA_EINVAL, prog + ": contracted-leg offsets disagree with the leg strides");
+}
+
 // `dims` gives the index ranges of the step; sdims[0..2] give the extents used for the storage strides of A, B
 // and C (they differ from `dims` only in the loop leg of a full-extent tensor addressed chunk by chunk).
 PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegDims& dims,
@@ -216,15 +282,15 @@ PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegD
     return t;
   };
   const int64_t M = ext(Ml), N = ext(Nl), K = ext(Kl);
-  const int64_t Mp = roundup(M, 128), Np = roundup(N, 128), Kp = roundup(K, 32);
+  const int64_t Mp = roundup(M, 128), Np = roundup(N, 128);
   auto sa = strides_of(LA, DA), sb = strides_of(LB, DB), sc = strides_of(s.lc, *sdims[2]);
+  const GettKLegs kl = k_legs(prog.name, Kl, dims, LA, sa, LB, sb, K);
+  check_k_legs(prog.name, kl, Kl, dims, LA, sa, LB, sb, K);
   std::vector<int64_t> host;
-  host.reserve(2 * Mp + 2 * Np + 2 * Kp);
+  host.reserve(2 * Mp + 2 * Np);
   std::vector<int64_t> tmp;
-  size_t off_am, off_ak, off_bk, off_bn, off_cm, off_cn;
+  size_t off_am, off_bn, off_cm, off_cn;
   off_am = host.size(); fill_table(tmp, Ml, dims, LA, sa, Mp); host.insert(host.end(), tmp.begin(), tmp.end());
-  off_ak = host.size(); fill_table(tmp, Kl, dims, LA, sa, Kp); host.insert(host.end(), tmp.begin(), tmp.end());
-  off_bk = host.size(); fill_table(tmp, Kl, dims, LB, sb, Kp); host.insert(host.end(), tmp.begin(), tmp.end());
   off_bn = host.size(); fill_table(tmp, Nl, dims, LB, sb, Np); host.insert(host.end(), tmp.begin(), tmp.end());
   off_cm = host.size(); fill_table(tmp, Ml, dims, s.lc, sc, Mp); host.insert(host.end(), tmp.begin(), tmp.end());
   off_cn = host.size(); fill_table(tmp, Nl, dims, s.lc, sc, Np); host.insert(host.end(), tmp.begin(), tmp.end());
@@ -237,16 +303,27 @@ PlanCache::Entry& plan_step(Ctx& ctx, const Program& prog, size_t si, const LegD
   MERA_HIP(hipStreamSynchronize(ctx.stream));
   const int64_t* base = e->tables.as<int64_t>();
   e->t.a_m = base + off_am;
-  e->t.a_k = base + off_ak;
-  e->t.b_k = base + off_bk;
   e->t.b_n = base + off_bn;
   e->t.c_m = base + off_cm;
   e->t.c_n = base + off_cn;
+  e->t.kl = kl;
   e->t.M = M;
   e->t.N = N;
   e->t.K = K;
   e->t.a_kfast = a_kfast;
   e->t.b_kfast = b_kfast;
+  // vector width of the tile loads each operand's layout allows
+  auto vec_width = [&](const std::string& L, const std::vector<int64_t>& st, const std::string& walk) {
+    if (walk.empty() || walk.back() != L.back()) return 1;
+    for (int w : {4, 2}) {
+      bool ok = dims[(unsigned char)L.back()] % w == 0;
+      for (size_t i = 0; i + 1 < L.size(); ++i) ok = ok && st[i] % w == 0;
+      if (ok) return w;
+    }
+    return 1;
+  };
+  e->t.a_vw = vec_width(LA, sa, a_kfast ? Kl : Ml);
+  e->t.b_vw = vec_width(LB, sb, b_kfast ? Kl : Nl);
   e->macs = (double)M * (double)N * (double)K;
   e->swap = swap;
   auto& ref = *e;
