@@ -204,18 +204,22 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t ntiles) {
   return (b < full * 8) ? (b % 8) * full + b / 8 : b;
 }
 
-// Origin of logical tile `tile`. Consecutive tiles run along the dimension with fewer tiles, so they share a
-// panel of the operand with more tiles (the larger one), which is then read from HBM about once.
+// Origin of logical tile `tile`. Tiles are taken in groups of kTileGroup panels of the dimension with more tiles
+// (the larger operand); within a group that dimension runs fastest, then the other one. The 64 tiles an XCD runs
+// at once then cover about 8 panels of each operand, which its L2 serves to all of them: each operand is fetched
+// from beyond L2 about (tiles of the other dimension) / kTileGroup times instead of once per tile of the other
+// dimension for the smaller operand.
+constexpr int64_t kTileGroup = 8;
 template <int BM, int BN>
 __device__ inline void tile_origin(int64_t tile, int64_t M, int64_t N, int64_t& m0, int64_t& n0) {
   const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
-  if (tm >= tn) {
-    m0 = (tile / tn) * BM;
-    n0 = (tile % tn) * BN;
-  } else {
-    m0 = (tile % tm) * BM;
-    n0 = (tile / tm) * BN;
-  }
+  const bool mgroups = tm >= tn;
+  const int64_t tbig = mgroups ? tm : tn, tsmall = mgroups ? tn : tm;
+  const int64_t grp = tile / (kTileGroup * tsmall), loc = tile % (kTileGroup * tsmall);
+  const int64_t gsize = (tbig - grp * kTileGroup < kTileGroup) ? tbig - grp * kTileGroup : kTileGroup;
+  const int64_t big = grp * kTileGroup + loc % gsize, small = loc / gsize;
+  m0 = (mgroups ? big : small) * BM;
+  n0 = (mgroups ? small : big) * BN;
 }
 
 template <typename T, int BM, int BN, int BK, bool AKF, bool BKF, int NKL, bool VEC>
@@ -223,10 +227,12 @@ template <typename T, int BM, int BN, int BK, bool AKF, bool BKF, int NKL, bool 
 // accumulators in VGPRs and the 128 x 128 FP32 and 128 x 64 FP64 tiles reach 3 waves per SIMD.
 __global__ void __launch_bounds__(256, 2) gett_kernel(Args g) {
   using F = Mma<T>;
-  // vector width of the tile loads (VEC: both operands qualify); LDS rows padded to a multiple of it
+  // vector width of the tile loads (VEC: both operands qualify). LDS rows are padded: to a multiple of VW where
+  // an operand is staged with vector writes (loads along rows), else by 2 FP32 / 1 FP64 elements, which keeps the
+  // strided scalar writes of k-walking loads free of bank conflicts.
   constexpr int VW = VEC ? 16 / (int)sizeof(T) : 1;
-  constexpr int PAD = VEC ? VW : (sizeof(T) == 4 ? 2 : 1);
-  constexpr int LDA = BM + PAD, LDB = BN + PAD;
+  constexpr int PADS = sizeof(T) == 4 ? 2 : 1;
+  constexpr int LDA = BM + ((VEC && !AKF) ? VW : PADS), LDB = BN + ((VEC && !BKF) ? VW : PADS);
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / F::MT, FN = WN / F::NT;
   static_assert(FM >= 1 && FN >= 1, "wave tile smaller than one MFMA block");
@@ -692,7 +698,7 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
   if (ctx.profiling) {
     rec.kernel = std::string("gett<") + (l.prec == Prec::F64 ? "f64" : (l.prec == Prec::F32 ? "f32" : "bf16x3")) +
                  "," + std::to_string(BMsel) + "x" + std::to_string(BNsel) + (t.a_kfast ? ",Ak" : ",Am") +
-                 (t.b_kfast ? ",Bk" : ",Bn") + (vec ? ",v" : "") +
+                 (t.b_kfast ? ",Bk" : ",Bn") + (vec ? ",v" : "") + (t.kl.n <= 2 ? ",k2" : ",k4") +
                  (splits > 1 ? ",splitk" : "") + (G > 1 ? ",grouped" : "") + ">";
     rec.flops = 2.0 * G * (double)t.M * (double)t.N * (double)t.K;
     rec.bytes = G * (double)eb * ((double)t.M * t.K + (double)t.K * t.N + (double)t.M * t.N * (l.beta != 0.0 ? 2 : 1));
