@@ -273,21 +273,37 @@ void ev_update_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& 
   mm(ctx, "Y[nq] = W[np] * R[pq]", dnp, {{"Y", Y}, {"W", W.data}, {"R", rho.data}});
   axpby(ctx, -1.0, d64(D), gamma, VPtr{Y, Prec::F64}, np_);   // Y = gamma W rho - D
   double* K = tmp(ctx, "ev.K", pp);
-  mm(ctx, "K[pq] = Y[np] * Y2[nq]", dnp, {{"K", K}, {"Y", Y}, {"Y2", Y}});
-  symmetrize(ctx, VPtr{K, Prec::F64}, p);
   double* lam = tmp(ctx, "ev.lam", p);
   double* V = tmp(ctx, "ev.V", pp);
-  jacobi_eigh(ctx, K, lam, V, p);
   std::vector<double> hl(p);
-  MERA_HIP(hipMemcpyAsync(hl.data(), lam, (size_t)p * 8, hipMemcpyDeviceToHost, ctx.stream));
-  ctx.sync();
   double lmax = 0.0;
-  for (double x : hl) lmax = std::max(lmax, x);
-  for (double& x : hl) {
-    MERA_CHECK(std::isfinite(x) && x > 1e-28 * lmax && x > 0.0, MERA_ENONFINITE,
-               "Evenbly-Vidal update: gamma W rho - D is rank deficient");
-    x = 1.0 / std::sqrt(x);
+  // Y^T Y = V diag(lam) V^T; returns whether Y has full column rank
+  auto gram = [&]() {
+    mm(ctx, "K[pq] = Y[np] * Y2[nq]", dnp, {{"K", K}, {"Y", Y}, {"Y2", Y}});
+    symmetrize(ctx, VPtr{K, Prec::F64}, p);
+    jacobi_eigh(ctx, K, lam, V, p);
+    MERA_HIP(hipMemcpyAsync(hl.data(), lam, (size_t)p * 8, hipMemcpyDeviceToHost, ctx.stream));
+    ctx.sync();
+    lmax = 0.0;
+    for (double x : hl) {
+      MERA_CHECK(std::isfinite(x), MERA_ENONFINITE, "Evenbly-Vidal update: non-finite environment");
+      lmax = std::max(lmax, x);
+    }
+    MERA_CHECK(lmax > 0.0, MERA_ENONFINITE, "Evenbly-Vidal update: gamma W rho - D vanishes");
+    for (double x : hl)
+      if (!(x > 1e-24 * lmax)) return false;
+    return true;
+  };
+  int refine = 1;  // Newton-Schulz polar refinements after the eigenvalue step
+  if (!gram()) {
+    // A rank-deficient Y has many polar factors. Take the limit of polar(Y + delta W) for small delta: on Y's
+    // range it is Y's own polar factor, on the null space it keeps W's columns. Y + delta W is ill-conditioned
+    // (about 1e7), so the eigenvalue step is followed by more refinements (each squares the isometry error).
+    axpby(ctx, 1e-7 * std::sqrt(lmax), VPtr{W.data, Prec::F64}, 1.0, VPtr{Y, Prec::F64}, np_);
+    MERA_CHECK(gram(), MERA_ENONFINITE, "Evenbly-Vidal update: gamma W rho - D is rank deficient");
+    refine = 4;
   }
+  for (double& x : hl) x = 1.0 / std::sqrt(x);
   double* sdev = tmp(ctx, "ev.s", p);
   MERA_HIP(hipMemcpyAsync(sdev, hl.data(), (size_t)p * 8, hipMemcpyHostToDevice, ctx.stream));
   double* T = tmp(ctx, "ev.T", pp);
@@ -298,11 +314,15 @@ void ev_update_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& 
   mm(ctx, "Z[pq] = T[pr] * V[qr]", dpp, {{"Z", Z}, {"T", T}, {"V", V}});   // (Y^T Y)^{-1/2}
   double* Wt = tmp(ctx, "ev.W", np_);
   mm(ctx, "Wt[nq] = Y[np] * Z[pq]", dnp, {{"Wt", Wt}, {"Y", Y}, {"Z", Z}});
-  // one Newton-Schulz polar refinement: W <- W (3 - W^T W)/2
-  mm(ctx, "S[pq] = Wt[np] * Wt2[nq]", dnp, {{"S", T}, {"Wt", Wt}, {"Wt2", Wt}});
-  scal(ctx, -0.5, VPtr{T, Prec::F64}, pp);
-  add_diag(ctx, VPtr{T, Prec::F64}, p, 1.5);
-  mm(ctx, "Wo[nq] = Wt[np] * S[pq]", dnp, {{"Wo", Wout.data}, {"Wt", Wt}, {"S", T}});
+  // Newton-Schulz polar refinements W <- W (3 - W^T W)/2, the last one into Wout
+  for (int r = 0; r < refine; ++r) {
+    mm(ctx, "S[pq] = Wt[np] * Wt2[nq]", dnp, {{"S", T}, {"Wt", Wt}, {"Wt2", Wt}});
+    scal(ctx, -0.5, VPtr{T, Prec::F64}, pp);
+    add_diag(ctx, VPtr{T, Prec::F64}, p, 1.5);
+    double* dst = (r + 1 == refine) ? Wout.data : Y;  // Y is no longer needed
+    mm(ctx, "Wo[nq] = Wt[np] * S[pq]", dnp, {{"Wo", dst}, {"Wt", Wt}, {"S", T}});
+    if (r + 1 < refine) copy(ctx, VPtr{Wt, Prec::F64}, VPtr{Y, Prec::F64}, np_);
+  }
 }
 
 void Metric::compute(Ctx& ctx, const std::vector<MatView>& rho) {

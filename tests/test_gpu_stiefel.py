@@ -135,3 +135,21 @@ def test_ev_update(ctx, gamma):
         wo = to_np(wo)
         assert np.max(np.abs(wo.T @ wo - np.eye(w.shape[1]))) < 1e-13
         assert rel(wo, optim.ev_update(w, d, r, gamma)) < 1e-11
+
+
+@pytest.mark.gpu
+def test_ev_update_rank_deficient(ctx):
+    """Evenbly-Vidal update when gamma W rho - D has a null space: the result is still an isometry and a polar factor
+    of Y = gamma W rho - D (P^T Y = (Y^T Y)^{1/2}, symmetric positive semidefinite), up to the vanishing shift."""
+    n, p, gamma = 12, 6, 1.5
+    W = inputs.haar_params(60, [(n, p)])[0]
+    rho = inputs.density_matrix(61, p) + 0.01 * np.eye(p)
+    rng = np.random.default_rng(62)
+    Y0 = rng.standard_normal((n, p - 2)) @ rng.standard_normal((p - 2, p))   # rank p - 2
+    D = gamma * W @ rho - Y0
+    P = to_np(ctx.ev_update([W], [D], [rho], gamma)[0])
+    assert np.max(np.abs(P.T @ P - np.eye(p))) < 1e-12
+    S = P.T @ Y0
+    lam, V = np.linalg.eigh(Y0.T @ Y0)
+    absY = (V * np.sqrt(np.clip(lam, 0.0, None))) @ V.T
+    assert np.max(np.abs(S - absY)) < 1e-6 * np.linalg.norm(Y0, 2)
