@@ -409,6 +409,65 @@ __device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
+// Epilogue of the split-bf16 kernels: 16 x 16 accumulator blocks (acc[i] -> row 4 (lane / 16) + i, col lane % 16),
+// written as split-K partials or as C = alpha acc + beta C through the C offset tables.
+template <int FM, int FN>
+__device__ inline void bf16x3_epilogue(const Args& g, const f32x4 (&acc)[FM][FN], int64_t m0, int64_t n0, int wm,
+                                       int wn, int lane, int grp) {
+  if (g.split) {
+    float* P = static_cast<float*>(g.partial[grp]) + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+          int64_t col = n0 + wn + j * 16 + (lane & 15);
+          if (row < g.M && col < g.N) P[row * g.N + col] = acc[i][j][r];
+        }
+    return;
+  }
+  float* __restrict__ C = static_cast<float*>(g.C[grp]);
+  const float alpha = float(g.alpha), beta = float(g.beta);
+  int64_t cn[FN];
+  bool cv[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int64_t col = n0 + wn + j * 16 + (lane & 15);
+    cn[j] = g.c_n[col];
+    cv[j] = col < g.N;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    int64_t cm[4];
+    bool rv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+      cm[r] = g.c_m[row];
+      rv[r] = row < g.M;
+    }
+    float cold[FN][4];
+    if (g.beta != 0.0) {
+      // unconditional reads first (padded table entries address a valid element), then the masked stores
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cold[j][r] = C[cm[r] + cn[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (cv[j] && rv[r]) {
+          float v = alpha * acc[i][j][r];
+          if (g.beta != 0.0) v += beta * cold[j][r];
+          C[cm[r] + cn[j]] = v;
+        }
+  }
+}
+
 // FP32 tiles are split into bf16 hi and lo planes when staged in LDS. Each plane is stored row-major with k
 // contiguous (row pitch BK + 8 bf16 = 80 bytes), so a lane's 8-element MFMA fragment is one 16-byte LDS read.
 template <int BM, int BN, int BK, bool AKF, bool BKF, int NKL>
@@ -495,58 +554,160 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
     __syncthreads();
   }
 
-  if (g.split) {
-    float* P = static_cast<float*>(g.partial[grp]) + (int64_t)blockIdx.z * g.M * g.N;
+  bf16x3_epilogue<FM, FN>(g, acc, m0, n0, wm, wn, lane, grp);
+}
+
+// Split-bf16 form with 16-byte tile loads (both operands' layouts allow them): 128 x 128 tiles, BK = 32, each
+// thread loading four 4-element vectors per operand and tile. A k-walking operand's vector is 4 consecutive k of
+// one row; a row-walking operand's four vectors are the same 4 rows at 4 consecutive k, transposed in registers.
+// Either way a thread stages 4 k of a row at a time: split into hi and lo and written as one 8-byte LDS store per
+// plane (planes row-major with k contiguous, pitch BK + 8, as in the kernel above).
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+template <bool KFAST, int NKL>
+struct Bf16VecLoader {
+  static constexpr int BMN = 128, BK = 32, LDK = BK + 8;
+  const float* rowp[4];
+  int r0, k0;
+  f32x4 reg[4];
+
+  __device__ inline void init(const float* base, const int64_t* off_r, int64_t rbase, int tid) {
+    if (KFAST) {
+      r0 = tid / 8;  // rows r0 + 32 i
+      k0 = 4 * (tid % 8);
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
-          int64_t col = n0 + wn + j * 16 + (lane & 15);
-          if (row < g.M && col < g.N) P[row * g.N + col] = acc[i][j][r];
-        }
-    return;
-  }
-  float* __restrict__ C = static_cast<float*>(g.C[grp]);
-  const float alpha = float(g.alpha), beta = float(g.beta);
-  int64_t cn[FN];
-  bool cv[FN];
-#pragma unroll
-  for (int j = 0; j < FN; ++j) {
-    const int64_t col = n0 + wn + j * 16 + (lane & 15);
-    cn[j] = g.c_n[col];
-    cv[j] = col < g.N;
-  }
-#pragma unroll
-  for (int i = 0; i < FM; ++i) {
-    int64_t cm[4];
-    bool rv[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
-      cm[r] = g.c_m[row];
-      rv[r] = row < g.M;
+      for (int i = 0; i < 4; ++i) rowp[i] = base + off_r[rbase + r0 + 32 * i];
+    } else {
+      r0 = 4 * (tid % 32);  // rows r0 .. r0 + 3
+      k0 = 4 * (tid / 32);
+      rowp[0] = base + off_r[rbase + r0];
     }
-    float cold[FN][4];
-    if (g.beta != 0.0) {
-      // unconditional reads first (padded table entries address a valid element), then the masked stores
+  }
+  __device__ inline void load(int64_t kt, int64_t K, const GettKLegs& kl, const int64_t* stride) {
+    if (KFAST) {
+      const int64_t k = kt + k0;
+      const int64_t o = k_offset<NKL>((uint32_t)(k < K - 4 ? k : K - 4), kl, stride);
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
+      for (int i = 0; i < 4; ++i) reg[i] = *reinterpret_cast<const f32x4*>(rowp[i] + o);
+    } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) cold[j][r] = C[cm[r] + cn[j]];
+      for (int j = 0; j < 4; ++j) {
+        const int64_t k = kt + k0 + j;
+        const int64_t o = k_offset<NKL>((uint32_t)(k < K ? k : K - 1), kl, stride);
+        reg[j] = *reinterpret_cast<const f32x4*>(rowp[0] + o);
+      }
+    }
+  }
+  // stages the tile starting at kt; KMASK: zero past kend
+  template <bool KMASK>
+  __device__ inline void store(__bf16* hi, __bf16* lo, int64_t kt, int64_t kend) const {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bf16x4 h, l;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float x = KFAST ? reg[i][j] : reg[j][i];
+        if (KMASK && kt + k0 + j >= kend) x = 0.f;
+        __bf16 a, b;
+        split_bf16(x, a, b);
+        h[j] = a;
+        l[j] = b;
+      }
+      const int row = KFAST ? r0 + 32 * i : r0 + i;
+      *reinterpret_cast<bf16x4*>(&hi[row * LDK + k0]) = h;
+      *reinterpret_cast<bf16x4*>(&lo[row * LDK + k0]) = l;
+    }
+  }
+  __device__ inline void store_tile(__bf16* hi, __bf16* lo, int64_t kt, int64_t kend) const {
+    if (kt + BK <= kend) store<false>(hi, lo, kt, kend);
+    else store<true>(hi, lo, kt, kend);
+  }
+};
+
+// Pipeline as in gett_kernel: double-buffered planes, tile t+1 staged from registers at the start of tile t and
+// tile t+2 loaded right after (fenced), one barrier per tile; one MFMA k-step (k = 32) per tile.
+template <bool AKF, bool BKF, int NKL>
+__global__ void __launch_bounds__(256, 2) gett_bf16x3_vec_kernel(Args g) {
+  constexpr int BM = 128, BN = 128, BK = 32, LDK = BK + 8;
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN * LDK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * WM;
+  const int wn = (wave & 1) * WN;
+  int64_t m0, n0;
+  tile_origin<BM, BN>(xcd_tile(blockIdx.x, gridDim.x), g.M, g.N, m0, n0);
+  const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t ke = (g.K < kb + g.kchunk) ? g.K : kb + g.kchunk;
+  const int grp = blockIdx.y;
+  const float* __restrict__ A = static_cast<const float*>(g.A[grp]);
+  const float* __restrict__ B = static_cast<const float*>(g.B[grp]);
+
+  Bf16VecLoader<AKF, NKL> la;
+  Bf16VecLoader<BKF, NKL> lb;
+  la.init(A, g.a_m, m0, tid);
+  lb.init(B, g.b_n, n0, tid);
+
+  f32x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int kq = 8 * (lane >> 4);
+  auto compute = [&](int buf) {
+    bf16x8 bh[FN], bl[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int c = (wn + j * 16 + (lane & 15)) * LDK + kq;
+      bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[buf][c]);
+      bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[buf][c]);
     }
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+    for (int i = 0; i < FM; ++i) {
+      const int r = (wm + i * 16 + (lane & 15)) * LDK + kq;
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&Ah[buf][r]);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(&Al[buf][r]);
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (cv[j] && rv[r]) {
-          float v = alpha * acc[i][j][r];
-          if (g.beta != 0.0) v += beta * cold[j][r];
-          C[cm[r] + cn[j]] = v;
-        }
+      for (int j = 0; j < FN; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+
+  if (kb < ke) {
+    la.load(kb, g.K, g.kl, g.kl.sa);
+    lb.load(kb, g.K, g.kl, g.kl.sb);
+    la.store_tile(Ah[0], Al[0], kb, ke);
+    lb.store_tile(Bh[0], Bl[0], kb, ke);
+    if (kb + BK < ke) {
+      la.load(kb + BK, g.K, g.kl, g.kl.sa);
+      lb.load(kb + BK, g.K, g.kl, g.kl.sb);
+    }
   }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t kt = kb; kt < ke; kt += BK, buf ^= 1) {
+    if (kt + 2 * BK < ke) {
+      la.template store<false>(Ah[buf ^ 1], Al[buf ^ 1], kt + BK, ke);
+      lb.template store<false>(Bh[buf ^ 1], Bl[buf ^ 1], kt + BK, ke);
+      la.load(kt + 2 * BK, g.K, g.kl, g.kl.sa);
+      lb.load(kt + 2 * BK, g.K, g.kl, g.kl.sb);
+      __builtin_amdgcn_sched_barrier(0);
+    } else if (kt + BK < ke) {
+      la.store_tile(Ah[buf ^ 1], Al[buf ^ 1], kt + BK, ke);
+      lb.store_tile(Bh[buf ^ 1], Bl[buf ^ 1], kt + BK, ke);
+    }
+    compute(buf);
+    __syncthreads();
+  }
+  bf16x3_epilogue<FM, FN>(g, acc, m0, n0, wm, wn, lane, grp);
 }
 
 struct RedArgs {
@@ -605,10 +766,26 @@ void launch_bf16x3_k(const Args& a, dim3 grid, hipStream_t s, bool akf, bool bkf
   else hipLaunchKernelGGL((gett_bf16x3_kernel<BM, BN, BK, false, false, NKL>), grid, block, 0, s, a);
 }
 
+template <int NKL>
+void launch_bf16x3_vec_k(const Args& a, dim3 grid, hipStream_t s, bool akf, bool bkf) {
+  const dim3 block(256);
+  if (akf && bkf) hipLaunchKernelGGL((gett_bf16x3_vec_kernel<true, true, NKL>), grid, block, 0, s, a);
+  else if (akf) hipLaunchKernelGGL((gett_bf16x3_vec_kernel<true, false, NKL>), grid, block, 0, s, a);
+  else if (bkf) hipLaunchKernelGGL((gett_bf16x3_vec_kernel<false, true, NKL>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gett_bf16x3_vec_kernel<false, false, NKL>), grid, block, 0, s, a);
+}
+
 template <int BM, int BN, int BK>
-void launch_bf16x3(const Args& a, int groups, int splits, hipStream_t s, bool akf, bool bkf) {
+void launch_bf16x3(const Args& a, int groups, int splits, hipStream_t s, bool akf, bool bkf, bool vec) {
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
   const dim3 grid((unsigned)tiles, (unsigned)groups, (unsigned)splits);
+  if constexpr (BM == 128 && BN == 128 && BK == 32) {
+    if (vec) {
+      if (a.kl.n <= 2) launch_bf16x3_vec_k<2>(a, grid, s, akf, bkf);
+      else launch_bf16x3_vec_k<4>(a, grid, s, akf, bkf);
+      return;
+    }
+  }
   if (a.kl.n <= 2) launch_bf16x3_k<BM, BN, BK, 2>(a, grid, s, akf, bkf);
   else launch_bf16x3_k<BM, BN, BK, 4>(a, grid, s, akf, bkf);
 }
@@ -690,9 +867,10 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
   if (l.prepare_only) return;
   // vector tile loads when both operands' layouts allow them (planned) and every base is 16-byte aligned
   const int vw = l.prec == Prec::F64 ? 2 : 4;
-  bool vec = t.a_vw >= vw && t.b_vw >= vw && l.prec != Prec::BF16X3;
+  bool vec = t.a_vw >= vw && t.b_vw >= vw;
   for (int g = 0; g < G; ++g)
     vec = vec && ((uintptr_t)l.A[g] % 16 == 0) && ((uintptr_t)l.B[g] % 16 == 0);
+  if (l.prec == Prec::BF16X3) vec = vec && BMsel == 128 && BNsel == 128;  // the vector split-bf16 kernel's tile
   hipStream_t s = ctx.stream;
   LaunchRecord rec;
   if (ctx.profiling) {
@@ -723,10 +901,10 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
     }
   } else {
     switch (sel) {
-      case 128128: launch_bf16x3<128, 128, 32>(a, G, splits, s, akf, bkf); break;
-      case 128064: launch_bf16x3<128, 64, 32>(a, G, splits, s, akf, bkf); break;
-      case 64128: launch_bf16x3<64, 128, 32>(a, G, splits, s, akf, bkf); break;
-      default: launch_bf16x3<64, 64, 32>(a, G, splits, s, akf, bkf); break;
+      case 128128: launch_bf16x3<128, 128, 32>(a, G, splits, s, akf, bkf, vec); break;
+      case 128064: launch_bf16x3<128, 64, 32>(a, G, splits, s, akf, bkf, vec); break;
+      case 64128: launch_bf16x3<64, 128, 32>(a, G, splits, s, akf, bkf, vec); break;
+      default: launch_bf16x3<64, 64, 32>(a, G, splits, s, akf, bkf, vec); break;
     }
   }
   MERA_HIP(hipGetLastError());
