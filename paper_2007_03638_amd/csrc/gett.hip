@@ -224,7 +224,7 @@ __device__ inline void tile_origin(int64_t tile, int64_t M, int64_t N, int64_t& 
 
 template <typename T, int BM, int BN, int BK, bool AKF, bool BKF, int NKL, bool VEC>
 // At most 256 registers per lane (2 waves per SIMD) for every tile; the register allocator then keeps the
-// accumulators in VGPRs and the 128 x 128 FP32 and 128 x 64 FP64 tiles reach 3 waves per SIMD.
+// accumulators in VGPRs (the 128 x 64 FP64 tile fits in 168 and runs 3 waves per SIMD).
 __global__ void __launch_bounds__(256, 2) gett_kernel(Args g) {
   using F = Mma<T>;
   // vector width of the tile loads (VEC: both operands qualify). LDS rows are padded: to a multiple of VW where
@@ -380,18 +380,17 @@ __global__ void __launch_bounds__(256, 2) gett_kernel(Args g) {
       rv[r] = row < g.M;
     }
     if (g.beta != 0.0) {
-      // all reads of C first, unconditionally (padded table entries address element 0 of a valid row or
-      // column), so they are in flight together; then the masked read-modify-write stores
-      T cold[FN][F::NACC];
+      // per MFMA block, all reads of C first, unconditionally (padded table entries address element 0 of a
+      // valid row or column), so they are in flight together; then the masked read-modify-write stores
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
+      for (int j = 0; j < FN; ++j) {
+        T cold[F::NACC];
 #pragma unroll
-        for (int r = 0; r < F::NACC; ++r) cold[j][r] = C[cm[r] + cn[j]];
-#pragma unroll
-      for (int j = 0; j < FN; ++j)
+        for (int r = 0; r < F::NACC; ++r) cold[r] = C[cm[r] + cn[j]];
 #pragma unroll
         for (int r = 0; r < F::NACC; ++r)
-          if (cv[j] && rv[r]) C[cm[r] + cn[j]] = alpha * acc[i][j][r] + beta * cold[j][r];
+          if (cv[j] && rv[r]) C[cm[r] + cn[j]] = alpha * acc[i][j][r] + beta * cold[r];
+      }
     } else {
 #pragma unroll
       for (int j = 0; j < FN; ++j)
