@@ -190,9 +190,9 @@ const char* const kTDesL[] = {
     "Wl[fpFP] = w[xyfp] * w[xyFP]",
     "Wr[cbqCBQ] = w[cbzq] * w[CBzQ]",
     "U[afcAFC] = u[eafc] * u[eAFC]",
-    "R1[pPcbCB] = rho[pqPQ] * Wr[cbqCBQ]",
-    "R2[cbCBfF] = R1[pPcbCB] * Wl[fpFP]",
-    "out[abAB] += 0.3333333333333333 * R2[cbCBfF] * U[afcAFC]",
+    "R1[pPbBcC] = rho[pqPQ] * Wr[cbqCBQ]",
+    "R2[bBfcFC] = R1[pPbBcC] * Wl[fpFP]",
+    "out[abAB] += 0.3333333333333333 * R2[bBfcFC] * U[afcAFC]",
 };
 const char* const kTDesC[] = {
     "Wl[acpACP] = w[xacp] * w[xACP]",
@@ -218,15 +218,15 @@ const char* const kTGradL[] = {
     "U[afcAFC] = u[eafc] * u[eAFC]",
     "T1[bBfcFC] = h[abAB] * U[afcAFC]",
     "T2[bBcCpP] = T1[bBfcFC] * Wl[fpFP]",
-    "R1[pPcbCB] = rho[pqPQ] * Wr[cbqCBQ]",
-    "R2[cbCBfF] = R1[pPcbCB] * Wl[fpFP]",
-    "X1[aAcCfF] = h[abAB] * R2[cbCBfF]",
-    "Du[eafc] += 0.6666666666666666 * X1[aAcCfF] * u[eAFC]",
-    "Mwl[fFpP] = T1[bBfcFC] * R1[pPcbCB]",
+    "R1[pPbBcC] = rho[pqPQ] * Wr[cbqCBQ]",
+    "R2[bBfcFC] = R1[pPbBcC] * Wl[fpFP]",
+    "X1[acfAFC] = h[abAB] * R2[bBfcFC]",
+    "Du[eafc] += 0.6666666666666666 * X1[acfAFC] * u[eAFC]",
+    "Mwl[fFpP] = T1[bBfcFC] * R1[pPbBcC]",
     "Dw[xyfp] += 0.6666666666666666 * w[xyFP] * Mwl[fFpP]",
     "Mwr[bBcCqQ] = T2[bBcCpP] * rho[pqPQ]",
     "Dw[cbzq] += 0.6666666666666666 * Mwr[bBcCqQ] * w[CBzQ]",
-    "rhoout[abAB] += 0.3333333333333333 * R2[cbCBfF] * U[afcAFC]",
+    "rhoout[abAB] += 0.3333333333333333 * R2[bBfcFC] * U[afcAFC]",
 };
 const char* const kTGradC[] = {
     "Wl[acpACP] = w[xacp] * w[xACP]",
