@@ -29,6 +29,24 @@ def test_descending_diagrams_equal_ring_rdms(a, b):
     assert np.allclose(finite.rdm(low, [2, 3]), tm.descend_one('R', rho_top, u, w, a, b), atol=1e-13)
 
 
+@pytest.mark.parametrize("a,b", [(2, 2), (2, 3)])
+def test_preconditioner_rdms_equal_ring_rdms(a, b):
+    """Brute force for the density matrices of the preconditioner (Sec. 4): on an explicit 3-site upper ring,
+    rho_w is the mean of the one-site RDMs of the two sites of rho_top, and rho_u is the two-site RDM on the inner
+    legs (2, 3) of w_0 (x) w_1 after the isometries alone (disentanglers set to the identity)."""
+    rng = np.random.default_rng(a * 7 + b)
+    u, w = _layer(11, a, b)
+    top = rng.standard_normal((b, b, b))
+    top /= np.linalg.norm(top)
+    rho_top = finite.rdm(top, [0, 1])
+    _, w_si = inputs.haar_params(12, [(b * b, b * b), (b ** 3, b)])
+    out = tm.preconditioner_rdms([None, rho_top], [(u, w), (None, w_si)], [(a, b), (b, b)])
+    rho_u, rho_w = out[0]
+    assert np.allclose(rho_w, 0.5 * (finite.rdm(top, [0]) + finite.rdm(top, [1])), atol=1e-13)
+    low_w = tm.apply_layer(top, np.eye(a * a), w, a, b)
+    assert np.allclose(rho_u, finite.rdm(low_w, [2, 3]), atol=1e-13)
+
+
 def test_map_identities():
     a, b = 3, 4
     u, w = _layer(5, a, b)
