@@ -20,6 +20,8 @@
 // counted twice, which with the 1/2 of the position average gives weight 1.
 #include "mera_eval.h"
 
+#include <array>
+
 #include <cmath>
 #include <functional>
 
@@ -142,6 +144,82 @@ const char* const kGradR[] = {
     "dT2[eECFcf] = dT3[qeEhdCF] * UW[cdhfq]",
     "dT1[eCcfAB] = dT2[eECFcf] * u[ABEF]",
     "Du[ABEF] += T1[cABCef] * dT2[eECFcf]",
+    "rhoout[abcABC] += 0.5 * dT1[eCcfAB] * u[abef]",
+    "Dw[xep] += dW1[eEpP] * w[xEP]",
+    "@end",
+    "Du[cdgh] += dUW[cfqhd] * w[fgq]",
+    "Dw[fgq] += u[cdgh] * dUW[cfqhd]",
+    "Dw[hyr] += dW3[hHrR] * w[HyR]",
+};
+// The same two derivative programs split into a forward half, which also produces the layer's ascended operator,
+// and a reverse half. The forward half keeps the activations the reverse half reads (F1, F2, F4, F5: a^6, a^6,
+// a^4 b^2 and a^2 b^4 elements) in caller buffers, so a transition layer's forward pass, which its ascending map
+// computes anyway, is not repeated in its derivative.
+const char* const kFwdL[] = {
+    "W1[epEP] = w[xep] * w[xEP]",
+    "W3[hrHR] = w[hyr] * w[HyR]",
+    "UW[daegq] = u[daef] * w[fgq]",
+    "@loop h",
+    "F1[BChAag] = h[abcABC] * u[bcgh]",
+    "F2[aghHAG] = F1[BChAag] * u[BCGH]",
+    "T3[hHAGdeq] = F2[aghHAG] * UW[daegq]",
+    "F4[hHeqEQ] = T3[hHAGdeq] * UW[dAEGQ]",
+    "F5[hHqQpP] = F4[hHeqEQ] * W1[epEP]",
+    "out[pqrPQR] += 0.5 * F5[hHqQpP] * W3[hrHR]",
+    "@end",
+};
+const char* const kRevL[] = {
+    "W1[epEP] = w[xep] * w[xEP]",
+    "W3[hrHR] = w[hyr] * w[HyR]",
+    "UW[daegq] = u[daef] * w[fgq]",
+    "UWb[dAGEQ] = u[dAEF] * w[FGQ]",
+    "@zero dW1 dUW",
+    "@loop h",
+    "dT5[pPhHqQ] = rho[pqrPQR] * W3[hrHR]",
+    "dW3[hHrR] = F5[hHqQpP] * rho[pqrPQR]",
+    "dT4[qhHeEQ] = dT5[pPhHqQ] * W1[epEP]",
+    "dW1[eEpP] += F4[hHeqEQ] * dT5[pPhHqQ]",
+    "dT3[qhHedAG] = dT4[qhHeEQ] * UWb[dAGEQ]",
+    "dUW[agqed] += F2[aghHAG] * dT3[qhHedAG]",
+    "dT2[hHAGag] = dT3[qhHedAG] * UW[daegq]",
+    "dT1[hAagBC] = dT2[hHAGag] * u[BCGH]",
+    "Du[BCGH] += F1[BChAag] * dT2[hHAGag]",
+    "rhoout[abcABC] += 0.5 * dT1[hAagBC] * u[bcgh]",
+    "Dw[hyr] += dW3[hHrR] * w[HyR]",
+    "@end",
+    "Du[daef] += dUW[agqed] * w[fgq]",
+    "Dw[fgq] += u[daef] * dUW[agqed]",
+    "Dw[xep] += dW1[eEpP] * w[xEP]",
+};
+const char* const kFwdR[] = {
+    "W1[epEP] = w[xep] * w[xEP]",
+    "W3[hrHR] = w[hyr] * w[HyR]",
+    "UW[cdhfq] = u[cdgh] * w[fgq]",
+    "@loop e",
+    "F1[cABCef] = h[abcABC] * u[abef]",
+    "F2[cfeECF] = F1[cABCef] * u[ABEF]",
+    "T3[eECFdhq] = F2[cfeECF] * UW[cdhfq]",
+    "F4[eEhqHQ] = T3[eECFdhq] * UW[CdHFQ]",
+    "F5[eEqQrR] = F4[eEhqHQ] * W3[hrHR]",
+    "out[pqrPQR] += 0.5 * F5[eEqQrR] * W1[epEP]",
+    "@end",
+};
+const char* const kRevR[] = {
+    "W1[epEP] = w[xep] * w[xEP]",
+    "W3[hrHR] = w[hyr] * w[HyR]",
+    "UW[cdhfq] = u[cdgh] * w[fgq]",
+    "UWb[dCFHQ] = u[CdGH] * w[FGQ]",
+    "@zero dW3 dUW",
+    "@loop e",
+    "dT5[rReEqQ] = rho[pqrPQR] * W1[epEP]",
+    "dW1[eEpP] = F5[eEqQrR] * rho[pqrPQR]",
+    "dT4[qeEhHQ] = dT5[rReEqQ] * W3[hrHR]",
+    "dW3[hHrR] += F4[eEhqHQ] * dT5[rReEqQ]",
+    "dT3[qeEhdCF] = dT4[qeEhHQ] * UWb[dCFHQ]",
+    "dUW[cfqhd] += F2[cfeECF] * dT3[qeEhdCF]",
+    "dT2[eECFcf] = dT3[qeEhdCF] * UW[cdhfq]",
+    "dT1[eCcfAB] = dT2[eECFcf] * u[ABEF]",
+    "Du[ABEF] += F1[cABCef] * dT2[eECFcf]",
     "rhoout[abcABC] += 0.5 * dT1[eCcfAB] * u[abef]",
     "Dw[xep] += dW1[eEpP] * w[xEP]",
     "@end",
@@ -274,16 +352,21 @@ std::vector<std::string> lines(const char* const (&a)[N]) {
 }
 
 struct Programs {
-  Program asc[2], des[2], grad[2], rhou;
+  Program asc[2], des[2], grad[2], fwd[2], rev[2], rhou;
   Program tasc[3], tdes[3], tgrad[3], trhou;  // ternary geometry
   Programs() {
-    const std::vector<std::string> ext = {"h", "u", "w", "rho", "out", "Du", "Dw", "rhoout", "rho2", "rhou"};
+    const std::vector<std::string> ext = {"h",  "u",    "w",    "rho", "out", "Du", "Dw", "rhoout",
+                                          "rho2", "rhou", "F1",  "F2",  "F4",  "F5"};
     asc[0] = Program::parse("ascL", lines(kAscL), ext);
     asc[1] = Program::parse("ascR", lines(kAscR), ext);
     des[0] = Program::parse("desL", lines(kDesL), ext);
     des[1] = Program::parse("desR", lines(kDesR), ext);
     grad[0] = Program::parse("gradL", lines(kGradL), ext);
     grad[1] = Program::parse("gradR", lines(kGradR), ext);
+    fwd[0] = Program::parse("fwdL", lines(kFwdL), ext);
+    fwd[1] = Program::parse("fwdR", lines(kFwdR), ext);
+    rev[0] = Program::parse("revL", lines(kRevL), ext);
+    rev[1] = Program::parse("revR", lines(kRevR), ext);
     rhou = Program::parse("rhou", lines(kRhoU), ext);
     tasc[0] = Program::parse("tascL", lines(kTAscL), ext);
     tasc[1] = Program::parse("tascC", lines(kTAscC), ext);
@@ -296,8 +379,8 @@ struct Programs {
     tgrad[2] = Program::parse("tgradR", lines(kTGradR), ext);
     trhou = Program::parse("trhou", lines(kTRhoU), ext);
     // the chi^9 (binary) and chi^8 (ternary) networks are worth grouping across concurrent jobs
-    for (Program* p : {&asc[0], &asc[1], &des[0], &des[1], &grad[0], &grad[1], &tasc[0], &tasc[1], &tasc[2],
-                       &tdes[0], &tdes[1], &tdes[2], &tgrad[0], &tgrad[1], &tgrad[2]})
+    for (Program* p : {&asc[0], &asc[1], &des[0], &des[1], &grad[0], &grad[1], &fwd[0], &fwd[1], &rev[0], &rev[1],
+                       &tasc[0], &tasc[1], &tasc[2], &tdes[0], &tdes[1], &tdes[2], &tgrad[0], &tgrad[1], &tgrad[2]})
       p->batch = true;
   }
 };
@@ -367,6 +450,16 @@ std::vector<LayerDim> layer_dims(const mera_shape& s) {
   return out;
 }
 
+size_t activation_cache_bytes(const std::vector<LayerDim>& dims, size_t eb) {
+  if (dims.empty() || dims[0].ternary) return 0;
+  size_t bytes = 0;
+  for (size_t t = 0; t + 1 < dims.size(); ++t) {
+    const int64_t a = dims[t].a, b = dims[t].b;
+    bytes += 2 * eb * (size_t)(2 * a * a * a * a * a * a + a * a * a * a * b * b + a * a * b * b * b * b);
+  }
+  return bytes;
+}
+
 namespace {
 
 // diagrams of one layer map: the L/R pair (binary) or L/C/R (ternary)
@@ -406,6 +499,48 @@ void layer_grad(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr h, VPtr rho, V
     run_program(ctx, grad_prog(L, s), d,
                 {{"h", h.p}, {"rho", rho.p}, {"u", t.u}, {"w", t.w}, {"Du", Du.p}, {"Dw", Dw.p},
                  {"rhoout", rhoout.p}},
+                prec, ch);
+  symmetrize(ctx, rhoout, L.opdim(L.a));
+}
+
+// Caller buffers of the forward activations of one transition layer, per diagram: F1, F2, F4, F5.
+struct Activations {
+  void* F[2][4] = {};
+};
+
+// Element counts of F1, F2, F4, F5 (the same for both diagrams).
+std::array<int64_t, 4> activation_elems(const LayerDim& L) {
+  const int64_t a = L.a, b = L.b;
+  return {a * a * a * a * a * a, a * a * a * a * a * a, a * a * a * a * b * b, a * a * b * b * b * b};
+}
+
+// Ascending map of a binary transition layer through the forward halves of its derivative programs, keeping the
+// activations for layer_grad_rev.
+void ascend_fwd(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr in, VPtr out, Prec prec, const Activations& act) {
+  fill(ctx, out, L.opsize(L.b), 0.0);
+  const LegDims d = legs_of(L);
+  const int64_t ch = loop_chunk(ctx, L, elem_bytes(prec));
+  for (int s = 0; s < 2; ++s)
+    run_program(ctx, programs().fwd[s], d,
+                {{"h", in.p}, {"u", t.u}, {"w", t.w}, {"out", out.p}, {"F1", act.F[s][0]}, {"F2", act.F[s][1]},
+                 {"F4", act.F[s][2]}, {"F5", act.F[s][3]}},
+                prec, ch);
+  symmetrize(ctx, out, L.opdim(L.b));
+}
+
+// layer_grad from the activations ascend_fwd kept (the reverse halves only).
+void layer_grad_rev(Ctx& ctx, const LayerDim& L, LayerTensors t, VPtr rho, VPtr Du, VPtr Dw, VPtr rhoout, Prec prec,
+                    const Activations& act) {
+  const int64_t a2 = (int64_t)L.a * L.a;
+  fill(ctx, Du, a2 * a2, 0.0);
+  fill(ctx, Dw, L.wrows() * L.b, 0.0);
+  fill(ctx, rhoout, L.opsize(L.a), 0.0);
+  const LegDims d = legs_of(L);
+  const int64_t ch = loop_chunk(ctx, L, elem_bytes(prec));
+  for (int s = 0; s < 2; ++s)
+    run_program(ctx, programs().rev[s], d,
+                {{"rho", rho.p}, {"u", t.u}, {"w", t.w}, {"Du", Du.p}, {"Dw", Dw.p}, {"rhoout", rhoout.p},
+                 {"F1", act.F[s][0]}, {"F2", act.F[s][1]}, {"F4", act.F[s][2]}, {"F5", act.F[s][3]}},
                 prec, ch);
   symmetrize(ctx, rhoout, L.opdim(L.a));
 }
@@ -574,9 +709,21 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
   std::vector<VPtr> hs(T + 1);
   hs[0] = VPtr{ctx.buf("hs0", S.opsize(shape.d) * eb), prec};
   copy(ctx, hs[0], VPtr{(void*)h3, Prec::F64}, S.opsize(shape.d));
+  // binary transition layers keep their forward activations for their derivatives when they fit the limit
+  const bool cache = activation_cache_bytes(dims, eb) > 0 && activation_cache_bytes(dims, eb) <= ctx.inter_limit;
+  std::vector<Activations> acts(T);
+  if (cache)
+    for (int t = 0; t < T; ++t) {
+      const auto n = activation_elems(dims[t]);
+      for (int s = 0; s < 2; ++s)
+        for (int j = 0; j < 4; ++j)
+          acts[t].F[s][j] = ctx.buf("act" + std::to_string(t) + "." + std::to_string(s) + "." + std::to_string(j),
+                                    (size_t)n[j] * eb);
+    }
   for (int t = 0; t < T; ++t) {
     hs[t + 1] = VPtr{ctx.buf("hs" + std::to_string(t + 1), S.opsize(dims[t].b) * eb), prec};
-    ascend_raw(ctx, dims[t], lt[t], hs[t], hs[t + 1], prec);
+    if (cache) ascend_fwd(ctx, dims[t], lt[t], hs[t], hs[t + 1], prec, acts[t]);
+    else ascend_raw(ctx, dims[t], lt[t], hs[t], hs[t + 1], prec);
   }
 
   const double tol = ko.tol > 0 ? ko.tol : (prec == Prec::F64 ? 1e-13 : 1e-7);
@@ -665,7 +812,8 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
     // scale-invariant layer, whose bottom is rho_s itself
     const bool keep = (t >= 1 && t < T);
     VPtr rdown{ctx.buf(keep ? "rl" + std::to_string(t) : std::string("rl.discard"), L.opsize(L.a) * eb), prec};
-    layer_grad(ctx, L, lt[t], hin, rtop, Du, Dw, rdown, prec);
+    if (cache && t < T) layer_grad_rev(ctx, L, lt[t], rtop, Du, Dw, rdown, prec, acts[t]);
+    else layer_grad(ctx, L, lt[t], hin, rtop, Du, Dw, rdown, prec);
     if (keep) rl[t] = rdown;
     if (prec != Prec::F64) {
       copy(ctx, VPtr{out.Du[t], Prec::F64}, Du, a2 * a2);

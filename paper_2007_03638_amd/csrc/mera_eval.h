@@ -22,6 +22,10 @@ struct LayerDim {
 // Transition layers 0..T-1 then the scale-invariant layer T (a = b = chi). Throws MERA_EINVAL if b_T != chi.
 std::vector<LayerDim> layer_dims(const mera_shape& s);
 
+// Bytes the binary transition layers' forward activations take when an evaluation keeps them for the derivative
+// (0 for the ternary geometry, which does not keep them); kept only when within the context's intermediate limit.
+size_t activation_cache_bytes(const std::vector<LayerDim>& dims, size_t eb);
+
 // Device views of one evaluation point, all FP64 row-major (u: a^2 x a^2, w: a^2 x b or a^3 x b).
 struct Point {
   std::vector<const double*> u, w;
