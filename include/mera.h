@@ -93,7 +93,9 @@ int mera_ctx_kernel_stats(mera_ctx* ctx, mera_kernel_stat* out, int cap);
 
 /* Memory bound for the two largest intermediates of a layer program (7-leg tensors of a^6 b elements): when one
  * would exceed `bytes`, the program runs in chunks of a spectator leg so that each chunked intermediate stays
- * within bytes/2 (default 32 GiB; results are unchanged up to rounding order). */
+ * within bytes/2 (default 32 GiB; results are unchanged up to rounding order). The same bound decides whether a
+ * binary evaluation keeps the transition layers' forward activations for their derivatives (kept when their total,
+ * 2 (2 a^6 + a^4 b^2 + a^2 b^4) elements per layer, fits; results equal up to rounding order either way). */
 mera_status mera_ctx_set_intermediate_limit(mera_ctx* ctx, size_t bytes);
 
 /* Layer dimensions: a_out[0..T], b_out[0..T] (host arrays of T+1 ints). */
