@@ -123,7 +123,8 @@ mera_status mera_warm_create(mera_ctx* ctx, const mera_shape* shape, mera_warm**
 void mera_warm_destroy(mera_warm* warm);
 
 typedef struct {
-  int krylov_dim;          /* Krylov subspace dimension per restart (App. B suggests 4); 0 -> 4          */
+  int krylov_dim;          /* Krylov subspace dimension per restart (App. B suggests 4); 0 -> 16, or    */
+                           /* fewer (at least 4) to keep the basis within 16 GiB                       */
   int max_restarts;        /* per solve; 0 -> 200                                                      */
   double tol;              /* relative residual of both solves; 0 -> 1e-13 (FP64) or 1e-7 (FP32/BF16X3)  */
 } mera_krylov_opts;

@@ -450,6 +450,11 @@ std::vector<LayerDim> layer_dims(const mera_shape& s) {
   return out;
 }
 
+int default_krylov_dim(size_t vector_bytes) {
+  const double fit = (double)((size_t)16 << 30) / (double)vector_bytes - 1.0;  // basis of dim + 1 vectors
+  return (int)std::max(4.0, std::min(16.0, std::floor(fit)));
+}
+
 size_t activation_cache_bytes(const std::vector<LayerDim>& dims, size_t eb) {
   if (dims.empty() || dims[0].ternary) return 0;
   size_t bytes = 0;
@@ -727,7 +732,7 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
   }
 
   const double tol = ko.tol > 0 ? ko.tol : (prec == Prec::F64 ? 1e-13 : 1e-7);
-  const int kdim = ko.dim > 0 ? ko.dim : 4;
+  const int kdim = ko.dim > 0 ? ko.dim : default_krylov_dim((size_t)n6 * eb);
   const int kres = ko.max_restarts > 0 ? ko.max_restarts : 200;
 
   // scale-invariant density matrix: x - D(x) + Tr[x] sigma = sigma, sigma = warm start with unit trace

@@ -22,6 +22,11 @@ struct LayerDim {
 // Transition layers 0..T-1 then the scale-invariant layer T (a = b = chi). Throws MERA_EINVAL if b_T != chi.
 std::vector<LayerDim> layer_dims(const mera_shape& s);
 
+// Krylov dimension used when the caller gives none: 16, or fewer so that the basis (dimension + 1 operators of
+// vector_bytes each) stays within 16 GiB, but at least 4. Near a critical point the GMRES solves need about 14 steps
+// per evaluation (measured at chi = 24); restarting after 4 costs about 25 % more operator applications there.
+int default_krylov_dim(size_t vector_bytes);
+
 // Bytes the binary transition layers' forward activations take when an evaluation keeps them for the derivative
 // (0 for the ternary geometry, which does not keep them); kept only when within the context's intermediate limit.
 size_t activation_cache_bytes(const std::vector<LayerDim>& dims, size_t eb);

@@ -40,8 +40,10 @@ size_t job_footprint(const mera_shape& s, Prec prec) {
     bytes = std::max(bytes, layer);
   }
   const double chi6 = (double)dims.back().opsize(s.chi);
-  // Krylov basis (dim 4 + residual), fixed point, h~, sigma, scratch, hs/rho levels, FP64 warm starts
-  bytes += eb * chi6 * (6 + 6 + 2 * (s.T + 1)) + 16.0 * chi6;
+  // Krylov basis (default dimension + 1 vectors, residual), fixed point, h~, sigma, scratch, hs/rho levels, FP64
+  // warm starts
+  const int kdim = default_krylov_dim((size_t)(eb * chi6));
+  bytes += eb * chi6 * ((kdim + 2) + 6 + 2 * (s.T + 1)) + 16.0 * chi6;
   // forward activations of the transition layers, kept within the default intermediate limit
   const double act = (double)activation_cache_bytes(dims, elem_bytes(prec));
   if (act <= (double)((size_t)32 << 30)) bytes += act;
