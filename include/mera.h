@@ -316,7 +316,8 @@ mera_status mera_server_submit(mera_server* srv, const mera_job* job, uint64_t* 
 /* MERA_EBUSY while queued or running; MERA_OK with the result once finished (or the job's error status,
  * with out->status set to it). Time to converged = queued_seconds + seconds. */
 mera_status mera_server_poll(mera_server* srv, uint64_t job_id, mera_result* out);
-/* Device bytes a job of this shape and precision needs (admission estimate). */
+/* Device bytes a job of this shape and precision needs (admission estimate, default Krylov dimension). The server
+ * admits a job with polish_tol > 0 at its FP64 size, which it reaches once polishing starts. */
 size_t mera_job_footprint(const mera_shape* shape, mera_prec prec);
 void mera_server_destroy(mera_server* srv);
 

@@ -43,7 +43,7 @@ struct Warm {
 };
 
 struct KrylovOpts {
-  int dim = 4;
+  int dim = 0;  // 0: default_krylov_dim of the vector size
   int max_restarts = 200;
   double tol = 0.0;  // 0: precision default
 };

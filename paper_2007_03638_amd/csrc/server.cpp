@@ -21,7 +21,7 @@ namespace mera {
 
 int ctx_device_of(const mera_ctx* ctx);  // capi.cpp
 
-size_t job_footprint(const mera_shape& s, Prec prec) {
+size_t job_footprint(const mera_shape& s, Prec prec, int krylov_dim = 0) {
   auto dims = layer_dims(s);
   const double eb = (double)elem_bytes(prec);
   double bytes = 0;
@@ -40,9 +40,8 @@ size_t job_footprint(const mera_shape& s, Prec prec) {
     bytes = std::max(bytes, layer);
   }
   const double chi6 = (double)dims.back().opsize(s.chi);
-  // Krylov basis (default dimension + 1 vectors, residual), fixed point, h~, sigma, scratch, hs/rho levels, FP64
-  // warm starts
-  const int kdim = default_krylov_dim((size_t)(eb * chi6));
+  // Krylov basis (dimension + 1 vectors, residual), fixed point, h~, sigma, scratch, hs/rho levels, FP64 warm starts
+  const int kdim = krylov_dim > 0 ? krylov_dim : default_krylov_dim((size_t)(eb * chi6));
   bytes += eb * chi6 * ((kdim + 2) + 6 + 2 * (s.T + 1)) + 16.0 * chi6;
   // forward activations of the transition layers, kept within the default intermediate limit
   const double act = (double)activation_cache_bytes(dims, elem_bytes(prec));
@@ -434,7 +433,9 @@ mera_status mera_server_submit(mera_server* srv, const mera_job* job, uint64_t* 
   if (!srv || !job || !job_id) return MERA_EINVAL;
   try {
     JobSpec spec = JobSpec::from_c(*job);
-    const size_t fp = job_footprint(spec.shape, spec.prec);
+    // a job that may switch to FP64 polishing holds FP64 buffers from then on: admit it at that size
+    const Prec peak = spec.polish_tol > 0 ? Prec::F64 : spec.prec;
+    const size_t fp = job_footprint(spec.shape, peak, spec.krylov.dim);
     if (fp > srv->s.budget) return MERA_ENOMEM;
     {
       std::lock_guard<std::mutex> lk(srv->s.mu);
