@@ -4,7 +4,7 @@
 Workload (default): TFIM h = 1 with two spins per blocked site (d = 4, 3-site term), chi = 24, three transition
 layers plus the scale-invariant layer, Haar-random initial tensors (seed 2), FP32 MFMA contractions with FP64
 retraction / density-matrix normalisation / L-BFGS scalars, Hilbert-space preconditioner, L-BFGS memory 8,
-warm-started Krylov solves (dimension 4). One step = one L-BFGS iteration of the library's optimiser
+warm-started Krylov solves (the library's default dimension: 16 at this size). One step = one L-BFGS iteration of the library's optimiser
 (mera_opt_step): its energy+gradient evaluation(s), projection, preconditioned two-loop, line search,
 polar retraction and transport. value = evaluations / second over the timed steps.
 
