@@ -577,7 +577,7 @@ KStat gmres(Ctx& ctx, const std::function<void(VPtr, VPtr)>& op, VPtr b, VPtr x,
   axpby(ctx, 1.0, b, -1.0, V[0], n);  // V0 = b - A x
   double beta = nrm2(ctx, V[0], n);
   MERA_CHECK(std::isfinite(beta), MERA_ENONFINITE, "non-finite residual in Krylov solve");
-  std::vector<double> H((m + 1) * m), Hr((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double> H((m + 1) * m), Hr((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hcol(m + 1);
   for (int restart = 0; restart <= max_restarts; ++restart) {
     st.res = beta / bnorm;
     if (beta <= tol * bnorm) {
@@ -593,12 +593,15 @@ KStat gmres(Ctx& ctx, const std::function<void(VPtr, VPtr)>& op, VPtr b, VPtr x,
     for (int j = 0; j < m; ++j) {
       op(V[j], V[j + 1]);
       st.apps++;
-      for (int pass = 0; pass < 2; ++pass)
+      // classical Gram-Schmidt, twice: each pass is one fused projection onto V_0..V_j and one fused update
+      for (int pass = 0; pass < 2; ++pass) {
+        multi_dot(ctx, V.data(), j + 1, V[j + 1], n, hcol.data());
         for (int i = 0; i <= j; ++i) {
-          double hij = dot(ctx, V[j + 1], V[i], n);
-          H[i * m + j] += hij;
-          axpby(ctx, -hij, V[i], 1.0, V[j + 1], n);
+          H[i * m + j] += hcol[i];
+          hcol[i] = -hcol[i];
         }
+        multi_axpby(ctx, V.data(), hcol.data(), j + 1, 1.0, V[j + 1], n);
+      }
       double hn = nrm2(ctx, V[j + 1], n);
       MERA_CHECK(std::isfinite(hn), MERA_ENONFINITE, "non-finite Krylov vector");
       H[(j + 1) * m + j] = hn;
@@ -627,14 +630,13 @@ KStat gmres(Ctx& ctx, const std::function<void(VPtr, VPtr)>& op, VPtr b, VPtr x,
       for (int l = i + 1; l < k; ++l) s -= Hr[i * m + l] * y[l];
       y[i] = s / Hr[i * m + i];
     }
-    for (int i = 0; i < k; ++i) axpby(ctx, y[i], V[i], 1.0, x, n);
+    multi_axpby(ctx, V.data(), y.data(), k, 1.0, x, n);
     // residual r = V_{0..k} (beta e1 - Hbar y)
     std::vector<double> c(k + 1, 0.0);
     c[0] = beta;
     for (int i = 0; i <= k; ++i)
       for (int l = 0; l < k; ++l) c[i] -= H[i * m + l] * y[l];
-    fill(ctx, R, n, 0.0);
-    for (int i = 0; i <= k; ++i) axpby(ctx, c[i], V[i], 1.0, R, n);
+    multi_axpby(ctx, V.data(), c.data(), k + 1, 0.0, R, n);
     std::swap(V[0], R);
     beta = nrm2(ctx, V[0], n);
     MERA_CHECK(std::isfinite(beta), MERA_ENONFINITE, "non-finite residual in Krylov solve");

@@ -16,6 +16,12 @@ struct VPtr {
 double dot(Ctx& ctx, VPtr x, VPtr y, int64_t n);               // sum x*y in FP64 (syncs)
 double nrm2(Ctx& ctx, VPtr x, int64_t n);
 void axpby(Ctx& ctx, double a, VPtr x, double b, VPtr y, int64_t n);  // y = a x + b y
+// out[j] = <w, v_j>, j < k (host array), FP64 accumulation, one pass over w per 17 vectors (syncs). All vectors of
+// one precision.
+void multi_dot(Ctx& ctx, const VPtr* v, int k, VPtr w, int64_t n, double* out);
+// y <- b y + sum_j c_j v_j (c: host array of k), accumulated in FP64, one pass per 17 vectors (b == 0: y is not
+// read). All vectors of one precision; y must not be one of the v_j.
+void multi_axpby(Ctx& ctx, const VPtr* v, const double* c, int k, double b, VPtr y, int64_t n);
 void scal(Ctx& ctx, double a, VPtr x, int64_t n);
 void copy(Ctx& ctx, VPtr dst, VPtr src, int64_t n);            // with conversion
 void fill(Ctx& ctx, VPtr x, int64_t n, double v);

@@ -47,6 +47,74 @@ __global__ void axpby_kernel(double a, const TX* __restrict__ x, double b, TY* _
   }
 }
 
+// Several vectors of one precision per launch, passed by value with their coefficients.
+constexpr int kMulti = 17;
+template <typename T>
+struct VecList {
+  const T* v[kMulti];
+  double c[kMulti];
+};
+
+// Block partials of the k dot products <w, v_j>: one pass over w, each element of w read once.
+// out[j * gridDim.x + blockIdx.x] = this block's share of sum_i w[i] v_j[i].
+template <typename T>
+__global__ void multi_dot_kernel(VecList<T> L, int k, const T* __restrict__ w, int64_t n, double* __restrict__ out) {
+  double s[kMulti];
+#pragma unroll
+  for (int j = 0; j < kMulti; ++j) s[j] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double wi = (double)w[i];
+#pragma unroll
+    for (int j = 0; j < kMulti; ++j)
+      if (j < k) s[j] += wi * (double)L.v[j][i];
+  }
+  __shared__ double part[kMulti][TPB / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < kMulti; ++j)
+    if (j < k) {
+      const double t = wave_sum(s[j]);
+      if (lane == 0) part[j][wave] = t;
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < k) {
+    double t = 0.0;
+    for (int q = 0; q < TPB / 64; ++q) t += part[threadIdx.x][q];
+    out[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// sums[j] = sum of the `blocks` partials of vector j, in a fixed order (one wave per vector).
+__global__ void sum_partials_kernel(const double* __restrict__ part, int blocks, double* __restrict__ sums) {
+  const int j = blockIdx.x;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < blocks; b += 64) t += part[(int64_t)j * blocks + b];
+  t = wave_sum(t);
+  if (threadIdx.x == 0) sums[j] = t;
+}
+
+// y <- b y + sum_j c_j v_j, accumulated in FP64 and rounded once (b == 0: y is not read).
+template <typename T>
+__global__ void multi_axpby_kernel(VecList<T> L, int k, double b, T* __restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double t = (b != 0.0) ? b * (double)y[i] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kMulti; ++j)
+      if (j < k) t += L.c[j] * (double)L.v[j][i];
+    y[i] = (T)t;
+  }
+}
+
+template <typename T>
+VecList<T> vec_list(const VPtr* v, const double* c, int k) {
+  VecList<T> L{};
+  for (int j = 0; j < k; ++j) {
+    L.v[j] = static_cast<const T*>(v[j].p);
+    L.c[j] = c ? c[j] : 0.0;
+  }
+  return L;
+}
+
 template <typename T>
 __global__ void scal_kernel(double a, T* x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -300,6 +368,53 @@ double dot(Ctx& ctx, VPtr x, VPtr y, int64_t n) {
 }
 
 double nrm2(Ctx& ctx, VPtr x, int64_t n) { return std::sqrt(dot(ctx, x, x, n)); }
+
+void multi_dot(Ctx& ctx, const VPtr* v, int k, VPtr w, int64_t n, double* out) {
+  for (int j = 0; j < k; ++j)
+    MERA_CHECK(v[j].dbl() == w.dbl(), MERA_EINVAL, "multi_dot: vectors of different precisions");
+  const int blocks = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + TPB - 1) / TPB));
+  ctx.red.ensure(((size_t)kMulti * blocks + kMulti) * sizeof(double));
+  double* part = ctx.red.as<double>();
+  double* sums = part + (size_t)kMulti * blocks;
+  for (int j0 = 0; j0 < k; j0 += kMulti) {
+    const int kk = std::min(kMulti, k - j0);
+    if (w.dbl())
+      hipLaunchKernelGGL(multi_dot_kernel<double>, dim3(blocks), dim3(TPB), 0, ctx.stream,
+                         vec_list<double>(v + j0, nullptr, kk), kk, (const double*)w.p, n, part);
+    else
+      hipLaunchKernelGGL(multi_dot_kernel<float>, dim3(blocks), dim3(TPB), 0, ctx.stream,
+                         vec_list<float>(v + j0, nullptr, kk), kk, (const float*)w.p, n, part);
+    MERA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(kk), dim3(64), 0, ctx.stream, (const double*)part, blocks, sums);
+    MERA_HIP(hipGetLastError());
+    MERA_HIP(hipMemcpyAsync(out + j0, sums, kk * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+    ctx.sync();
+  }
+}
+
+void multi_axpby(Ctx& ctx, const VPtr* v, const double* c, int k, double b, VPtr y, int64_t n) {
+  for (int j = 0; j < k; ++j) {
+    MERA_CHECK(v[j].dbl() == y.dbl(), MERA_EINVAL, "multi_axpby: vectors of different precisions");
+    MERA_CHECK(v[j].p != y.p, MERA_EINVAL, "multi_axpby: output aliases an input");
+  }
+  if (k == 0) {
+    if (b == 0.0) fill(ctx, y, n, 0.0);
+    else if (b != 1.0) scal(ctx, b, y, n);
+    return;
+  }
+  const int g = grid_for(n);
+  for (int j0 = 0; j0 < k; j0 += kMulti) {
+    const int kk = std::min(kMulti, k - j0);
+    const double bb = j0 == 0 ? b : 1.0;
+    if (y.dbl())
+      hipLaunchKernelGGL(multi_axpby_kernel<double>, dim3(g), dim3(TPB), 0, ctx.stream,
+                         vec_list<double>(v + j0, c + j0, kk), kk, bb, (double*)y.p, n);
+    else
+      hipLaunchKernelGGL(multi_axpby_kernel<float>, dim3(g), dim3(TPB), 0, ctx.stream,
+                         vec_list<float>(v + j0, c + j0, kk), kk, bb, (float*)y.p, n);
+    MERA_HIP(hipGetLastError());
+  }
+}
 
 void axpby(Ctx& ctx, double a, VPtr x, double b, VPtr y, int64_t n) {
   int g = grid_for(n);
