@@ -325,16 +325,26 @@ void ev_update_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& 
   }
 }
 
+// The density matrices of consecutive iterates differ little, so the previous eigenbasis Q nearly diagonalises the
+// new rho: the decomposition starts from Q^T rho Q and needs a few Jacobi sweeps instead of a full run. One in
+// kMetricColdEvery decompositions starts from scratch, which keeps the accumulated rounding in Q's orthogonality
+// bounded.
+constexpr int kMetricColdEvery = 32;
+
 void Metric::compute(Ctx& ctx, const std::vector<MatView>& rho) {
   const size_t k = rho.size();
+  const std::vector<int> prev_p = p;
   V.resize(k);
   lam.resize(k);
   f.resize(k);
   g.resize(k);
+  warm.resize(k, 0);
   p.assign(k, 0);
   for (size_t i = 0; i < k; ++i) {
     const int q = rho[i].p;
     MERA_CHECK(rho[i].n == q, MERA_EINVAL, "metric must be square");
+    const bool reuse = i < prev_p.size() && prev_p[i] == q && warm[i] > 0 && warm[i] < kMetricColdEvery &&
+                       V[i].bytes >= (size_t)q * q * 8;
     p[i] = q;
     V[i].ensure((size_t)q * q * 8);
     lam[i].ensure((size_t)q * 8);
@@ -343,7 +353,20 @@ void Metric::compute(Ctx& ctx, const std::vector<MatView>& rho) {
     double* a = tmp(ctx, "met.a", (int64_t)q * q);
     copy(ctx, VPtr{a, Prec::F64}, d64(rho[i]), (int64_t)q * q);
     symmetrize(ctx, VPtr{a, Prec::F64}, q);
-    jacobi_eigh(ctx, a, lam[i].as<double>(), V[i].as<double>(), q);
+    double* Q = V[i].as<double>();
+    if (reuse) {
+      const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', q}, {'q', q}, {'r', q}};
+      double* t = tmp(ctx, "met.t", (int64_t)q * q);
+      double* b = tmp(ctx, "met.b", (int64_t)q * q);
+      mm(ctx, "T[pq] = A[pr] * Q[rq]", dpp, {{"T", t}, {"A", a}, {"Q", Q}});
+      mm(ctx, "B[pq] = Q[rp] * T[rq]", dpp, {{"B", b}, {"Q", Q}, {"T", t}});
+      symmetrize(ctx, VPtr{b, Prec::F64}, q);
+      jacobi_eigh(ctx, b, lam[i].as<double>(), Q, q, 1e-15, 30, true);
+      warm[i]++;
+    } else {
+      jacobi_eigh(ctx, a, lam[i].as<double>(), Q, q);
+      warm[i] = 1;
+    }
   }
 }
 

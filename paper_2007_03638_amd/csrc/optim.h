@@ -69,6 +69,7 @@ void ev_update_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& 
 struct Metric {
   std::vector<DevBuf> V, lam, f, g;
   std::vector<int> p;
+  std::vector<int> warm;  // per factor: decompositions since the last one from scratch (0: no basis kept)
   void compute(Ctx& ctx, const std::vector<MatView>& rho);
   bool empty() const { return p.empty(); }
 };

@@ -495,7 +495,7 @@ double trace(Ctx& ctx, VPtr x, int64_t dim) {
   return finish_partials(ctx, blocks);
 }
 
-int jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol, int max_sweeps) {
+int jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol, int max_sweeps, bool v_init) {
   if (dim <= 0) return 0;
   static thread_local std::unordered_map<std::string, std::unique_ptr<JacobiSchedule>> scheds;
   const std::string key = std::to_string(ctx.device) + ":" + std::to_string(dim);
@@ -530,7 +530,7 @@ int jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol
   JacobiSchedule& s = *it->second;
   double* b = static_cast<double*>(ctx.buf("jacobi.pingpong", (size_t)dim * dim * sizeof(double)));
   const int g = grid_for((int64_t)dim * dim);
-  hipLaunchKernelGGL(eye_kernel, dim3(g), dim3(TPB), 0, ctx.stream, v, dim);
+  if (!v_init) hipLaunchKernelGGL(eye_kernel, dim3(g), dim3(TPB), 0, ctx.stream, v, dim);
   const double fro = std::sqrt(dot(ctx, VPtr{a, Prec::F64}, VPtr{a, Prec::F64}, (int64_t)dim * dim));
   ctx.red.ensure(RED_BLOCKS * sizeof(double));
   const int64_t work = std::max<int64_t>((int64_t)s.npairs * s.npairs, (int64_t)dim * s.npairs);
