@@ -138,10 +138,16 @@ template <typename T>
 __global__ void symmetrize_kernel(T* x, int64_t dim) {
   __shared__ T a[32][33], b[32][33];
   const int64_t ntile = (dim + 31) / 32;
-  // map blockIdx.x to (I, J) with I <= J
-  int64_t t = blockIdx.x, I = 0;
-  while (t >= ntile - I) { t -= ntile - I; ++I; }
-  const int64_t J = I + t;
+  // map blockIdx.x to (I, J) with I <= J: the rows above I hold S(I) = I ntile - I (I - 1) / 2 pairs; I from the
+  // root of that quadratic, corrected for rounding
+  const int64_t t = blockIdx.x;
+  auto S = [ntile](int64_t r) { return r * ntile - r * (r - 1) / 2; };
+  const double nn = 2.0 * (double)ntile + 1.0;
+  int64_t I = (int64_t)((nn - sqrt(nn * nn - 8.0 * (double)t)) * 0.5);
+  if (I < 0) I = 0;
+  while (I + 1 <= ntile && S(I + 1) <= t) ++I;
+  while (I > 0 && S(I) > t) --I;
+  const int64_t J = I + (t - S(I));
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
   for (int r = ty; r < 32; r += 8) {
     int64_t i = I * 32 + r, j = J * 32 + tx;

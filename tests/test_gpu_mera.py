@@ -102,3 +102,29 @@ def test_sliced_programs_match(ctx, T, chi, d, limit):
         assert rel(to_np(got["Dw"][t]), ref["grads"][t][1]) < 1e-10
     assert rel(asc, om.ascend(h, params[T][0], params[T][1], a, b)) < 1e-13
     assert rel(des, om.descend(rho, params[T][0], params[T][1], a, b)) < 1e-13
+
+
+@pytest.mark.parametrize("T,chi,d,seed", [(2, 4, 4, 0), (2, 6, 3, 4)])
+def test_krylov_dimensions(ctx, T, chi, d, seed):
+    """The fixed point and h~ solved with restarted GMRES of dimension 1, 4 and 24 (the last beyond one fused
+    Gram-Schmidt launch of 17 vectors) all give the oracle's energy and gradient. A solve that dimension 24 finishes
+    without a restart takes no more superoperator applications than with dimension 4: its iterate minimises the
+    residual over a Krylov space that contains every restarted iterate of as many steps."""
+    dims = om.layer_dims(chi, T, d)
+    params = inputs.mera_init(seed, dims)
+    h3 = model.tfim_h3(1.0) if d == 4 else inputs.symmetric_operator(seed + 1, d ** 3)
+    ref = om.evaluate(params, h3, chi, T, d=d)
+    apps = {}
+    for m in (1, 4, 24):
+        got = ctx.energy_grad(T, chi, [p[0] for p in params], [p[1] for p in params], h3, prec="fp64", d=d,
+                              krylov={"dim": m})
+        apps[m] = (got["applications_rho"], got["applications_htilde"])
+        print(f"case T={T} chi={chi} d={d} dim={m}: apps {got['applications_rho']},{got['applications_htilde']}",
+              flush=True)
+        assert abs(got["energy"] - ref["energy"]) <= 1e-12 * abs(ref["energy"])
+        for t in range(T + 1):
+            assert rel(to_np(got["Du"][t]), ref["grads"][t][0]) < 1e-10
+            assert rel(to_np(got["Dw"][t]), ref["grads"][t][1]) < 1e-10
+    for s in range(2):
+        if apps[24][s] <= 25:  # one cycle: the initial residual plus at most 24 Arnoldi steps
+            assert apps[24][s] <= apps[4][s]
