@@ -33,10 +33,11 @@ double trace(Ctx& ctx, VPtr x, int64_t dim);                   // syncs
 
 // Symmetric eigendecomposition of a dim x dim FP64 matrix (row-major, device) by cyclic two-sided Jacobi
 // rotations in tournament order: A = V diag(lam) V^T, eigenvectors in the columns of V. `a` is overwritten.
-// Returns the number of sweeps. v_init: v holds an orthogonal basis Q on entry and a = Q^T A Q; the rotations are
-// then accumulated onto Q, so that v returns the eigenvectors of A (few sweeps when Q nearly diagonalises A).
-int jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol = 1e-15, int max_sweeps = 30,
-                bool v_init = false);
+// v_init: v holds an orthogonal basis Q on entry and a = Q^T A Q; the rotations are then accumulated onto Q, so
+// that v returns the eigenvectors of A (few sweeps when Q nearly diagonalises A). Matrices up to 64 x 64 run in one
+// launch (one workgroup, A and V in LDS); larger ones launch one kernel per round.
+void jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol = 1e-15, int max_sweeps = 30,
+                 bool v_init = false);
 
 // Element-wise helpers for the preconditioner (all FP64, device):
 //   M_ij <- M_ij * 2 / (f_i + f_j)

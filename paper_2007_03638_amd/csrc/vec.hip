@@ -254,6 +254,115 @@ __global__ void jacobi_round_kernel(const double* __restrict__ ain, double* __re
   }
 }
 
+// Matrices up to this size are decomposed by one workgroup, with A and V in LDS and every sweep in one launch.
+constexpr int kJacobiSmall = 64;
+
+// The same rounds and stopping rule as the multi-launch path, for dim <= kJacobiSmall: per round the rotations of
+// all pairs are taken from A, the 2x2 blocks of J^T A J are formed in registers (at most 4 blocks per thread) and
+// written back after a barrier, and V <- V J in place (each (row, pair) belongs to one thread).
+__global__ void __launch_bounds__(256) jacobi_small_kernel(double* a, double* lam, double* v,
+                                                           const int* __restrict__ pairs, int npairs, int rounds,
+                                                           int dim, double tol, int max_sweeps, int v_init) {
+  constexpr int LD = kJacobiSmall + 1;
+  constexpr int NB = (kJacobiSmall / 2) * (kJacobiSmall / 2) / 256;
+  __shared__ double As[kJacobiSmall * LD], Vs[kJacobiSmall * LD];
+  __shared__ double cs[kJacobiSmall / 2], sn[kJacobiSmall / 2];
+  __shared__ double part[4];
+  const int tid = threadIdx.x;
+  const int n2 = dim * dim;
+  for (int t = tid; t < n2; t += 256) {
+    const int r = t / dim, c = t - r * dim;
+    As[r * LD + c] = a[t];
+    Vs[r * LD + c] = v_init ? v[t] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  auto block_sum = [&](double x) {
+    x = wave_sum(x);
+    if ((tid & 63) == 0) part[tid >> 6] = x;
+    __syncthreads();
+    const double tot = part[0] + part[1] + part[2] + part[3];
+    __syncthreads();
+    return tot;
+  };
+  double f2 = 0.0;
+  for (int t = tid; t < n2; t += 256) {
+    const double x = As[(t / dim) * LD + t % dim];
+    f2 += x * x;
+  }
+  const double fro = sqrt(block_sum(f2));
+  double prev_off = INFINITY;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    double o2 = 0.0;
+    for (int t = tid; t < n2; t += 256) {
+      const int r = t / dim, c = t - r * dim;
+      if (r != c) o2 += As[r * LD + c] * As[r * LD + c];
+    }
+    const double off = sqrt(block_sum(o2));
+    if (!(off > tol * fro) || dim == 1) break;
+    if (sweep >= 4 && off > 0.25 * prev_off && off < 1e-12 * fro) break;
+    prev_off = off;
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int* pr = pairs + (size_t)rd * npairs * 2;
+      if (tid < npairs) {
+        double c, s;
+        rot_of(As, LD, pr[2 * tid], pr[2 * tid + 1], c, s);
+        cs[tid] = c;
+        sn[tid] = s;
+      }
+      __syncthreads();
+      double nv[NB][4];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int id = tid + q * 256;
+        if (id < npairs * npairs) {
+          const int P = id / npairs, Q = id - P * npairs;
+          const int i = pr[2 * P], j = pr[2 * P + 1], k = pr[2 * Q], l = pr[2 * Q + 1];
+          const double cp = cs[P], sp = sn[P], cq = cs[Q], sq = sn[Q];
+          const double aik = (i >= 0 && k >= 0) ? As[i * LD + k] : 0.0;
+          const double ail = (i >= 0 && l >= 0) ? As[i * LD + l] : 0.0;
+          const double ajk = (j >= 0 && k >= 0) ? As[j * LD + k] : 0.0;
+          const double ajl = (j >= 0 && l >= 0) ? As[j * LD + l] : 0.0;
+          const double t0k = cp * aik - sp * ajk, t0l = cp * ail - sp * ajl;
+          const double t1k = sp * aik + cp * ajk, t1l = sp * ail + cp * ajl;
+          nv[q][0] = cq * t0k - sq * t0l;
+          nv[q][1] = (P == Q) ? 0.0 : sq * t0k + cq * t0l;
+          nv[q][2] = (P == Q) ? 0.0 : cq * t1k - sq * t1l;
+          nv[q][3] = sq * t1k + cq * t1l;
+        }
+      }
+      for (int id = tid; id < dim * npairs; id += 256) {
+        const int r = id / npairs, P = id - r * npairs;
+        const int i = pr[2 * P], j = pr[2 * P + 1];
+        if (i >= 0 && j >= 0) {
+          const double vi = Vs[r * LD + i], vj = Vs[r * LD + j];
+          Vs[r * LD + i] = cs[P] * vi - sn[P] * vj;
+          Vs[r * LD + j] = sn[P] * vi + cs[P] * vj;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int id = tid + q * 256;
+        if (id < npairs * npairs) {
+          const int P = id / npairs, Q = id - P * npairs;
+          const int i = pr[2 * P], j = pr[2 * P + 1], k = pr[2 * Q], l = pr[2 * Q + 1];
+          if (i >= 0 && k >= 0) As[i * LD + k] = nv[q][0];
+          if (i >= 0 && l >= 0) As[i * LD + l] = nv[q][1];
+          if (j >= 0 && k >= 0) As[j * LD + k] = nv[q][2];
+          if (j >= 0 && l >= 0) As[j * LD + l] = nv[q][3];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = tid; t < dim; t += 256) lam[t] = As[t * LD + t];
+  for (int t = tid; t < n2; t += 256) {
+    const int r = t / dim, c = t - r * dim;
+    a[t] = As[r * LD + c];
+    v[t] = Vs[r * LD + c];
+  }
+}
+
 __global__ void offdiag_kernel(const double* a, int dim, double* out) {
   double s = 0.0;
   const int64_t n = (int64_t)dim * dim;
@@ -501,8 +610,8 @@ double trace(Ctx& ctx, VPtr x, int64_t dim) {
   return finish_partials(ctx, blocks);
 }
 
-int jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol, int max_sweeps, bool v_init) {
-  if (dim <= 0) return 0;
+void jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol, int max_sweeps, bool v_init) {
+  if (dim <= 0) return;
   static thread_local std::unordered_map<std::string, std::unique_ptr<JacobiSchedule>> scheds;
   const std::string key = std::to_string(ctx.device) + ":" + std::to_string(dim);
   auto it = scheds.find(key);
@@ -534,6 +643,12 @@ int jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol
     it = scheds.emplace(key, std::move(s)).first;
   }
   JacobiSchedule& s = *it->second;
+  if (dim <= kJacobiSmall) {
+    hipLaunchKernelGGL(jacobi_small_kernel, dim3(1), dim3(256), 0, ctx.stream, a, lam, v, s.pairs.as<int>(),
+                       s.npairs, s.rounds, dim, tol, max_sweeps, v_init ? 1 : 0);
+    MERA_HIP(hipGetLastError());
+    return;
+  }
   double* b = static_cast<double*>(ctx.buf("jacobi.pingpong", (size_t)dim * dim * sizeof(double)));
   const int g = grid_for((int64_t)dim * dim);
   if (!v_init) hipLaunchKernelGGL(eye_kernel, dim3(g), dim3(TPB), 0, ctx.stream, v, dim);
@@ -562,7 +677,6 @@ int jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol
   hipLaunchKernelGGL(diag_kernel, dim3((dim + TPB - 1) / TPB), dim3(TPB), 0, ctx.stream, cur, dim, lam);
   if (cur != a) MERA_HIP(hipMemcpyAsync(a, cur, (size_t)dim * dim * 8, hipMemcpyDeviceToDevice, ctx.stream));
   MERA_HIP(hipGetLastError());
-  return sweeps;
 }
 
 void rho_marginals(Ctx& ctx, VPtr rho, int b, double* rho1, double* rho2) {
