@@ -168,7 +168,8 @@ mera_status mera_descend(mera_ctx* ctx, const mera_shape* shape, int layer, cons
                          mera_prec prec, const double* rho_in, double* rho_out);
 
 /* ---- Stiefel manifold (Sec. 2) ------------------------------------------------------------------------ */
-/* All take `count` matrices (a point of the product manifold, Sec. 2.4) and act factor by factor. */
+/* All take `count` matrices (a point of the product manifold, Sec. 2.4) and act factor by factor. count = 0 does
+ * nothing and returns MERA_OK (the arrays may then be NULL). */
 
 /* G = D - W (W^T D + D^T W) / 2 (eq. stiefel_gradient, real case). G may alias D. */
 mera_status stiefel_project(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, mera_mat* G);

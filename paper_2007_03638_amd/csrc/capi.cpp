@@ -51,7 +51,7 @@ mera_status guarded(mera_ctx* ctx, F&& f) {
 }
 
 void check_mats(const mera_mat* m, int count, const char* what) {
-  MERA_CHECK(m != nullptr, MERA_EINVAL, std::string(what) + ": null matrix array");
+  MERA_CHECK(count == 0 || m != nullptr, MERA_EINVAL, std::string(what) + ": null matrix array");
   for (int i = 0; i < count; ++i)
     MERA_CHECK(m[i].data != nullptr && m[i].n > 0 && m[i].p > 0, MERA_EINVAL,
                std::string(what) + ": bad matrix " + std::to_string(i));

@@ -153,3 +153,13 @@ def test_ev_update_rank_deficient(ctx):
     lam, V = np.linalg.eigh(Y0.T @ Y0)
     absY = (V * np.sqrt(np.clip(lam, 0.0, None))) @ V.T
     assert np.max(np.abs(S - absY)) < 1e-6 * np.linalg.norm(Y0, 2)
+
+
+def test_empty_factor_lists(ctx):
+    """count = 0: the manifold calls do nothing and succeed, and the context keeps working."""
+    assert ctx.stiefel_project([], []) == []
+    assert ctx.stiefel_retract([], [], 0.5) == ([], [])
+    assert ctx.stiefel_transport([], []) == []
+    W, D = _case(9)
+    G = ctx.stiefel_project(W[:1], D[:1])
+    assert rel(to_np(G[0]), mf.project(W[0], D[0])) < 1e-13
