@@ -128,3 +128,27 @@ def test_krylov_dimensions(ctx, T, chi, d, seed):
     for s in range(2):
         if apps[24][s] <= 25:  # one cycle: the initial residual plus at most 24 Arnoldi steps
             assert apps[24][s] <= apps[4][s]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_degenerate_hamiltonians(ctx, prec, tol):
+    """h = 0 gives energy 0 and a zero gradient (the h~ solve then has a zero right-hand side); h = c 1 gives
+    energy c per blocked site, since every layer map sends the identity to the identity, and no Riemannian
+    gradient, since the energy is then constant on the manifold."""
+    T, chi, d = 2, 4, 4
+    dims = om.layer_dims(chi, T, d)
+    params = inputs.mera_init(6, dims)
+    u, w = [p[0] for p in params], [p[1] for p in params]
+    zero = ctx.energy_grad(T, chi, u, w, np.zeros((d ** 3, d ** 3)), prec=prec)
+    assert zero["energy"] == 0.0
+    for t in range(T + 1):
+        assert not np.any(to_np(zero["Du"][t])) and not np.any(to_np(zero["Dw"][t]))
+    c = 1.7
+    const = ctx.energy_grad(T, chi, u, w, c * np.eye(d ** 3), prec=prec)
+    print(f"{prec}: energy of c 1 minus c: {const['energy'] - c:.2e}", flush=True)
+    assert abs(const["energy"] - c) <= tol * c
+    for t in range(T + 1):
+        for v, key in ((u[t], "Du"), (w[t], "Dw")):
+            D = to_np(const[key][t])
+            G = D - v @ (v.T @ D + D.T @ v) / 2
+            assert np.max(np.abs(G)) <= tol * c * max(1.0, np.max(np.abs(D))), (t, key)
