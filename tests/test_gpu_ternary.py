@@ -100,3 +100,25 @@ def test_ternary_optimiser_trajectory(ctx):
         assert abs(a["energy"] - b["energy"]) <= 1e-10 * abs(b["energy"])
     assert abs(got["energy"] - f_ref) <= 1e-10 * abs(f_ref)
     assert got["energy"] > model.tfim_exact_energy_per_spin(1.0)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_degenerate_hamiltonians(ctx, prec, tol):
+    """Ternary geometry: h = 0 gives energy 0 and a zero gradient; h = c 1 gives energy c and no Riemannian
+    gradient (every layer map sends the identity to the identity)."""
+    T, chi = 1, 6
+    dims = tm.layer_dims(chi, T)
+    params = _params(8, dims)
+    u, w = [p[0] for p in params], [p[1] for p in params]
+    zero = ctx.energy_grad(T, chi, u, w, np.zeros((4, 4)), prec=prec, d=2, geometry="ternary")
+    assert zero["energy"] == 0.0
+    for t in range(T + 1):
+        assert not np.any(to_np(zero["Du"][t])) and not np.any(to_np(zero["Dw"][t]))
+    c = 0.6
+    const = ctx.energy_grad(T, chi, u, w, c * np.eye(4), prec=prec, d=2, geometry="ternary")
+    assert abs(const["energy"] - c) <= tol * c
+    for t in range(T + 1):
+        for v, key in ((u[t], "Du"), (w[t], "Dw")):
+            D = to_np(const[key][t])
+            G = D - v @ (v.T @ D + D.T @ v) / 2
+            assert np.max(np.abs(G)) <= tol * c * max(1.0, np.max(np.abs(D))), (t, key)
