@@ -137,3 +137,20 @@ def test_fp64_ev_sweeps_match_oracle(ctx):
     assert got["evaluations"] == info["evals"]
     for w in got["final"]:
         assert np.max(np.abs(w.T @ w - np.eye(w.shape[1]))) < 1e-13
+
+
+def test_zero_iterations_and_immediate_convergence(ctx):
+    """max_iter = 0 evaluates the start once and stops with the cap status, tensors untouched; a gradient
+    tolerance above the starting gradient norm stops at once as converged."""
+    chi, T = 4, 2
+    W0 = _init(3, chi, T)
+    h3 = model.tfim_h3(1.0)
+    e_ref = om.energy_only([(W0[2 * i], W0[2 * i + 1]) for i in range(T + 1)], h3, chi, T)
+    got = ctx.run_optimize(T, chi, h3, W0, prec="fp64", m=8, max_iter=0, grad_tol=0.0, want_final=True)
+    assert (got["iterations"], got["evaluations"], got["status"]) == (0, 1, 1)
+    assert abs(got["energy"] - e_ref) <= 1e-12 * abs(e_ref)
+    for a, b in zip(got["final"], W0):
+        assert np.array_equal(a, b)
+    done = ctx.run_optimize(T, chi, h3, W0, prec="fp64", m=8, max_iter=50, grad_tol=1e9)
+    assert (done["iterations"], done["evaluations"], done["status"]) == (0, 1, 0)
+    assert abs(done["energy"] - e_ref) <= 1e-12 * abs(e_ref)

@@ -163,3 +163,15 @@ def test_empty_factor_lists(ctx):
     W, D = _case(9)
     G = ctx.stiefel_project(W[:1], D[:1])
     assert rel(to_np(G[0]), mf.project(W[0], D[0])) < 1e-13
+
+
+def test_zero_tangent(ctx):
+    """A zero tangent vector retracts to the point itself with a zero curve tangent, and transports to zero."""
+    W, _ = _case(10)
+    Z = [np.zeros_like(w) for w in W]
+    Wo, Xo = ctx.stiefel_retract(W, Z, 0.8)
+    for w, wo, xo in zip(W, Wo, Xo):
+        assert np.max(np.abs(to_np(wo) - w)) < 1e-14
+        assert not np.any(to_np(xo))
+    for t in ctx.stiefel_transport(W, Z):
+        assert not np.any(to_np(t))
