@@ -68,3 +68,26 @@ def test_invalid_arguments_are_rejected(lib):
     a = (ctypes.c_int * 4)()
     assert lib.mera_layer_dims(ctypes.byref(sh), a, a) == -1
     assert lib.mera_job_footprint(ctypes.byref(_lib.MeraShape(3, 4, 24)), 1) > 20 * 2 ** 30
+
+
+def test_two_site_builders_and_ternary_dims_match_oracle(lib):
+    """Host-only calls of the ternary geometry: two-site model terms and layer dimensions."""
+    from oracle import ternary
+    from paper_2007_03638_amd import api
+    for h in (1.0, 0.7, 1.3):
+        assert np.max(np.abs(api.h2_tfim(h) - ternary.tfim_h2(h))) < 1e-15
+    for dl in (-0.5, 0.3, 1.0):
+        assert np.max(np.abs(api.h2_xxz(dl) - ternary.xxz_h2(dl))) < 1e-15
+    for T, chi in [(1, 4), (1, 6), (2, 9), (2, 12), (2, 32)]:
+        assert api.layer_dims(T, chi, d=2, geometry="ternary") == ternary.layer_dims(chi, T)
+
+
+def test_job_footprint_orders(lib):
+    """The admission estimate grows with chi and with the element size, and the FP32 estimate at chi = 24 holds
+    at least the two 7-leg FP32 intermediates of a derivative program (a^6 b elements each)."""
+    from paper_2007_03638_amd import api
+    f32 = [api.job_footprint(3, chi, "fp32") for chi in (8, 12, 16, 20, 24)]
+    assert f32 == sorted(f32) and len(set(f32)) == len(f32)
+    for chi in (8, 16, 24):
+        assert api.job_footprint(3, chi, "fp64") > api.job_footprint(3, chi, "fp32")
+    assert api.job_footprint(3, 24, "fp32") >= 2 * 24 ** 7 * 4
