@@ -152,3 +152,17 @@ def test_degenerate_hamiltonians(ctx, prec, tol):
             D = to_np(const[key][t])
             G = D - v @ (v.T @ D + D.T @ v) / 2
             assert np.max(np.abs(G)) <= tol * c * max(1.0, np.max(np.abs(D))), (t, key)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_product_state_special_case(ctx, prec, tol):
+    """u = 1 and w|i> = |i>|0> on every layer drive each site to |0>: the fixed point is |000><000| and the TFIM
+    (h = 1, two spins per blocked site) energy is <000|h3|000> = -2 per blocked site."""
+    chi, T = 4, 1
+    u = np.eye(chi * chi)
+    w = np.zeros((chi, chi, chi))
+    for i in range(chi):
+        w[i, 0, i] = 1.0
+    w = w.reshape(chi * chi, chi)
+    got = ctx.energy_grad(T, chi, [u, u], [w, w], model.tfim_h3(1.0), prec=prec)
+    assert abs(got["energy"] + 2.0) <= 2.0 * tol
