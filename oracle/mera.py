@@ -230,6 +230,78 @@ def layer_environments(h, rho, u, w, a, b):
     return Du.reshape(a * a, a * a), Dw.reshape(a * a, b)
 
 
+def _split3(lab):
+    """Labels of a 3-site operator 'abcABC' as three one-site factors ['aA', 'bB', 'cC']."""
+    return [lab[0] + lab[3], lab[1] + lab[4], lab[2] + lab[5]]
+
+
+def layer_environments_product(hterms, rterms, u, w, a, b):
+    """`layer_environments` for operators given as sums of products of one-site matrices.
+
+    h = sum_i A_i (x) B_i (x) C_i (each a x a) and rho = sum_j P_j (x) Q_j (x) R_j (each b x b), with
+    h[abc, ABC] = A[a, A] B[b, B] C[c, C]. The networks and occurrences are those of `layer_environments` (sec. 4,
+    eq. mera_derivative: D_v is the sum over the occurrences of v of the network with v removed, times 1/2 from the
+    position average), with each operator entered as its three factors; by linearity the result is summed over all
+    pairs of terms. Each network is one library einsum call with its greedy path; without a 6-leg operator in the
+    network that path stays near a^6 per occurrence, so full gradients of dense u, w are available at the bond
+    dimensions of the benchmark.
+    """
+    ops_uw = _operands(u, w, a, b)
+    Du = np.zeros((a, a, a, a))
+    Dw = np.zeros((a, a, b))
+    for net in (_NET_L, _NET_R):
+        hl = _split3(net[0])
+        rl = _split3(_TOP)
+        body = net[1:]
+        for hf in hterms:
+            for rf in rterms:
+                labels = hl + body + rl
+                ops = list(hf) + ops_uw + list(rf)
+                for i, kind in enumerate(_KINDS[1:]):
+                    k = 3 + i
+                    others = [labels[j] for j in range(len(labels)) if j != k]
+                    spec = ','.join(others) + '->' + labels[k]
+                    env = np.einsum(spec, *[ops[j] for j in range(len(ops)) if j != k], optimize='greedy')
+                    if kind == 'u':
+                        Du += 0.5 * env
+                    else:
+                        Dw += 0.5 * env
+    return Du.reshape(a * a, a * a), Dw.reshape(a * a, b)
+
+
+def ascend_product(hterms, u, w, a, b):
+    """Dense A(h) = (A_L(h) + A_R(h))/2 for h = sum_i A_i (x) B_i (x) C_i (one-site factors, a x a).
+
+    The networks of `ascend_one` with h entered as its three factors, each diagram one library einsum call with
+    its greedy path (about a^6 b^2 multiply-adds per term, the output being b^6), so that whole outputs can be
+    compared at the benchmark's bond dimension.
+    """
+    ops_uw = _operands(u, w, a, b)
+    out = np.zeros((b,) * 6)
+    for net in (_NET_L, _NET_R):
+        spec = ','.join(_split3(net[0]) + net[1:]) + '->' + _TOP
+        for hf in hterms:
+            out += 0.5 * np.einsum(spec, *hf, *ops_uw, optimize='greedy')
+    return out.reshape(b ** 3, b ** 3)
+
+
+def descend_product(rterms, u, w, a, b):
+    """Dense D(rho) = (D_L(rho) + D_R(rho))/2 for rho = sum_j P_j (x) Q_j (x) R_j (one-site factors, b x b), the
+    networks of `descend_one` with rho entered as its factors (one einsum call per diagram and term)."""
+    ops_uw = _operands(u, w, a, b)
+    out = np.zeros((a,) * 6)
+    for net in (_NET_L, _NET_R):
+        spec = ','.join(net[1:] + _split3(_TOP)) + '->' + net[0]
+        for rf in rterms:
+            out += 0.5 * np.einsum(spec, *ops_uw, *rf, optimize='greedy')
+    return out.reshape(a ** 3, a ** 3)
+
+
+def product_operator(terms):
+    """Dense 3-site operator sum_i A_i (x) B_i (x) C_i (rows abc, columns ABC)."""
+    return sum(np.kron(np.kron(A, B), C) for A, B, C in terms)
+
+
 def evaluate(params, h3, chi, T, d=4, htilde_method='solve', rho_s=None):
     """Energy per blocked site and Euclidean gradient of an infinite binary MERA.
 

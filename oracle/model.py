@@ -80,10 +80,16 @@ def spin_ring_hamiltonian(nspins, pair, field):
 
 
 def tfim_exact_energy_per_spin(hx=1.0):
-    """Infinite-chain ground energy per spin of -sum X X - hx sum Z (free-fermion closed form); -4/pi at hx=1."""
-    val, _ = integrate.quad(lambda k: np.sqrt(1.0 + hx * hx - 2.0 * hx * np.cos(k)), -np.pi, np.pi,
-                            epsabs=1e-14, epsrel=1e-14, limit=200)
-    return -val / (2.0 * np.pi)
+    """Infinite-chain ground energy per spin of -sum X X - hx sum Z (free-fermion closed form); -4/pi at hx=1.
+
+    Sum of the negative single-particle energies, -(1/2pi) int_{-pi}^{pi} eps(k) dk with
+    eps(k) = sqrt(1 + hx^2 - 2 hx cos k) = sqrt((1 - hx)^2 + 4 hx sin^2(k/2)). The integrand is even; with
+    t = k/2 the integral is (2/pi) int_0^{pi/2} sqrt((1 - hx)^2 + 4 hx sin^2 t) dt, which has no kink in the
+    range (at hx = 1 the k-form has one at k = 0).
+    """
+    val, _ = integrate.quad(lambda t: np.sqrt((1.0 - hx) ** 2 + 4.0 * hx * np.sin(t) ** 2), 0.0, 0.5 * np.pi,
+                            epsabs=0.0, epsrel=1e-13, limit=200)
+    return -2.0 * val / np.pi
 
 
 def xxz_exact_energy_per_spin(delta):

@@ -229,3 +229,47 @@ def test_preconditioner_rdms_match_brute_force():
     mid = finite.apply_layer(psi4, u1, w1, d, chi, isometries_only=True)
     two_site = sum(finite.rdm(mid, [2 * j + 1, (2 * j + 2) % 8]) for j in range(4)) / 4
     assert np.max(np.abs(rho_u - two_site)) < 1e-14
+
+
+@pytest.mark.parametrize("a,b", [(3, 3), (4, 2), (2, 3)])
+def test_ascend_element_matches_full_map(a, b):
+    """`ascend_element` (the sampler used for outputs at large bond dimension) against the whole `ascend_one`
+    output, at every index."""
+    u, w = _random_layer(7, a, b)
+    h = inputs.symmetric_operator(8, a ** 3)
+    for side, net in (("L", mera._NET_L), ("R", mera._NET_R)):
+        full = mera.ascend_one(net, h, u, w, a, b).reshape((b,) * 6)
+        for idx in np.ndindex(*(b,) * 6):
+            assert abs(mera.ascend_element(side, h, u, w, a, b, idx) - full[idx]) < 1e-13, (side, idx)
+
+
+def _factor_terms(rng, n, nterms):
+    """Sum of products of one-site matrices, closed under transposition so that the operator is symmetric while
+    no factor is: A (x) B (x) C + A^T (x) B^T (x) C^T for each random (A, B, C)."""
+    out = []
+    for _ in range(nterms):
+        f = [rng.standard_normal((n, n)) for _ in range(3)]
+        out.append(tuple(f))
+        out.append(tuple(x.T for x in f))
+    return out
+
+
+@pytest.mark.parametrize("a,b", [(3, 3), (4, 2), (2, 4)])
+def test_product_operator_forms_match_dense(a, b):
+    """The product-operator forms of the layer maps and environments equal the dense ones on the same operators."""
+    rng = np.random.default_rng(11)
+    u, w = _random_layer(12, a, b)
+    ht = _factor_terms(rng, a, 1)
+    rt = _factor_terms(rng, b, 1)
+    h = mera.product_operator(ht)
+    rho = mera.product_operator(rt)
+    assert np.max(np.abs(h - h.T)) < 1e-12 and np.max(np.abs(rho - rho.T)) < 1e-12
+    A = mera.ascend_product(ht, u, w, a, b)
+    assert np.max(np.abs(A - mera.ascend(h, u, w, a, b))) < 1e-12 * max(1.0, np.max(np.abs(A)))
+    D = mera.descend_product(rt, u, w, a, b)
+    assert np.max(np.abs(D - mera.descend(rho, u, w, a, b))) < 1e-12 * max(1.0, np.max(np.abs(D)))
+    Du, Dw = mera.layer_environments_product(ht, rt, u, w, a, b)
+    Du2, Dw2 = mera.layer_environments(h, rho, u, w, a, b)
+    scale = max(np.max(np.abs(Du2)), np.max(np.abs(Dw2)))
+    assert np.max(np.abs(Du - Du2)) < 1e-12 * scale
+    assert np.max(np.abs(Dw - Dw2)) < 1e-12 * scale

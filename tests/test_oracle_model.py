@@ -64,3 +64,66 @@ def test_closed_forms_from_golden_fixture():
     for kind, par, val, *_ in rows:
         f = model.tfim_exact_energy_per_spin if kind == "tfim" else model.xxz_exact_energy_per_spin
         assert abs(f(float(par)) - float(val)) < 1e-9, (kind, par)
+
+
+@pytest.mark.parametrize("hx", [0.0, 0.3, 0.999, 1.0, 1.001, 1.5, 3.0])
+def test_tfim_energy_against_elliptic_closed_form(hx):
+    """-(1/2pi) int sqrt(1 + h^2 - 2h cos k) dk = -(2/pi)(1 + h) E(4h/(1 + h)^2), E the complete elliptic integral
+    of the second kind in the parameter convention (scipy.special.ellipe)."""
+    from scipy import special
+    ref = -(2.0 / np.pi) * (1.0 + hx) * special.ellipe(4.0 * hx / (1.0 + hx) ** 2)
+    assert abs(model.tfim_exact_energy_per_spin(hx) - ref) < 1e-13
+
+
+def _total(nspins, op):
+    return sum(model._on_spins(nspins, {i: op}) for i in range(nspins))
+
+
+@pytest.mark.parametrize("delta", [-0.5, 0.0, 0.4, 1.0, 1.3])
+def test_xxz_ring_conserves_total_z(delta):
+    """XX + YY + delta ZZ conserves the total Z magnetisation for every delta (U(1) symmetry); a wrong sign of the
+    YY part (XX - YY flips two spins the same way) breaks it."""
+    H = model.spin_ring_hamiltonian(6, *model.xxz_pair_and_field(delta))
+    Z = _total(6, model.PZ)
+    assert np.max(np.abs(H @ Z - Z @ H)) < 1e-12
+    assert np.max(np.abs(H - H.T)) == 0.0
+
+
+def test_xxz_isotropic_point_is_su2_invariant():
+    """At delta = 1 the term is sigma . sigma: it commutes with the total X (and, being real, total iY) as well."""
+    H = model.spin_ring_hamiltonian(6, *model.xxz_pair_and_field(1.0))
+    for op in (model.PX, model.PIY):
+        S = _total(6, op)
+        assert np.max(np.abs(H @ S - S @ H)) < 1e-12
+
+
+def test_xxz_four_spin_heisenberg_ring():
+    """4-spin ring at delta = 1: sum_i S_i.S_{i+1} = ((S1+S2+S3+S4)^2 - (S1+S3)^2 - (S2+S4)^2)/2 has ground energy
+    (0 - 2 - 2)/2 = -2 in spin-1/2 units, i.e. -8 in Pauli units (sigma = 2S); spectrum {-8, -4 (x3), 0 (x7), 4 (x5)}
+    from the total-spin multiplets (S_A, S_B, S)."""
+    H = model.spin_ring_hamiltonian(4, *model.xxz_pair_and_field(1.0))
+    ev = np.linalg.eigvalsh(H)
+    # multiplets: (1,1,0) -> -8; (1,1,1) -> -4 (3); (1,0,1),(0,1,1) -> 0 (6); (0,0,0) -> 0; (1,1,2) -> 4 (5)
+    ref = sorted([-8.0] + [-4.0] * 3 + [0.0] * 7 + [4.0] * 5)
+    assert np.max(np.abs(ev - np.array(ref))) < 1e-12
+
+
+def _xx_ring_free_fermion_energy(nspins):
+    """Ground energy of sum_i (X_i X_{i+1} + Y_i Y_{i+1}) on a periodic ring from free fermions (Lieb, Schultz and
+    Mattis 1961): the term is 2 (s+_i s-_{i+1} + h.c.), the Jordan-Wigner fermions hop with single-particle energies
+    4 cos k, k = 2 pi m / N (periodic) when the fermion number is odd and k = 2 pi (m + 1/2) / N (antiperiodic)
+    when it is even; the ground energy is the lowest filling over all fermion numbers."""
+    m = np.arange(nspins)
+    eps_p = np.sort(4.0 * np.cos(2.0 * np.pi * m / nspins))
+    eps_a = np.sort(4.0 * np.cos(2.0 * np.pi * (m + 0.5) / nspins))
+    best = np.inf
+    for nf in range(nspins + 1):
+        eps = eps_p if nf % 2 == 1 else eps_a
+        best = min(best, float(np.sum(eps[:nf])))
+    return best
+
+
+@pytest.mark.parametrize("nspins", [6, 8, 10])
+def test_xx_ring_against_free_fermions(nspins):
+    H = model.spin_ring_hamiltonian(nspins, *model.xxz_pair_and_field(0.0))
+    assert abs(np.linalg.eigvalsh(H)[0] - _xx_ring_free_fermion_energy(nspins)) < 1e-10
