@@ -39,7 +39,9 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=2,
                     help="optimiser iterations of the plain FP64 form timed for comparison (0: skip)")
     ap.add_argument("--fp64-warmup", type=int, default=1)
-    ap.add_argument("--cpu-sample-chi", type=int, default=14)
+    ap.add_argument("--cpu-sample-chi", type=int, default=6)
+    ap.add_argument("--bf16x3-steps", type=int, default=2,
+                    help="optimiser iterations of the BF16X3 form timed for comparison (0: skip)")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--jobs", type=int, default=16)
     ap.add_argument("--serve-iters", type=int, default=30)
@@ -51,35 +53,58 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(sample_chi, gpu_flops_per_eval):
-    """Times the FP64 oracle's scale-invariant ascending map at a smaller bond dimension on the host cores and
-    converts its flop rate to evaluations/s of the benchmark workload (same algorithmic flop count per eval)."""
+def _time_oracle_evals(params, h3, chi, T, budget_s):
+    """Full oracle energy+gradient evaluations (oracle.mera.evaluate) of the same point until budget_s has passed;
+    returns (evaluations, seconds)."""
     from oracle import mera as om
-    from paper_2007_03638_amd import inputs
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        om.evaluate(params, h3, chi, T)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt > budget_s:
+            return n, dt
+
+
+def cpu_baseline(a, sample_chi, sample_T, flops_sample, flops_bench):
+    """The FP64 oracle's whole energy+gradient evaluation (ascending sweep, fixed point, h~, per-occurrence
+    environments: oracle.mera.evaluate, as it stands) timed on the host cores at a bond dimension it finishes in
+    seconds, on the benchmark's model and seed; also at the smallest configuration (chi = 4, T = 2) and on one
+    thread. value = measured evaluations/s of the sample configuration. The benchmark-size figure is only an
+    estimate (the sample's flop rate, with flops per evaluation from the library's counter at both sizes) and is
+    reported separately."""
+    from oracle import mera as om
+    from paper_2007_03638_amd import api, inputs
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
+        threadpool_limits = None
         threads = len(os.sched_getaffinity(0))
-    chi = sample_chi
-    (u, w), = inputs.mera_init(0, [(chi, chi)])
-    h = inputs.symmetric_operator(1, chi ** 3)
-    om.ascend(h, u, w, chi, chi)  # warm BLAS
-    t0 = time.perf_counter()
-    reps = 0
-    while True:
-        om.ascend(h, u, w, chi, chi)
-        reps += 1
-        if time.perf_counter() - t0 > 10.0:
-            break
-    dt = time.perf_counter() - t0
-    # two diagrams, each 2 chi^9 + 3 chi^8 + 2 chi^6 + 2 chi^5 multiply-adds in a pairwise order
-    macs = 2 * (2 * chi ** 9 + 3 * chi ** 8 + 2 * chi ** 6 + 2 * chi ** 5)
-    rate = 2.0 * macs * reps / dt
-    return dict(value=rate / gpu_flops_per_eval, unit="evals/s", cores=threads, kind="oracle",
-                sample=f"oracle FP64 ascending superoperator at chi={chi} ({reps} applications in {dt:.1f} s, "
-                       f"{rate / 1e9:.1f} GFLOP/s), scaled by the algorithmic flops of one chi=24 evaluation "
-                       f"({gpu_flops_per_eval:.3e})")
+    h3 = api.h3_tfim(1.0)
+    params = inputs.mera_init(a.seed, om.layer_dims(sample_chi, sample_T))
+    om.evaluate(params, h3, sample_chi, sample_T)  # warm the BLAS pool
+    n, dt = _time_oracle_evals(params, h3, sample_chi, sample_T, 12.0)
+    rate = n / dt
+    small = inputs.mera_init(0, om.layer_dims(4, 2))
+    n4, dt4 = _time_oracle_evals(small, h3, 4, 2, 3.0)
+    one = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            n1, dt1 = _time_oracle_evals(small, h3, 4, 2, 3.0)
+        one = n1 / dt1
+    return dict(value=rate, unit=f"evals/s (chi={sample_chi}, T={sample_T} sample)", cores=threads, kind="oracle",
+                sample=f"oracle.mera.evaluate (FP64 numpy/scipy) of the benchmark's model and seed at chi={sample_chi}, "
+                       f"T={sample_T}: {n} evaluations in {dt:.1f} s on {threads} BLAS threads; at chi=4, T=2: "
+                       f"{n4} in {dt4:.1f} s; on 1 thread at chi=4, T=2: "
+                       + (f"{one:.3g} evals/s" if one else "not measured"),
+                chi4_T2_evals_per_s=n4 / dt4, one_thread_chi4_T2_evals_per_s=one,
+                sample_gflops=rate * flops_sample / 1e9,
+                estimate_bench_evals_per_s=rate * flops_sample / flops_bench,
+                estimate_note=f"estimate for chi={a.chi}: the sample's flop rate divided by the algorithmic flops of "
+                              f"one chi={a.chi} evaluation (library MAC counter: {flops_sample:.3e} flop at the sample, "
+                              f"{flops_bench:.3e} at chi={a.chi})")
 
 
 def counter_traffic(kernel_variant):
@@ -122,27 +147,27 @@ def precision_check(a, ctx, opt, h3):
             "gradient_rel_error": num / den, "gnorm_fp64": den}
 
 
-def fp64_rate(a):
-    """Evaluations/s of the plain FP64 form on the same workload (same seed and start point)."""
+def form_rate(a, prec, steps, warmup):
+    """Evaluations/s of another contraction precision on the same workload (same seed and start point)."""
     import torch
     from paper_2007_03638_amd import api, inputs
     ctx = api.Context(0)
     dims = api.layer_dims(a.T, a.chi)
     init = [m for pair in inputs.mera_init(a.seed, dims) for m in pair]
-    opt = ctx.optimizer(T=a.T, chi=a.chi, h3=api.h3_tfim(1.0), init=init, prec="fp64", m=8, max_iter=10 ** 6,
+    opt = ctx.optimizer(T=a.T, chi=a.chi, h3=api.h3_tfim(1.0), init=init, prec=prec, m=8, max_iter=10 ** 6,
                         grad_tol=0.0, polish_tol=0.0, precondition=True, max_ls_evals=10)
     state = None
-    for _ in range(a.fp64_warmup):
+    for _ in range(warmup):
         _, state = opt.step()
     s0 = state if state is not None else {"evaluations": 1}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.fp64_steps):
+    for _ in range(steps):
         _, state = opt.step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     evals = state["evaluations"] - s0["evaluations"]
-    print(f"[bench] fp64 form: {evals} evaluations in {dt:.1f} s", file=sys.stderr, flush=True)
+    print(f"[bench] {prec} form: {evals} evaluations in {dt:.1f} s", file=sys.stderr, flush=True)
     return evals / dt
 
 
@@ -223,11 +248,17 @@ def run_eval_bench(a):
         out["precision_vs_fp64"] = precision_check(a, ctx, opt, h3)
         print(f"[bench] precision check: {out['precision_vs_fp64']}", file=sys.stderr, flush=True)
     if a.fp64_steps > 0 and a.prec != "fp64":
-        r64 = fp64_rate(a)
+        r64 = form_rate(a, "fp64", a.fp64_steps, a.fp64_warmup)
         out["fp64_form_evals_per_s"] = r64
         out["speedup_vs_fp64_form"] = out["value"] / r64
+    if a.bf16x3_steps > 0 and a.prec == "fp32":
+        out["bf16x3_form_evals_per_s"] = form_rate(a, "bf16x3", a.bf16x3_steps, 1)
+        out["speedup_bf16x3_vs_fp32"] = out["bf16x3_form_evals_per_s"] / out["value"]
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.cpu_sample_chi, flops / max(evals, 1))
+        # flops of one (cold-started, as the oracle's) FP64 evaluation at the sample size, from the library's counter
+        sp = inputs.mera_init(a.seed, api.layer_dims(a.T, a.cpu_sample_chi))
+        sample = ctx.energy_grad(a.T, a.cpu_sample_chi, [p[0] for p in sp], [p[1] for p in sp], h3, prec="fp64")
+        out["cpu_baseline"] = cpu_baseline(a, a.cpu_sample_chi, a.T, 2.0 * sample["macs"], flops / max(evals, 1))
     return out
 
 
@@ -277,11 +308,13 @@ def run_serve_bench(a):
     stats = srv.stats()
     srv.close()
     lat = np.array([results[i][1]["queued_seconds"] + results[i][1]["seconds"] for i in ids])
-    conv = sum(1 for i in ids if results[i][1]["status"] == 0)
+    status = np.array([results[i][1]["status"] for i in ids])
+    conv = lat[status == 0]
+    pct = (lambda x, q: float(np.percentile(x, q)) if len(x) else None)
     return {
         "metric": METRIC,
-        "value": float(np.percentile(lat, 50)),
-        "unit": "s (p50 time-to-converged)",
+        "value": pct(conv, 50),
+        "unit": "s (p50 time-to-converged over the converged jobs)",
         "n_gpus": 1, "steps": a.jobs, "warmup": 0,
         "ms_per_step": 1000.0 * makespan / a.jobs,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
@@ -289,8 +322,16 @@ def run_serve_bench(a):
         "config": {"workload": f"serving stream of {a.jobs} jobs, Poisson arrivals mean gap 2 s (seed 3), TFIM/XXZ "
                                f"50/50, chi in {{8,12,16,20}}, T=3, FP32 + FP64 polish below 1e-5, "
                                f"stop at |G|<=1e-7 or {a.serve_iters} iterations"},
-        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-        "jobs_per_s": a.jobs / makespan, "converged": conv, "makespan_s": makespan,
+        "converged": int(np.sum(status == 0)), "capped": int(np.sum(status == 1)),
+        "failed": int(np.sum((status != 0) & (status != 1))), "iteration_cap": a.serve_iters,
+        "p50_s": pct(conv, 50), "p99_s": pct(conv, 99),
+        "p50_result_all_s": pct(lat, 50), "p99_result_all_s": pct(lat, 99),
+        "jobs_per_s": a.jobs / makespan, "converged_per_s": float(np.sum(status == 0)) / makespan,
+        "makespan_s": makespan,
+        "jobs": [{"chi": jobs[k][1]["chi"], "arrival_s": arrivals[k], "status": int(results[i][1]["status"]),
+                  "iterations": results[i][1]["iterations"], "gnorm": results[i][1]["gnorm"],
+                  "polish_iter": results[i][1]["polish_iter"], "energy": results[i][1]["energy"],
+                  "latency_s": float(lat[k])} for k, i in enumerate(ids)],
         "slots": a.slots, "grouped_launches": not a.no_group, "graph_replay": not a.no_graphs,
         "batcher": stats,
     }

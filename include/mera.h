@@ -167,6 +167,24 @@ mera_status mera_ascend(mera_ctx* ctx, const mera_shape* shape, int layer, const
 mera_status mera_descend(mera_ctx* ctx, const mera_shape* shape, int layer, const mera_mat* u, const mera_mat* w,
                          mera_prec prec, const double* rho_in, double* rho_out);
 
+/* Derivative of one layer's term Tr[A(h) rho] with h and rho held fixed, for tests and tools (Sec. 4,
+ * eq. mera_derivative: the environment of every occurrence of u and w in the layer's diagrams, summed, with the
+ * 1/2 (binary) or 1/3 (ternary) of the position average; App. B: the same networks give the descending map).
+ *   layer            0..T.  h_in: device FP64 operator on the layer's bottom sites (a^k x a^k, k = 3 binary, 2
+ *                    ternary), rho_in: on its top sites (b^k x b^k); both symmetric (the derivative programs use
+ *                    the ket/bra symmetry of the network and are wrong for asymmetric operators).
+ *   split            0: the combined forward-and-reverse programs (the scale-invariant layer's path in
+ *                    mera_energy_grad); 1 (binary geometry only): the forward halves, which keep their
+ *                    activations, then the reverse halves (the transition layers' path). Same results up to
+ *                    rounding order.
+ *   h_out            nullable device FP64 b^k x b^k output A(h); only with split = 1 (MERA_EINVAL otherwise).
+ *   Du, Dw           caller-allocated device FP64 outputs, shapes of u and w.
+ *   rho_out          nullable device FP64 a^k x a^k output D(rho).
+ * Contractions in `prec`; inputs and outputs FP64. Synchronises the context stream. */
+mera_status mera_layer_grad(mera_ctx* ctx, const mera_shape* shape, int layer, const mera_mat* u,
+                            const mera_mat* w, mera_prec prec, int split, const double* h_in, const double* rho_in,
+                            double* h_out, mera_mat* Du, mera_mat* Dw, double* rho_out);
+
 /* ---- Stiefel manifold (Sec. 2) ------------------------------------------------------------------------ */
 /* All take `count` matrices (a point of the product manifold, Sec. 2.4) and act factor by factor. count = 0 does
  * nothing and returns MERA_OK (the arrays may then be NULL). */
@@ -237,7 +255,9 @@ typedef struct {
   int lbfgs_m;                     /* memory (8)                                                            */
   int max_iter;
   double grad_tol;                 /* stop at ||G|| <= grad_tol                                             */
-  double polish_tol;               /* FP32/BF16X3 forms switch to FP64 below this ||G|| (0: never)          */
+  double polish_tol;               /* FP32/BF16X3 forms switch to FP64 below this ||G||, or when a line      */
+                                   /* search fails in the reduced precision (0: never; a failed search then */
+                                   /* ends the run with status 2)                                           */
   int precondition;                /* 1: Hilbert-space preconditioner as H0 (Sec. 3, Sec. 4)                */
   int max_ls_evals;                /* line-search evaluations per iteration (10)                            */
   mera_krylov_opts krylov;

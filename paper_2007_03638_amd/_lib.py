@@ -78,6 +78,8 @@ SIGNATURES = {
                                  ctypes.POINTER(EvalInfo)]),
     "mera_ascend": (c_int, [c_void_p, ctypes.POINTER(MeraShape), c_int, MAT_P, MAT_P, c_int, c_void_p, c_void_p]),
     "mera_descend": (c_int, [c_void_p, ctypes.POINTER(MeraShape), c_int, MAT_P, MAT_P, c_int, c_void_p, c_void_p]),
+    "mera_layer_grad": (c_int, [c_void_p, ctypes.POINTER(MeraShape), c_int, MAT_P, MAT_P, c_int, c_int, c_void_p,
+                                c_void_p, c_void_p, MAT_P, MAT_P, c_void_p]),
     "stiefel_project": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P]),
     "stiefel_retract": (c_int, [c_void_p, c_int, MAT_P, MAT_P, c_double, MAT_P, MAT_P]),
     "stiefel_transport": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P]),

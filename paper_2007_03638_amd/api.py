@@ -208,6 +208,22 @@ class Context:
                                            ri.data_ptr(), ro.data_ptr()), "mera_descend")
         return ro
 
+    def layer_grad(self, T, chi, layer, u, w, h_in, rho_in, prec="fp64", split=False, d=4, geometry="binary"):
+        """Derivative of Tr[A(h) rho] for one layer: returns (Du, Dw, rho_out, h_out); h_out is None unless split."""
+        dims = layer_dims(T, chi, d, geometry)
+        a, b = dims[layer] if 0 <= layer < len(dims) else dims[-1]  # the library rejects a bad layer
+        u, w, hi, ri = self._dev(u), self._dev(w), self._dev(h_in), self._dev(rho_in)
+        k = _sites(geometry)
+        Du, Dw = torch.empty_like(u), torch.empty_like(w)
+        ro = torch.empty((a ** k, a ** k), dtype=torch.float64, device=self.device)
+        ho = torch.empty((b ** k, b ** k), dtype=torch.float64, device=self.device) if split else None
+        sh = _shape(T, chi, d, geometry)
+        self._check(self._lib.mera_layer_grad(self.ptr, ctypes.byref(sh), layer, _mats([u]), _mats([w]), _prec(prec),
+                                              1 if split else 0, hi.data_ptr(), ri.data_ptr(),
+                                              ho.data_ptr() if split else None, _mats([Du]), _mats([Dw]),
+                                              ro.data_ptr()), "mera_layer_grad")
+        return Du, Dw, ro, ho
+
     # ---- Stiefel manifold ---------------------------------------------------------------------------------
     def stiefel_project(self, W, D):
         W = [self._dev(x) for x in W]

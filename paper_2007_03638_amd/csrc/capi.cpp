@@ -8,6 +8,7 @@
 #include "network.h"
 
 
+
 namespace mera {
 
 Ctx::Ctx() : plans(new PlanCache) {}
@@ -271,6 +272,27 @@ mera_status mera_descend(mera_ctx* ctx, const mera_shape* shape, int layer, cons
                MERA_EINVAL, "tensor shape");
     DeviceGuard g(ctx->c.device);
     descend_op(ctx->c, dims[layer], u->data, w->data, to_prec(prec), rho_in, rho_out);
+    ctx->c.sync();
+  });
+}
+
+mera_status mera_layer_grad(mera_ctx* ctx, const mera_shape* shape, int layer, const mera_mat* u,
+                            const mera_mat* w, mera_prec prec, int split, const double* h_in, const double* rho_in,
+                            double* h_out, mera_mat* Du, mera_mat* Dw, double* rho_out) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(shape && u && w && h_in && rho_in && Du && Dw, MERA_EINVAL, "null argument");
+    auto dims = layer_dims(*shape);
+    MERA_CHECK(layer >= 0 && layer <= shape->T, MERA_EINVAL, "layer out of range");
+    const LayerDim& L = dims[layer];
+    const int a2 = L.a * L.a;
+    MERA_CHECK(u->data && u->n == a2 && u->p == a2 && w->data && w->n == (int)L.wrows() && w->p == L.b,
+               MERA_EINVAL, "tensor shape");
+    MERA_CHECK(Du->data && Du->n == a2 && Du->p == a2 && Dw->data && Dw->n == (int)L.wrows() && Dw->p == L.b,
+               MERA_EINVAL, "gradient shape");
+    DeviceGuard g(ctx->c.device);
+    layer_grad_op(ctx->c, L, u->data, w->data, to_prec(prec), split != 0, h_in, rho_in, h_out, Du->data,
+                  Dw->data, rho_out);
     ctx->c.sync();
   });
 }

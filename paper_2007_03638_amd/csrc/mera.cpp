@@ -683,6 +683,49 @@ void descend_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, P
   copy(ctx, VPtr{rout, Prec::F64}, VPtr{ro, prec}, L.opsize(L.a));
 }
 
+void layer_grad_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, Prec prec, bool split,
+                   const double* hin, const double* rin, double* hout, double* Du, double* Dw, double* rout) {
+  MERA_CHECK(!split || !L.ternary, MERA_EINVAL, "the split forward/reverse programs exist for the binary geometry");
+  MERA_CHECK(split || hout == nullptr, MERA_EINVAL, "h_out is produced only by the split programs");
+  const int64_t a2 = (int64_t)L.a * L.a;
+  const int64_t wn = L.wrows() * L.b;
+  const size_t eb = elem_bytes(prec);
+  LayerTensors t{(void*)u, (void*)w};
+  VPtr hi{(void*)hin, prec}, ri{(void*)rin, prec};
+  VPtr du{Du, prec}, dw{Dw, prec};
+  if (prec != Prec::F64) {
+    t.u = ctx.buf("op.u", a2 * a2 * 4);
+    t.w = ctx.buf("op.w", wn * 4);
+    hi = VPtr{ctx.buf("op.in", L.opsize(L.a) * 4), prec};
+    ri = VPtr{ctx.buf("op.in2", L.opsize(L.b) * 4), prec};
+    du = VPtr{ctx.buf("Dacc.u", a2 * a2 * 4), prec};
+    dw = VPtr{ctx.buf("Dacc.w", wn * 4), prec};
+    copy(ctx, VPtr{t.u, prec}, VPtr{(void*)u, Prec::F64}, a2 * a2);
+    copy(ctx, VPtr{t.w, prec}, VPtr{(void*)w, Prec::F64}, wn);
+    copy(ctx, hi, VPtr{(void*)hin, Prec::F64}, L.opsize(L.a));
+    copy(ctx, ri, VPtr{(void*)rin, Prec::F64}, L.opsize(L.b));
+  }
+  VPtr ro{ctx.buf("op.out", L.opsize(L.a) * eb), prec};
+  if (split) {
+    VPtr ho{ctx.buf("op.out2", L.opsize(L.b) * eb), prec};
+    Activations act;
+    const auto n = activation_elems(L);
+    for (int s = 0; s < 2; ++s)
+      for (int j = 0; j < 4; ++j)
+        act.F[s][j] = ctx.buf("act.op." + std::to_string(s) + "." + std::to_string(j), (size_t)n[j] * eb);
+    ascend_fwd(ctx, L, t, hi, ho, prec, act);
+    layer_grad_rev(ctx, L, t, ri, du, dw, ro, prec, act);
+    if (hout) copy(ctx, VPtr{hout, Prec::F64}, ho, L.opsize(L.b));
+  } else {
+    layer_grad(ctx, L, t, hi, ri, du, dw, ro, prec);
+  }
+  if (prec != Prec::F64) {
+    copy(ctx, VPtr{Du, Prec::F64}, du, a2 * a2);
+    copy(ctx, VPtr{Dw, Prec::F64}, dw, wn);
+  }
+  if (rout) copy(ctx, VPtr{rout, Prec::F64}, ro, L.opsize(L.a));
+}
+
 EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const double* h3, Prec prec, Warm* warm,
                     const KrylovOpts& ko, const GradOut& out) {
   const std::vector<LayerDim> dims = layer_dims(shape);

@@ -70,4 +70,11 @@ void ascend_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, Pr
 void descend_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, Prec prec, const double* rin,
                 double* rout);
 
+// Derivative of Tr[A(h) rho] of one layer with h and rho held fixed (FP64 device operators in and out): Du, Dw
+// (Euclidean, FP64), rout (nullable) = D(rho). split: run the forward halves (hout, nullable, receives A(h)) and
+// then the reverse halves from the kept activations, as an evaluation does for its binary transition layers;
+// otherwise the combined programs, as for the scale-invariant layer (hout must be null).
+void layer_grad_op(Ctx& ctx, const LayerDim& L, const double* u, const double* w, Prec prec, bool split,
+                   const double* hin, const double* rin, double* hout, double* Du, double* Dw, double* rout);
+
 }  // namespace mera

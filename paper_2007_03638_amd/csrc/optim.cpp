@@ -773,6 +773,19 @@ bool Optimizer::advance() {
     if (expr) build_frames();
     ok = line_search(f, slope, 1.0, alpha);
   }
+  if (!ok && prec != Prec::F64 && job.polish_tol > 0) {
+    // Near the noise floor of the reduced-precision energy the expected decrease of a step falls below the
+    // energy's rounding error and the Wolfe conditions can no longer be met: polishing starts here instead,
+    // from the current point re-evaluated in FP64, with the history dropped (its pairs came from the noisy
+    // gradients).
+    prec = Prec::F64;
+    polish_iter = iter;
+    hist.reset();
+    cg_have = false;
+    f = evaluate(W, G, rv);
+    if (job.precondition) met.compute(c, rv.views());
+    return false;
+  }
   if (!ok) {
     status = 2;
     done = true;

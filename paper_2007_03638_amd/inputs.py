@@ -55,3 +55,28 @@ def density_matrix(seed, dim):
     g = rng.standard_normal((dim, dim))
     r = g @ g.T
     return r / np.trace(r)
+
+
+def one_site_factors(seed, n, nterms):
+    """nterms triples of n x n standard-normal matrices, the one-site factors of a product-operator sum."""
+    rng = np.random.default_rng(seed)
+    return [tuple(rng.standard_normal((n, n)) for _ in range(3)) for _ in range(nterms)]
+
+
+def near_identity_isometries(seed, shapes, eps):
+    """Isometries near the first p columns of the n x n identity: the Q factor (sign-fixed as above) of
+    E + eps G, E = [I_p; 0], G standard normal, one per (n, p) in order from default_rng(seed). With a small eps the
+    MERA stays close to a product state, whose energy is far from zero (unlike a Haar-random MERA's)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n, p in shapes:
+        g = np.eye(n)[:, :p] + eps * rng.standard_normal((n, p))
+        q, r = np.linalg.qr(g)
+        out.append(q * np.sign(np.diag(r))[None, :])
+    return out
+
+
+def mera_init_near_identity(seed, dims, eps, w_legs=2):
+    """near_identity_isometries grouped as [(u, w)] per layer, in the order of mera_init."""
+    mats = near_identity_isometries(seed, mera_shapes(dims, w_legs), eps)
+    return [(mats[2 * i], mats[2 * i + 1]) for i in range(len(dims))]

@@ -110,3 +110,89 @@ def test_admission_budget(ctx):
     with pytest.raises(Exception):
         small = api.Server(ctx, hbm_budget=1 << 20, max_slots=1)
         small.submit(**jobs[0])
+
+
+def test_nonfinite_job_fails_alone_in_a_mix(ctx):
+    """Two jobs poisoned on the host (a NaN in the local term, a NaN in an initial disentangler) end with
+    MERA_ENONFINITE, while the jobs running beside them, grouped with them where the shapes match, give exactly
+    their results alone."""
+    from paper_2007_03638_amd import api
+    jobs = _jobs()
+    alone = [_run_all(ctx, [j], 1, group_launches=False, graph_capture=False)[0][0] for j in jobs]
+    bad_h = dict(jobs[0])
+    bad_h["h3"] = bad_h["h3"].copy()
+    bad_h["h3"][5, 5] = np.nan
+    bad_u = dict(jobs[1])
+    bad_u["init"] = [m.copy() for m in bad_u["init"]]
+    bad_u["init"][2][3, 1] = np.nan
+    srv = api.Server(ctx, hbm_budget=64 << 30, max_slots=4)
+    ids = [srv.submit(**j) for j in (jobs[0], bad_h, jobs[1], bad_u, jobs[2], jobs[3])]
+    t0 = time.time()
+    out = {}
+    while len(out) < len(ids):
+        for i in ids:
+            if i in out:
+                continue
+            try:
+                r = srv.poll(i)
+            except api.MeraError as e:
+                out[i] = e.status
+                continue
+            if r is not None:
+                out[i] = r
+        assert time.time() - t0 < 300
+        time.sleep(0.01)
+    st = srv.stats()
+    srv.close()
+    print("stats", st, "poisoned:", out[ids[1]], out[ids[3]], flush=True)
+    assert out[ids[1]] == -5 and out[ids[3]] == -5
+    for k, i in zip((0, 1, 2, 3), (ids[0], ids[2], ids[4], ids[5])):
+        r = out[i]
+        assert r["status"] == alone[k]["status"] == 1
+        assert r["energy"] == alone[k]["energy"]
+        assert r["gnorm"] == alone[k]["gnorm"]
+        assert r["evaluations"] == alone[k]["evaluations"]
+
+
+def test_job_arriving_mid_evaluation(ctx):
+    """A job submitted while two jobs of its shape are running (their grouped programs under way) joins them and
+    computes exactly what it computes alone; so do the two."""
+    from paper_2007_03638_amd import api
+    jobs = _jobs()
+    j8 = [jobs[1], jobs[3], dict(jobs[1])]  # chi = 8 jobs; the third repeats the first
+    alone = [_run_all(ctx, [j], 1, group_launches=False, graph_capture=False)[0][0] for j in j8[:2]]
+    srv = api.Server(ctx, hbm_budget=64 << 30, max_slots=4)
+    ids = [srv.submit(**j8[0]), srv.submit(**j8[1])]
+    t0 = time.time()
+    while srv.stats()["grouped_batches"] < 3:  # the two running jobs share launches by now
+        assert time.time() - t0 < 120
+        time.sleep(0.002)
+    assert srv.poll(ids[0]) is None and srv.poll(ids[1]) is None
+    ids.append(srv.submit(**j8[2]))
+    res = _wait(srv, ids)
+    st = srv.stats()
+    srv.close()
+    print("stats", st, [r["energy"] for r in res], flush=True)
+    for r, a in zip(res, [alone[0], alone[1], alone[0]]):
+        assert r["energy"] == a["energy"] and r["gnorm"] == a["gnorm"] and r["evaluations"] == a["evaluations"]
+    assert res[2]["queued_seconds"] < res[2]["seconds"]
+
+
+def test_budget_below_one_job(ctx):
+    """A job larger than the whole budget is refused at submission with MERA_ENOMEM; the server keeps serving jobs
+    that fit."""
+    from paper_2007_03638_amd import api
+    jobs = _jobs()
+    small = jobs[0]
+    fp_small = api.job_footprint(small["T"], small["chi"], "fp32")
+    fp_big = api.job_footprint(jobs[1]["T"], jobs[1]["chi"], "fp32")
+    assert fp_big > fp_small
+    srv = api.Server(ctx, hbm_budget=fp_small, max_slots=2)
+    with pytest.raises(api.MeraError) as e:
+        srv.submit(**jobs[1])
+    assert e.value.status == -2
+    ids = [srv.submit(**small)]
+    res = _wait(srv, ids)
+    srv.close()
+    ref = _run_all(ctx, [small], 1, group_launches=False, graph_capture=False)[0][0]
+    assert res[0]["energy"] == ref["energy"] and res[0]["status"] == 1
