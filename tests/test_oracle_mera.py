@@ -273,3 +273,17 @@ def test_product_operator_forms_match_dense(a, b):
     scale = max(np.max(np.abs(Du2)), np.max(np.abs(Dw2)))
     assert np.max(np.abs(Du - Du2)) < 1e-12 * scale
     assert np.max(np.abs(Dw - Dw2)) < 1e-12 * scale
+
+
+@pytest.mark.parametrize("name", ["eval_chi12_T2.npz", "eval_chi12_T2_near.npz"])
+def test_stored_chi12_evaluation(name):
+    """tests/golden/eval_chi12_T2*.npz (written by tests/golden/make_chi12.py from the oracle): the energy agrees
+    with the one obtained by full descent stored beside it, lies above the exact infinite-chain energy (-4/pi per
+    spin), and the stored gradients have the layer shapes."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", name))
+    assert abs(float(g["energy"]) - float(g["energy_bottom"])) < 1e-13
+    assert float(g["energy"]) / 2 > model.tfim_exact_energy_per_spin(1.0)
+    for t, (a, b) in enumerate(mera.layer_dims(int(g["chi"]), int(g["T"]))):
+        assert g[f"Du{t}"].shape == (a * a, a * a) and g[f"Dw{t}"].shape == (a * a, b)
+        assert g[f"rho_u{t}"].shape == (a * a, a * a) and g[f"rho_w{t}"].shape == (b, b)
