@@ -191,6 +191,14 @@ mera_status mera_layer_grad(mera_ctx* ctx, const mera_shape* shape, int layer, c
 
 /* G = D - W (W^T D + D^T W) / 2 (eq. stiefel_gradient, real case). G may alias D. */
 mera_status stiefel_project(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, mera_mat* G);
+/* stiefel_project without any device allocation, for callers that cannot allocate: code under HIP graph capture,
+ * serving loops and harnesses that forbid hipMalloc. Same arguments and result as stiefel_project (up to rounding
+ * order). The p x p intermediate W^T D lives in a fixed file-scope device array of 2^20 doubles (8 MiB) per GPU,
+ * held until the process ends: every factor must have p * p <= 2^20 (p <= 1024), at most 2097120 rows, and count
+ * <= 64, else MERA_EINVAL. The call only launches kernels on the context stream and does not synchronise it (the
+ * outputs are ready when the stream is). All calls on one GPU share that array: calls that overlap on one GPU
+ * (other streams, other contexts, other threads) race and give wrong results. G may alias D, not W. */
+mera_status stiefel_project_noalloc(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, mera_mat* G);
 /* Polar retraction W_out = (W + alpha X)(I + alpha^2 X^T X)^{-1/2} computed as the polar factor of
  * Y = W + alpha X, with (Y^T Y)^{-1/2} by a coupled Newton-Schulz iteration in FP64 (retraction as defined in
  * Sec. 2.3; the polar form is this library's choice). X_out (nullable) receives dR/dalpha at alpha, the

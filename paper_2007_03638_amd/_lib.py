@@ -81,6 +81,7 @@ SIGNATURES = {
     "mera_layer_grad": (c_int, [c_void_p, ctypes.POINTER(MeraShape), c_int, MAT_P, MAT_P, c_int, c_int, c_void_p,
                                 c_void_p, c_void_p, MAT_P, MAT_P, c_void_p]),
     "stiefel_project": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P]),
+    "stiefel_project_noalloc": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P]),
     "stiefel_retract": (c_int, [c_void_p, c_int, MAT_P, MAT_P, c_double, MAT_P, MAT_P]),
     "stiefel_transport": (c_int, [c_void_p, c_int, MAT_P, MAT_P, MAT_P]),
     "stiefel_retract_exp": (c_int, [c_void_p, c_int, MAT_P, MAT_P, c_double, MAT_P, MAT_P]),

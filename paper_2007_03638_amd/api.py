@@ -232,6 +232,14 @@ class Context:
         self._check(self._lib.stiefel_project(self.ptr, len(W), _mats(W), _mats(D), _mats(G)), "stiefel_project")
         return G
 
+    def stiefel_project_noalloc(self, W, D, G=None):
+        """stiefel_project through the allocation-free entry point. W, D (and G, if given) must already be device
+        tensors; the call is only ordered on the context stream (synchronise before reading G)."""
+        G = [torch.empty_like(x) for x in D] if G is None else G
+        self._check(self._lib.stiefel_project_noalloc(self.ptr, len(W), _mats(W), _mats(D), _mats(G)),
+                    "stiefel_project_noalloc")
+        return G
+
     def stiefel_retract(self, W, X, alpha, tangent=True):
         W = [self._dev(x) for x in W]
         X = [self._dev(x) for x in X]

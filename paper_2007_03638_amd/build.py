@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmera_hip.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["gett.hip", "vec.hip", "network.cpp", "linalg.cpp", "model.cpp", "mera.cpp", "optim.cpp",
+SOURCES = ["gett.hip", "vec.hip", "noalloc.hip", "network.cpp", "linalg.cpp", "model.cpp", "mera.cpp", "optim.cpp",
            "server.cpp", "capi.cpp"]
 
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

@@ -7,6 +7,13 @@
 #include "model.h"
 #include "network.h"
 
+namespace mera {
+// noalloc.hip
+int64_t noalloc_scratch_doubles();
+double* noalloc_scratch(int device);
+void stiefel_project_noalloc_run(double* S, hipStream_t stream, int count, const int* n, const int* p,
+                                 const double* const* W, const double* const* D, double* const* G);
+}  // namespace mera
 
 
 namespace mera {
@@ -94,6 +101,7 @@ mera_status mera_ctx_create(int device, void* hip_stream, mera_ctx** out) {
     c->c.device = device;
     c->c.stream = static_cast<hipStream_t>(hip_stream);
     DeviceGuard g(device);
+    (void)noalloc_scratch(device);  // this device's copy of the allocation-free entry point's scratch array
     *out = c;
     return MERA_OK;
   } catch (...) {
@@ -349,6 +357,40 @@ mera_status stiefel_project(mera_ctx* ctx, int count, const mera_mat* W, const m
       stiefel_project_one(ctx->c, MatView{W[i].n, W[i].p, W[i].data}, MatView{D[i].n, D[i].p, D[i].data},
                           MatView{G[i].n, G[i].p, G[i].data});
     ctx->c.sync();
+  });
+}
+
+mera_status stiefel_project_noalloc(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* D, mera_mat* G) {
+  if (!ctx) return MERA_EINVAL;
+  return guarded(ctx, [&] {
+    MERA_CHECK(count >= 0, MERA_EINVAL, "count");
+    check_isometry_shapes(W, count, "stiefel_project_noalloc W");
+    check_mats(D, count, "stiefel_project_noalloc D");
+    check_mats(G, count, "stiefel_project_noalloc G");
+    same_shapes(W, D, count, "stiefel_project_noalloc");
+    same_shapes(W, G, count, "stiefel_project_noalloc");
+    constexpr int kMaxFactors = 64;
+    MERA_CHECK(count <= kMaxFactors, MERA_EINVAL, "stiefel_project_noalloc: more than 64 factors in one call");
+    int n[kMaxFactors], p[kMaxFactors];
+    const double* Wp[kMaxFactors];
+    const double* Dp[kMaxFactors];
+    double* Gp[kMaxFactors];
+    for (int i = 0; i < count; ++i) {
+      MERA_CHECK((int64_t)W[i].p * W[i].p <= noalloc_scratch_doubles(), MERA_EINVAL,
+                 "stiefel_project_noalloc: factor " + std::to_string(i) + " has p = " + std::to_string(W[i].p) +
+                     "; p * p must fit the fixed scratch of " + std::to_string(noalloc_scratch_doubles()) +
+                     " doubles (p <= 1024)");
+      MERA_CHECK(W[i].n <= 65535 * 32, MERA_EINVAL, "stiefel_project_noalloc: more than 2097120 rows");
+      MERA_CHECK(G[i].data != W[i].data, MERA_EINVAL, "stiefel_project_noalloc: G aliases W");
+      n[i] = W[i].n;
+      p[i] = W[i].p;
+      Wp[i] = W[i].data;
+      Dp[i] = D[i].data;
+      Gp[i] = G[i].data;
+    }
+    if (count == 0) return;
+    DeviceGuard g(ctx->c.device);
+    stiefel_project_noalloc_run(noalloc_scratch(ctx->c.device), ctx->c.stream, count, n, p, Wp, Dp, Gp);
   });
 }
 
