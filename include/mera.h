@@ -127,6 +127,11 @@ typedef struct {
                            /* fewer (at least 4) to keep the basis within 16 GiB                       */
   int max_restarts;        /* per solve; 0 -> 200                                                      */
   double tol;              /* relative residual of both solves; 0 -> 1e-13 (FP64) or 1e-7 (FP32/BF16X3)  */
+  int extrapolate;         /* with a warm-start object: > 0 (and 0, the default) starts both solves from the */
+                           /* solutions of the last two evaluations extrapolated along this evaluation's    */
+                           /* step (x1 + t (x1 - x2), t = <P - P1, P1 - P2> / |P1 - P2|^2 over the tensors */
+                           /* P of the three points, clamped to [-1, 1]); < 0 starts them from the last    */
+                           /* solution alone (App. B)                                                      */
 } mera_krylov_opts;
 
 typedef struct {

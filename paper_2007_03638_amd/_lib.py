@@ -18,7 +18,7 @@ class MeraShape(ctypes.Structure):
 
 
 class KrylovOpts(ctypes.Structure):
-    _fields_ = [("krylov_dim", c_int), ("max_restarts", c_int), ("tol", c_double)]
+    _fields_ = [("krylov_dim", c_int), ("max_restarts", c_int), ("tol", c_double), ("extrapolate", c_int)]
 
 
 class EvalInfo(ctypes.Structure):

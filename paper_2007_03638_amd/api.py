@@ -173,7 +173,8 @@ class Context:
         info = L.EvalInfo()
         ko = None
         if krylov is not None:
-            ko = L.KrylovOpts(krylov.get("dim", 0), krylov.get("max_restarts", 0), krylov.get("tol", 0.0))
+            ko = L.KrylovOpts(krylov.get("dim", 0), krylov.get("max_restarts", 0), krylov.get("tol", 0.0),
+                              krylov.get("extrapolate", 0))
         sh = _shape(T, chi, d, geometry)
         st = self._lib.mera_energy_grad(self.ptr, ctypes.byref(sh), _mats(u), _mats(w), h3d.data_ptr(),
                                         _prec(prec), warm.ptr if warm else None,
@@ -355,7 +356,7 @@ def make_job(T, chi, h3, init, prec="fp64", m=8, max_iter=100, grad_tol=1e-10, p
     kr = krylov or {}
     job = L.Job(_shape(T, chi, d, geometry), h3c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ptrs, _prec(prec), m,
                 max_iter, grad_tol, polish_tol, 1 if precondition else 0, max_ls_evals,
-                L.KrylovOpts(kr.get("dim", 0), kr.get("max_restarts", 0), kr.get("tol", 0.0)),
+                L.KrylovOpts(kr.get("dim", 0), kr.get("max_restarts", 0), kr.get("tol", 0.0), kr.get("extrapolate", 0)),
                 {"lbfgs": 0, "cg": 1, "ev": 2}[method], {"polar": 0, "exp": 1}[retraction],
                 1 if grassmann_w else 0, float(ev_gamma))
     return job, (h3c, mats, ptrs)

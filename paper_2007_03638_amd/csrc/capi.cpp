@@ -232,6 +232,7 @@ mera_status mera_energy_grad(mera_ctx* ctx, const mera_shape* shape, const mera_
     KrylovOpts ko;
     if (kopts) {
       if (kopts->krylov_dim > 0) ko.dim = kopts->krylov_dim;
+      if (kopts->extrapolate != 0) ko.extrapolate = kopts->extrapolate > 0;
       if (kopts->max_restarts > 0) ko.max_restarts = kopts->max_restarts;
       if (kopts->tol > 0) ko.tol = kopts->tol;
     }

@@ -20,6 +20,7 @@
 // counted twice, which with the 1/2 of the position average gives weight 1.
 #include "mera_eval.h"
 
+#include <algorithm>
 #include <array>
 
 #include <cmath>
@@ -776,6 +777,50 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
     else ascend_raw(ctx, dims[t], lt[t], hs[t], hs[t + 1], prec);
   }
 
+  // Extrapolated warm starts: with the solutions x1, x2 of the last two evaluations (at points P1, P2), both solves
+  // start from x1 + t (x1 - x2), t the component of this evaluation's step P - P1 along the previous step P1 - P2
+  // (a first-order prediction along the line the optimiser moves on; within a line search the points are
+  // collinear). The tensors of the last two points are kept flattened in the warm-start object.
+  double theta = 0.0;
+  bool extrap = false;
+  if (warm && ko.extrapolate) {
+    int64_t ne = 0;
+    for (int t = 0; t <= T; ++t) ne += (int64_t)dims[t].a * dims[t].a * dims[t].a * dims[t].a + dims[t].wrows() * dims[t].b;
+    if (warm->pt_elems != ne || warm->chi != chi) {
+      warm->npts = 0;
+      warm->has_prev = false;
+      warm->pt_elems = ne;
+    }
+    warm->pts[0].ensure(ne * 8);
+    warm->pts[1].ensure(ne * 8);
+    double* cur = static_cast<double*>(ctx.buf("warm.cur", ne * 8));
+    int64_t o = 0;
+    for (int t = 0; t <= T; ++t) {
+      const int64_t nu = (int64_t)dims[t].a * dims[t].a * dims[t].a * dims[t].a, nw = dims[t].wrows() * dims[t].b;
+      copy(ctx, VPtr{cur + o, Prec::F64}, VPtr{(void*)pt.u[t], Prec::F64}, nu);
+      copy(ctx, VPtr{cur + o + nu, Prec::F64}, VPtr{(void*)pt.w[t], Prec::F64}, nw);
+      o += nu + nw;
+    }
+    if (warm->npts >= 2 && warm->has_prev && warm->has_rho && warm->has_ht) {
+      double* d1 = static_cast<double*>(ctx.buf("warm.d1", ne * 8));
+      double* d0 = static_cast<double*>(ctx.buf("warm.d0", ne * 8));
+      const VPtr p1{warm->pts[0].ptr, Prec::F64}, p2{warm->pts[1].ptr, Prec::F64};
+      copy(ctx, VPtr{d1, Prec::F64}, VPtr{cur, Prec::F64}, ne);
+      axpby(ctx, -1.0, p1, 1.0, VPtr{d1, Prec::F64}, ne);
+      copy(ctx, VPtr{d0, Prec::F64}, p1, ne);
+      axpby(ctx, -1.0, p2, 1.0, VPtr{d0, Prec::F64}, ne);
+      const double den = dot(ctx, VPtr{d0, Prec::F64}, VPtr{d0, Prec::F64}, ne);
+      if (den > 0.0 && std::isfinite(den)) {
+        theta = dot(ctx, VPtr{d1, Prec::F64}, VPtr{d0, Prec::F64}, ne) / den;
+        theta = std::max(-1.0, std::min(1.0, theta));
+        extrap = std::isfinite(theta) && theta != 0.0;
+      }
+    }
+    std::swap(warm->pts[0], warm->pts[1]);
+    copy(ctx, VPtr{warm->pts[0].ptr, Prec::F64}, VPtr{cur, Prec::F64}, ne);
+    warm->npts = std::min(2, warm->npts + 1);
+  }
+
   const double tol = ko.tol > 0 ? ko.tol : (prec == Prec::F64 ? 1e-13 : 1e-7);
   const int kdim = ko.dim > 0 ? ko.dim : default_krylov_dim((size_t)n6 * eb);
   const int kres = ko.max_restarts > 0 ? ko.max_restarts : 200;
@@ -786,6 +831,10 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
   VPtr tmp{ctx.buf("ktmp", n6 * eb), prec};
   if (warm && warm->has_rho && warm->chi == chi) {
     copy(ctx, rho, VPtr{warm->rho.ptr, Prec::F64}, n6);
+    if (extrap) {
+      axpby(ctx, theta, VPtr{warm->rho.ptr, Prec::F64}, 1.0, rho, n6);
+      axpby(ctx, -theta, VPtr{warm->rho_prev.ptr, Prec::F64}, 1.0, rho, n6);
+    }
     double tr = trace(ctx, rho, chi3);
     scal(ctx, 1.0 / tr, rho, n6);
   } else {
@@ -819,8 +868,15 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
   VPtr ht{ctx.buf("htilde", n6 * eb), prec};
   copy(ctx, hp, hs[T], n6);
   add_diag(ctx, hp, chi3, -e);
-  if (warm && warm->has_ht && warm->chi == chi) copy(ctx, ht, VPtr{warm->ht.ptr, Prec::F64}, n6);
-  else copy(ctx, ht, hp, n6);
+  if (warm && warm->has_ht && warm->chi == chi) {
+    copy(ctx, ht, VPtr{warm->ht.ptr, Prec::F64}, n6);
+    if (extrap) {
+      axpby(ctx, theta, VPtr{warm->ht.ptr, Prec::F64}, 1.0, ht, n6);
+      axpby(ctx, -theta, VPtr{warm->ht_prev.ptr, Prec::F64}, 1.0, ht, n6);
+    }
+  } else {
+    copy(ctx, ht, hp, n6);
+  }
   auto op_ht = [&](VPtr in, VPtr o) {
     ascend_raw(ctx, S, lt[T], in, o, prec);
     axpby(ctx, 1.0, in, -1.0, o, n6);
@@ -834,6 +890,14 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
   res.res_ht = kh.res;
 
   if (warm) {
+    if (ko.extrapolate && warm->has_rho && warm->has_ht && warm->chi == chi) {
+      // the current solutions become the previous ones
+      warm->rho_prev.ensure(n6 * 8);
+      warm->ht_prev.ensure(n6 * 8);
+      std::swap(warm->rho, warm->rho_prev);
+      std::swap(warm->ht, warm->ht_prev);
+      warm->has_prev = true;
+    }
     warm->chi = chi;
     warm->rho.ensure(n6 * 8);
     warm->ht.ensure(n6 * 8);

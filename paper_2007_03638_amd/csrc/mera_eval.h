@@ -39,13 +39,21 @@ struct Point {
 struct Warm {
   int chi = 0;
   bool has_rho = false, has_ht = false;
-  DevBuf rho, ht;  // FP64 operators (chi^6 binary, chi^4 ternary)
+  DevBuf rho, ht;  // FP64 operators (chi^6 binary, chi^4 ternary) of the last evaluation
+  // for extrapolated starts: the solutions of the evaluation before (valid with has_prev) and the tensors of the
+  // last two evaluation points, flattened (pts[0] the newer; npts of them valid)
+  bool has_prev = false;
+  DevBuf rho_prev, ht_prev;
+  DevBuf pts[2];
+  int npts = 0;
+  int64_t pt_elems = 0;
 };
 
 struct KrylovOpts {
   int dim = 0;  // 0: default_krylov_dim of the vector size
   int max_restarts = 200;
   double tol = 0.0;  // 0: precision default
+  bool extrapolate = true;  // start from the last two solutions extrapolated along the step (needs a Warm)
 };
 
 struct EvalOut {

@@ -586,6 +586,7 @@ JobSpec JobSpec::from_c(const mera_job& j) {
   if (j.krylov.krylov_dim > 0) s.krylov.dim = j.krylov.krylov_dim;
   if (j.krylov.max_restarts > 0) s.krylov.max_restarts = j.krylov.max_restarts;
   if (j.krylov.tol > 0) s.krylov.tol = j.krylov.tol;
+  if (j.krylov.extrapolate != 0) s.krylov.extrapolate = j.krylov.extrapolate > 0;
   MERA_CHECK(s.m >= 0 && s.max_iter >= 0, MERA_EINVAL, "job: negative memory or iteration cap");
   return s;
 }

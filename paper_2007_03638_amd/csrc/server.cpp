@@ -41,8 +41,9 @@ size_t job_footprint(const mera_shape& s, Prec prec, int krylov_dim = 0) {
   }
   const double chi6 = (double)dims.back().opsize(s.chi);
   // Krylov basis (dimension + 1 vectors, residual), fixed point, h~, sigma, scratch, hs/rho levels, FP64 warm starts
+  // of the last two evaluations (extrapolated starts)
   const int kdim = krylov_dim > 0 ? krylov_dim : default_krylov_dim((size_t)(eb * chi6));
-  bytes += eb * chi6 * ((kdim + 2) + 6 + 2 * (s.T + 1)) + 16.0 * chi6;
+  bytes += eb * chi6 * ((kdim + 2) + 6 + 2 * (s.T + 1)) + 32.0 * chi6;
   // forward activations of the transition layers, kept within the default intermediate limit
   const double act = (double)activation_cache_bytes(dims, elem_bytes(prec));
   if (act <= (double)((size_t)32 << 30)) bytes += act;

@@ -39,6 +39,9 @@ def main():
     ap.add_argument("--retraction", default="polar", choices=["polar", "exp"])
     ap.add_argument("--grassmann-w", action="store_true")
     ap.add_argument("--progress", type=int, default=0)
+    ap.add_argument("--extrapolate", type=int, default=0,
+                    help="Krylov warm starts extrapolated along the step (1), or from the last solution (-1); "
+                         "0: library default (extrapolated)")
     ap.add_argument("--save", default="", help="write the final tensors to this .npz")
     ap.add_argument("--init", default="", help="initial tensors from an .npz written by --save")
     ap.add_argument("--iter-offset", type=int, default=0, help="iterations already done (with --init)")
@@ -64,7 +67,8 @@ def main():
     t0 = time.perf_counter()
     opt = ctx.optimizer(T=a.T, chi=a.chi, h3=h3, init=init, prec=a.prec, m=a.m, max_iter=a.iters - a.iter_offset,
                         grad_tol=a.grad_tol, polish_tol=a.polish, method=a.method, retraction=a.retraction,
-                        grassmann_w=a.grassmann_w, ev_gamma=a.ev_gamma, d=d, geometry=a.geometry)
+                        grassmann_w=a.grassmann_w, ev_gamma=a.ev_gamma, d=d, geometry=a.geometry,
+                        krylov={"extrapolate": a.extrapolate})
     done, st = False, None
     history = []
     stopped = ""
@@ -112,6 +116,7 @@ def main():
                stopped=stopped, init=a.init, polish=polish,
                polish_iter=st["polish_iter"], seconds=dt, tflops=2 * st["macs"] / dt / 1e12,
                krylov_applications=st["krylov_applications"],
+               krylov_per_eval=st["krylov_applications"] / max(1, st["evaluations"]),
                history=history[:: max(1, len(history) // 50)])
     print(json.dumps(out), flush=True)
 

@@ -67,6 +67,30 @@ def test_fp32_with_fp64_polish(ctx):
     assert got["energy"] / 2 > model.tfim_exact_energy_per_spin(1.0)
 
 
+def test_fp32_polish_reaches_the_fp64_minimum(ctx):
+    """The FP32 form with FP64 polishing (switch below |G| = 1e-5) converges to the energy the plain FP64 form
+    converges to, within 1e-10 relative, from the same start near a minimum (a point after 600 FP64 iterations, so
+    that both runs stay in one basin; points that differ by the MERA's gauge freedom have equal energies); both end
+    converged at |G| <= 1e-8 and the oracle re-evaluates the polished point to 1e-10."""
+    chi, T = 4, 2
+    h3 = model.tfim_h3(1.0)
+    pre = ctx.run_optimize(T, chi, h3, _init(3, chi, T), prec="fp64", m=8, max_iter=600, grad_tol=0.0,
+                           want_final=True)
+    W1 = pre["final"]
+    ref = ctx.run_optimize(T, chi, h3, W1, prec="fp64", m=8, max_iter=3000, grad_tol=1e-8)
+    got = ctx.run_optimize(T, chi, h3, W1, prec="fp32", m=8, max_iter=3000, grad_tol=1e-8, polish_tol=1e-5,
+                           want_final=True)
+    print(f"start |G| {pre['gnorm']:.2e}; fp64 {ref['energy']!r} |G| {ref['gnorm']:.2e} it {ref['iterations']}; "
+          f"fp32+polish {got['energy']!r} |G| {got['gnorm']:.2e} it {got['iterations']} polish at "
+          f"{got['polish_iter']}", flush=True)
+    assert ref["status"] == 0 and got["status"] == 0
+    assert got["polish_iter"] >= 0
+    assert abs(got["energy"] - ref["energy"]) <= 1e-10 * abs(ref["energy"])
+    W = got["final"]
+    params = [(W[2 * i], W[2 * i + 1]) for i in range(T + 1)]
+    assert abs(om.energy_only(params, h3, chi, T) - got["energy"]) <= 1e-10 * abs(got["energy"])
+
+
 @pytest.mark.parametrize("precondition", [True, False])
 def test_fp64_cg_trajectory_matches_oracle(ctx, precondition):
     """Nonlinear CG (Hager-Zhang coefficient, transported previous direction) against the oracle's CG driver."""
