@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--jobs", type=int, default=16)
     ap.add_argument("--serve-iters", type=int, default=30)
+    ap.add_argument("--serve-tol", type=float, default=1e-7, help="serving: converged at |G| <= this")
+    ap.add_argument("--serve-chis", default="8,12,16,20", help="serving: bond dimensions drawn uniformly")
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--no-group", action="store_true", help="serving: no grouped launches across jobs")
     ap.add_argument("--no-graphs", action="store_true", help="serving: no HIP graph replay")
@@ -264,8 +266,8 @@ def run_eval_bench(a):
 
 def run_serve_bench(a):
     """Serving stream: Poisson arrivals (mean gap 2 s, seed 3), TFIM h ~ U[0.5, 1.5] or XXZ delta ~ U[-0.5, 1.5]
-    (50/50), chi from {8, 12, 16, 20}, FP32 contractions with FP64 polishing, stop at |G| <= 1e-7 or the
-    iteration cap."""
+    (50/50), chi from {8, 12, 16, 20} (--serve-chis), FP32 contractions with FP64 polishing, stop at |G| <= 1e-7
+    (--serve-tol) or the iteration cap."""
     from paper_2007_03638_amd import api, inputs
     rng = np.random.default_rng(3)
     ctx = api.Context(0)
@@ -275,7 +277,7 @@ def run_serve_bench(a):
     t_arr = 0.0
     for k in range(a.jobs):
         t_arr += rng.exponential(2.0)
-        chi = int(rng.choice([8, 12, 16, 20]))
+        chi = int(rng.choice([int(c) for c in a.serve_chis.split(",")]))
         if rng.random() < 0.5:
             h3 = api.h3_tfim(rng.uniform(0.5, 1.5))
         else:
@@ -283,7 +285,7 @@ def run_serve_bench(a):
         dims = api.layer_dims(3, chi)
         init = [m for pair in inputs.mera_init(1000 + k, dims) for m in pair]
         jobs.append((t_arr, dict(T=3, chi=chi, h3=h3, init=init, prec="fp32", m=8, max_iter=a.serve_iters,
-                                 grad_tol=1e-7, polish_tol=1e-5)))
+                                 grad_tol=a.serve_tol, polish_tol=1e-5)))
     t0 = time.perf_counter()
     ids, arrivals = [], []
     pending = list(jobs)
@@ -320,8 +322,8 @@ def run_serve_bench(a):
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"serving stream of {a.jobs} jobs, Poisson arrivals mean gap 2 s (seed 3), TFIM/XXZ "
-                               f"50/50, chi in {{8,12,16,20}}, T=3, FP32 + FP64 polish below 1e-5, "
-                               f"stop at |G|<=1e-7 or {a.serve_iters} iterations"},
+                               f"50/50, chi in {{{a.serve_chis}}}, T=3, FP32 + FP64 polish below 1e-5, "
+                               f"stop at |G|<={a.serve_tol:g} or {a.serve_iters} iterations"},
         "converged": int(np.sum(status == 0)), "capped": int(np.sum(status == 1)),
         "failed": int(np.sum((status != 0) & (status != 1))), "iteration_cap": a.serve_iters,
         "p50_s": pct(conv, 50), "p99_s": pct(conv, 99),

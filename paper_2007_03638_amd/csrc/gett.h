@@ -18,14 +18,15 @@ namespace mera {
 // arithmetically (no table, no memory load): q / ext_l = mulhi(q, mag_l) with mag_l = ceil(2^32 / ext_l), exact
 // because every quotient q met satisfies q * ext_l <= 2^32 (checked when the legs are built); the slowest leg has
 // mag 0 (its digit is the whole remaining quotient). Legs of extent 1 are dropped and legs contiguous in both
-// operands merged; unused entries are zero.
+// operands merged; unused entries are zero. Strides are 32-bit (in elements, checked when the legs are built); the
+// digits are formed in 32-bit arithmetic and each digit-stride product is accumulated into a 64-bit offset.
 constexpr int kGettMaxKLegs = 4;
 struct GettKLegs {
   int n = 0;
   uint32_t ext[kGettMaxKLegs] = {};
   uint32_t mag[kGettMaxKLegs] = {};
-  int64_t sa[kGettMaxKLegs] = {};
-  int64_t sb[kGettMaxKLegs] = {};
+  uint32_t sa[kGettMaxKLegs] = {};
+  uint32_t sb[kGettMaxKLegs] = {};
 };
 
 struct GettTables {

@@ -63,16 +63,16 @@ template <> struct Mma<double> {
 // Offset of the k-th index along the contracted legs (fastest leg first; see GettKLegs): NKL digit extractions
 // by reciprocal multiplication, no memory access. Entries past kl.n are zero and contribute nothing.
 template <int NKL>
-__device__ inline int64_t k_offset(uint32_t k, const GettKLegs& kl, const int64_t* stride) {
-  int64_t off = 0;
+__device__ inline uint64_t k_offset(uint32_t k, const GettKLegs& kl, const uint32_t* stride) {
+  uint64_t off = 0;
   uint32_t q = k;
 #pragma unroll
   for (int l = 0; l + 1 < NKL; ++l) {
     const uint32_t qn = __umulhi(q, kl.mag[l]);
-    off += (int64_t)(q - qn * kl.ext[l]) * stride[l];
+    off += (uint64_t)(q - qn * kl.ext[l]) * stride[l];
     q = qn;
   }
-  return off + (int64_t)q * stride[NKL - 1];
+  return off + (uint64_t)q * stride[NKL - 1];
 }
 
 // Tile loader: BMN x BK tile of an operand whose element (r, k) lives at base + off_r[r] + k_offset(k).
@@ -109,11 +109,12 @@ struct Loader {
     for (int i = 0; i < NR; ++i) rowp[i] = base + off_r[rbase + r0 + i * RSTEP];
   }
   // loads the tile starting at kt; element (i): row index i % NR, k index i / NR
-  __device__ inline void load(int64_t kt, int64_t K, const GettKLegs& kl, const int64_t* stride) {
+  __device__ inline void load(int64_t kt, int64_t K, const GettKLegs& kl, const uint32_t* stride) {
+    const uint32_t klast = (uint32_t)K - 1;
 #pragma unroll
     for (int j = 0; j < NK; ++j) {
-      const int64_t k = kt + k0 + j * KSTEP;
-      const int64_t o = k_offset<NKL>((uint32_t)(k < K ? k : K - 1), kl, stride);
+      const uint32_t k = (uint32_t)kt + k0 + j * KSTEP;
+      const uint64_t o = k_offset<NKL>(k < klast ? k : klast, kl, stride);
 #pragma unroll
       for (int r = 0; r < NR; ++r) reg[j * NR + r] = rowp[r][o];
     }
@@ -164,12 +165,12 @@ struct VecLoader {
       rowp[i] = base + off_r[rbase + rr[i]];
     }
   }
-  __device__ inline void load(int64_t kt, int64_t K, const GettKLegs& kl, const int64_t* stride) {
-    const int64_t klast = KFAST ? K - VW : K - 1;
+  __device__ inline void load(int64_t kt, int64_t K, const GettKLegs& kl, const uint32_t* stride) {
+    const uint32_t klast = (uint32_t)(KFAST ? K - VW : K - 1);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const int64_t k = kt + kk[i];
-      const int64_t o = k_offset<NKL>((uint32_t)(k < klast ? k : klast), kl, stride);
+      const uint32_t k = (uint32_t)kt + (uint32_t)kk[i];
+      const uint64_t o = k_offset<NKL>(k < klast ? k : klast, kl, stride);
       reg[i] = *reinterpret_cast<const V*>(rowp[i] + o);
     }
   }
@@ -581,17 +582,18 @@ struct Bf16VecLoader {
       rowp[0] = base + off_r[rbase + r0];
     }
   }
-  __device__ inline void load(int64_t kt, int64_t K, const GettKLegs& kl, const int64_t* stride) {
+  __device__ inline void load(int64_t kt, int64_t K, const GettKLegs& kl, const uint32_t* stride) {
     if (KFAST) {
-      const int64_t k = kt + k0;
-      const int64_t o = k_offset<NKL>((uint32_t)(k < K - 4 ? k : K - 4), kl, stride);
+      const uint32_t k = (uint32_t)kt + (uint32_t)k0, klast = (uint32_t)K - 4;
+      const uint64_t o = k_offset<NKL>(k < klast ? k : klast, kl, stride);
 #pragma unroll
       for (int i = 0; i < 4; ++i) reg[i] = *reinterpret_cast<const f32x4*>(rowp[i] + o);
     } else {
+      const uint32_t klast = (uint32_t)K - 1;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int64_t k = kt + k0 + j;
-        const int64_t o = k_offset<NKL>((uint32_t)(k < K ? k : K - 1), kl, stride);
+        const uint32_t k = (uint32_t)kt + (uint32_t)k0 + j;
+        const uint64_t o = k_offset<NKL>(k < klast ? k : klast, kl, stride);
         reg[j] = *reinterpret_cast<const f32x4*>(rowp[0] + o);
       }
     }

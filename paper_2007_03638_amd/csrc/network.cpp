@@ -182,6 +182,9 @@ GettKLegs k_legs(const std::string& prog, const std::string& Kl, const LegDims& 
   if (K >= (int64_t(1) << 31)) throw Error(MERA_EINVAL, prog + ": contracted extent too large");
   GettKLegs kl;
   kl.n = (int)legs.size();
+  for (const Leg& l : legs)
+    if (l.xa < 0 || l.xb < 0 || l.xa >= (int64_t(1) << 32) || l.xb >= (int64_t(1) << 32))
+      throw Error(MERA_EINVAL, prog + ": contracted-leg stride outside 32 bits");
   int64_t below = 1;  // product of the faster extents
   for (int l = 0; l < kl.n; ++l) {
     const uint64_t e = (uint64_t)legs[l].ext;
@@ -191,23 +194,24 @@ GettKLegs k_legs(const std::string& prog, const std::string& Kl, const LegDims& 
       if (qmax * e > (uint64_t(1) << 32)) throw Error(MERA_EINVAL, prog + ": contracted leg too large");
       kl.mag[l] = (uint32_t)(((uint64_t(1) << 32) + e - 1) / e);
     }  // the slowest leg takes the whole remaining quotient: mag 0 (no division)
-    kl.sa[l] = legs[l].xa;
-    kl.sb[l] = legs[l].xb;
+    kl.sa[l] = (uint32_t)legs[l].xa;
+    kl.sb[l] = (uint32_t)legs[l].xb;
     below *= (int64_t)e;
   }
   return kl;
 }
 
-// The kernels' k offset (digit extraction by reciprocal multiplication over NKL legs), on the host.
-int64_t host_k_offset(uint32_t k, const GettKLegs& kl, const int64_t* stride, int nkl) {
-  int64_t off = 0;
+// The kernels' k offset (digit extraction by reciprocal multiplication over NKL legs in 32-bit arithmetic,
+// digit-stride products accumulated in 64 bits), on the host.
+int64_t host_k_offset(uint32_t k, const GettKLegs& kl, const uint32_t* stride, int nkl) {
+  uint64_t off = 0;
   uint32_t q = k;
   for (int l = 0; l + 1 < nkl; ++l) {
     const uint32_t qn = (uint32_t)(((uint64_t)q * kl.mag[l]) >> 32);
-    off += (int64_t)(q - qn * kl.ext[l]) * stride[l];
+    off += (uint64_t)(q - qn * kl.ext[l]) * stride[l];
     q = qn;
   }
-  return off + (int64_t)q * stride[nkl - 1];
+  return (int64_t)(off + (uint64_t)q * stride[nkl - 1]);
 }
 
 // Checks the arithmetic k offsets against the explicit offset tables of A and B, once per planned step.

@@ -46,12 +46,19 @@ def main():
     ap.add_argument("--init", default="", help="initial tensors from an .npz written by --save")
     ap.add_argument("--iter-offset", type=int, default=0, help="iterations already done (with --init)")
     ap.add_argument("--time-limit", type=float, default=0.0, help="stop stepping after this many seconds")
+    ap.add_argument("--krylov-tol", type=float, default=0.0, help="Krylov relative residual (0: default)")
+    ap.add_argument("--precision-check", action="store_true",
+                    help="report the energy of the final point in the run's precision and in FP64")
+    ap.add_argument("--inter-limit-gib", type=float, default=0.0,
+                    help="context intermediate limit in GiB (0: library default, 32)")
     ap.add_argument("--polish-iters", type=int, default=0,
                     help="FP64 iterations from the final point after the run (fresh history)")
     a = ap.parse_args()
 
     from . import api, inputs
     ctx = api.Context(0)
+    if a.inter_limit_gib > 0:
+        ctx.set_intermediate_limit(int(a.inter_limit_gib * (1 << 30)))
     ter = a.geometry == "ternary"
     d = 2 if ter else 4
     dims = api.layer_dims(a.T, a.chi, d, a.geometry)
@@ -68,7 +75,7 @@ def main():
     opt = ctx.optimizer(T=a.T, chi=a.chi, h3=h3, init=init, prec=a.prec, m=a.m, max_iter=a.iters - a.iter_offset,
                         grad_tol=a.grad_tol, polish_tol=a.polish, method=a.method, retraction=a.retraction,
                         grassmann_w=a.grassmann_w, ev_gamma=a.ev_gamma, d=d, geometry=a.geometry,
-                        krylov={"extrapolate": a.extrapolate})
+                        krylov={"extrapolate": a.extrapolate, "tol": a.krylov_tol})
     done, st = False, None
     history = []
     stopped = ""
@@ -87,6 +94,12 @@ def main():
     if a.save:
         np.savez(a.save, *final)
     polish = None
+    check = None
+    if a.precision_check:
+        u, w = final[0::2], final[1::2]
+        e_run = ctx.energy_grad(a.T, a.chi, u, w, h3, prec=a.prec, d=d, geometry=a.geometry)["energy"]
+        e_64 = ctx.energy_grad(a.T, a.chi, u, w, h3, prec="fp64", d=d, geometry=a.geometry)["energy"]
+        check = dict(energy_run_precision=e_run, energy_fp64=e_64, rel_diff=abs(e_run - e_64) / abs(e_64))
     if a.polish_iters > 0:
         u, w = final[0::2], final[1::2]
         e_run = ctx.energy_grad(a.T, a.chi, u, w, h3, prec=a.prec, d=d, geometry=a.geometry)["energy"]
@@ -113,7 +126,7 @@ def main():
                geometry=a.geometry, energy=st["energy"], energy_per_spin=st["energy"] / (1 if ter else 2),
                gnorm=st["gnorm"],
                iterations=st["iterations"] + a.iter_offset, evaluations=st["evaluations"], status=st["status"],
-               stopped=stopped, init=a.init, polish=polish,
+               stopped=stopped, init=a.init, polish=polish, precision_check=check,
                polish_iter=st["polish_iter"], seconds=dt, tflops=2 * st["macs"] / dt / 1e12,
                krylov_applications=st["krylov_applications"],
                krylov_per_eval=st["krylov_applications"] / max(1, st["evaluations"]),

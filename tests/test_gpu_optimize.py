@@ -91,6 +91,26 @@ def test_fp32_polish_reaches_the_fp64_minimum(ctx):
     assert abs(om.energy_only(params, h3, chi, T) - got["energy"]) <= 1e-10 * abs(got["energy"])
 
 
+def test_failed_reduced_precision_line_search_starts_polishing(ctx):
+    """A split-bf16 run at chi = 4 fails a line search early (its energy noise exceeds the Wolfe decrease at
+    |G| ~ 5e-3). With polishing enabled (here only through that path: polish_tol far below any reachable |G|) the
+    run switches to FP64 at that iteration and converges instead of ending with status 2; without polishing it
+    ends there with status 2."""
+    chi, T = 4, 2
+    h3 = model.tfim_h3(1.0)
+    W0 = _init(3, chi, T)
+    got = ctx.run_optimize(T, chi, h3, W0, prec="bf16x3", m=8, max_iter=3000, grad_tol=1e-7, polish_tol=1e-30,
+                           want_final=True)
+    print({k: got[k] for k in ("energy", "gnorm", "iterations", "status", "polish_iter")}, flush=True)
+    assert got["polish_iter"] >= 0 and got["status"] == 0 and got["gnorm"] <= 1e-7
+    W = got["final"]
+    params = [(W[2 * i], W[2 * i + 1]) for i in range(T + 1)]
+    assert abs(om.energy_only(params, h3, chi, T) - got["energy"]) <= 1e-10 * abs(got["energy"])
+    off = ctx.run_optimize(T, chi, h3, W0, prec="bf16x3", m=8, max_iter=3000, grad_tol=1e-7, polish_tol=0.0)
+    assert off["status"] == 2 and off["polish_iter"] == -1
+    assert off["iterations"] == got["polish_iter"]
+
+
 @pytest.mark.parametrize("precondition", [True, False])
 def test_fp64_cg_trajectory_matches_oracle(ctx, precondition):
     """Nonlinear CG (Hager-Zhang coefficient, transported previous direction) against the oracle's CG driver."""
