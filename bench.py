@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--no-group", action="store_true", help="serving: no grouped launches across jobs")
     ap.add_argument("--no-graphs", action="store_true", help="serving: no HIP graph replay")
+    ap.add_argument("--profile-all", action="store_true",
+                    help="time every contraction launch of the run (not only the timed steps) and print the per-variant "
+                         "launch counts, algorithmic flops and bytes to stderr, for comparison with a rocprofv3 trace")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference dispatch for hardware byte counters)")
     return ap.parse_args()
@@ -187,6 +190,9 @@ def run_eval_bench(a):
     dims = api.layer_dims(a.T, a.chi)
     init = [m for pair in inputs.mera_init(a.seed, dims) for m in pair]
     h3 = api.h3_tfim(1.0)
+    all_stats = []
+    if a.profile_all:
+        ctx.profile(True)
     opt = ctx.optimizer(T=a.T, chi=a.chi, h3=h3, init=init, prec=a.prec, m=8, max_iter=10 ** 6, grad_tol=0.0,
                         polish_tol=0.0, precondition=True, max_ls_evals=10)
     state = None
@@ -197,7 +203,7 @@ def run_eval_bench(a):
     # state after the untimed part (with no warmup: the initial evaluation done at creation)
     s0 = state if state is not None else {"evaluations": 1, "macs": ctx.macs(), "krylov_applications": 0}
     ctx.profile(True)
-    ctx.kernel_stats()  # clear
+    all_stats += ctx.kernel_stats()  # clears the records before the timed steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
@@ -207,7 +213,8 @@ def run_eval_bench(a):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = ctx.kernel_stats()
-    ctx.profile(False)
+    all_stats += stats
+    ctx.profile(a.profile_all)
     dt = t1 - t0
     evals = state["evaluations"] - s0["evaluations"]
     macs = state["macs"] - s0["macs"]
@@ -249,6 +256,20 @@ def run_eval_bench(a):
     if a.prec != "fp64":
         out["precision_vs_fp64"] = precision_check(a, ctx, opt, h3)
         print(f"[bench] precision check: {out['precision_vs_fp64']}", file=sys.stderr, flush=True)
+    if a.profile_all:
+        all_stats += ctx.kernel_stats()
+        ctx.profile(False)
+        merged = {}
+        for s in all_stats:
+            m = merged.setdefault(s["kernel"], {"kernel": s["kernel"], "launches": 0, "seconds": 0.0, "flops": 0.0,
+                                                "bytes": 0.0})
+            for k in ("launches", "seconds", "flops", "bytes"):
+                m[k] += s[k]
+        rows = sorted(merged.values(), key=lambda m: -m["seconds"])
+        for m in rows:
+            m["flops_per_launch"] = m["flops"] / m["launches"]
+            m["bytes_per_launch"] = m["bytes"] / m["launches"]
+        print("[bench] all-launch kernel stats: " + json.dumps(rows), file=sys.stderr, flush=True)
     if a.fp64_steps > 0 and a.prec != "fp64":
         r64 = form_rate(a, "fp64", a.fp64_steps, a.fp64_warmup)
         out["fp64_form_evals_per_s"] = r64

@@ -250,7 +250,9 @@ mera_status lbfgs_reset(mera_lbfgs* lb);
 int lbfgs_size(const mera_lbfgs* lb);
 /* Two-loop recursion: dir_out = -H G with H0 = gamma P, P the preconditioner with rho (NULL: identity),
  * gamma = <s,y>/<y,P y> of the newest pair. slope_out (host) = <G, dir_out>. If the result is not a descent
- * direction the history is cleared and dir_out = -P G. */
+ * direction the history is cleared and dir_out = -P G. The object keeps the eigenbases of the last rho: the next
+ * call decomposes its rho in them (Q^T rho Q, a few Jacobi sweeps when rho changed little; every 32nd decomposition
+ * of a factor starts from scratch), as the optimiser does between iterations. */
 mera_status lbfgs_step(mera_ctx* ctx, mera_lbfgs* lb, const mera_mat* W, const mera_mat* G, const mera_mat* rho,
                        mera_mat* dir_out, double* slope_out);
 /* After an accepted step W_new = R_W(d, alpha): transport the stored pairs to W_new, form

@@ -314,6 +314,7 @@ mera_status mera_layer_grad(mera_ctx* ctx, const mera_shape* shape, int layer, c
 
 struct mera_lbfgs {
   mera::Lbfgs lb;
+  mera::Metric met;  // eigenbases of the last preconditioner density matrices (warm starts for the next step)
   int device = 0;
 };
 
@@ -600,14 +601,13 @@ mera_status lbfgs_step(mera_ctx* ctx, mera_lbfgs* lb, const mera_mat* W, const m
     same_shapes(W, G, count, "lbfgs_step");
     same_shapes(W, dir_out, count, "lbfgs_step");
     DeviceGuard g(ctx->c.device);
-    Metric met;
     if (rho) {
       check_mats(rho, count, "lbfgs_step rho");
       for (int i = 0; i < count; ++i)
         MERA_CHECK(rho[i].n == W[i].p && rho[i].p == W[i].p, MERA_EINVAL, "rho must be p x p");
-      met.compute(ctx->c, views(rho, count));
+      lb->met.compute(ctx->c, views(rho, count));
     }
-    *slope_out = lb->lb.step(ctx->c, views(W, count), views(G, count), rho ? &met : nullptr,
+    *slope_out = lb->lb.step(ctx->c, views(W, count), views(G, count), rho ? &lb->met : nullptr,
                              views(dir_out, count));
     ctx->c.sync();
   });

@@ -175,3 +175,54 @@ def test_zero_tangent(ctx):
         assert not np.any(to_np(xo))
     for t in ctx.stiefel_transport(W, Z):
         assert not np.any(to_np(t))
+
+
+# the factor sizes of the chi = 24 and chi = 32 binary MERAs: square disentanglers of 576^2 and 1024^2, isometries
+# 1024 x 32 and 576 x 24, and a ternary isometry 13824 x 24
+FULL = [(576, 576), (1024, 1024), (1024, 32), (576, 24), (13824, 24)]
+
+
+def _full(seed):
+    return [inputs.haar_params(seed + i, [s])[0] for i, s in enumerate(FULL)]
+
+
+@pytest.mark.parametrize("alpha", [0.37, 2.0])
+def test_retract_and_transport_full_size(ctx, alpha):
+    W = _full(60)
+    X = [mf.project(w, d) / np.linalg.norm(d) for w, d in zip(W, inputs.normal_like(61, W))]
+    Wo, Xo = ctx.stiefel_retract(W, X, alpha)
+    Wo = [to_np(x) for x in Wo]
+    for w, x, wo, xo in zip(W, X, Wo, Xo):
+        rw, rx = mf.retract(w, x, alpha)
+        xo = to_np(xo)
+        orth = np.max(np.abs(wo.T @ wo - np.eye(w.shape[1])))
+        print(f"full retract {w.shape} alpha={alpha}: W {rel(wo, rw):.2e} X' {rel(xo, rx):.2e} orth {orth:.2e}",
+              flush=True)
+        assert orth < 1e-13
+        assert rel(wo, rw) < 1e-12
+        assert rel(xo, rx) < 1e-10
+    Y = [mf.project(w, y) for w, y in zip(W, inputs.normal_like(62, W))]
+    T = ctx.stiefel_transport(Wo, Y)
+    for wn, y, t in zip(Wo, Y, T):
+        assert rel(to_np(t), mf.transport(wn, y)) < 1e-13
+
+
+def test_preconditioner_full_size_with_warm_eigenbasis(ctx):
+    """The preconditioned direction of the two-loop (empty history: d = -P G) for the full-size factors, first with
+    a cold Jacobi decomposition of each rho (p = 576, 1024, 32, 24, 24), then with rho changed a little, decomposed
+    in the kept eigenbasis (the optimiser's warm start); both against the oracle's eigh-based preconditioner."""
+    W = _full(70)
+    G = [mf.project(w, d) for w, d in zip(W, inputs.normal_like(71, W))]
+    rho1 = [inputs.density_matrix(72 + i, w.shape[1]) + 1e-3 * np.eye(w.shape[1]) / w.shape[1]
+            for i, w in enumerate(W)]
+    pert = [inputs.symmetric_operator(80 + i, w.shape[1]) for i, w in enumerate(W)]
+    rho2 = [r + 1e-3 * np.max(np.abs(r)) * q / np.max(np.abs(q)) for r, q in zip(rho1, pert)]
+    lb = ctx.lbfgs(FULL, m=4)
+    for tag, rho in (("cold", rho1), ("warm", rho2)):
+        d, slope = lb.step(W, G, rho)
+        ref = [-mf.precondition(w, g, r) for w, g, r in zip(W, G, rho)]
+        for w, a, b in zip(W, d, ref):
+            err = rel(to_np(a), b)
+            print(f"precondition {tag} {w.shape}: {err:.2e}", flush=True)
+            assert err < 1e-10
+        assert abs(slope - mf.inner(G, ref)) <= 1e-10 * abs(mf.inner(G, ref))
