@@ -1,4 +1,4 @@
-"""Builds the HIP library libmera_hip.so in place (hipcc, gfx950) and, when present, the oracle's C helpers.
+"""Builds the HIP library libmera_hip.so in place (hipcc, gfx950).
 
 Usage: python -m paper_2007_03638_amd.build  (or build() from Python). Always recompiles.
 """
