@@ -558,7 +558,9 @@ struct KStat {
 };
 
 // Restarted GMRES(m) for op(x) = b, starting from x (in/out). Vectors of length n in precision `prec`,
-// scalars in FP64; classical Gram-Schmidt applied twice; restart residual from the Arnoldi relation.
+// scalars in FP64; classical Gram-Schmidt applied twice; restart residual from the Arnoldi relation. Within an
+// Arnoldi step the projection coefficients and the new vector's norm stay in device memory (the operator, too,
+// must not synchronise); one copy to the host per step brings them back for the Hessenberg matrix.
 KStat gmres(Ctx& ctx, const std::function<void(VPtr, VPtr)>& op, VPtr b, VPtr x, int64_t n, int m, double tol,
             int max_restarts, Prec prec) {
   KStat st;
@@ -578,7 +580,13 @@ KStat gmres(Ctx& ctx, const std::function<void(VPtr, VPtr)>& op, VPtr b, VPtr x,
   axpby(ctx, 1.0, b, -1.0, V[0], n);  // V0 = b - A x
   double beta = nrm2(ctx, V[0], n);
   MERA_CHECK(std::isfinite(beta), MERA_ENONFINITE, "non-finite residual in Krylov solve");
-  std::vector<double> H((m + 1) * m), Hr((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hcol(m + 1);
+  std::vector<double> H((m + 1) * m), Hr((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  // device scalars of one Arnoldi step: two passes of projection coefficients, the norm, a work slot
+  double* dsc = static_cast<double*>(ctx.buf("krylov.scalars", (size_t)(2 * (m + 1) + 2) * sizeof(double)));
+  double* dh1 = dsc;
+  double* dh2 = dsc + (m + 1);
+  double* dhn = dsc + 2 * (m + 1);
+  std::vector<double> hsc(2 * (m + 1) + 2);
   for (int restart = 0; restart <= max_restarts; ++restart) {
     st.res = beta / bnorm;
     if (beta <= tol * bnorm) {
@@ -595,18 +603,20 @@ KStat gmres(Ctx& ctx, const std::function<void(VPtr, VPtr)>& op, VPtr b, VPtr x,
       op(V[j], V[j + 1]);
       st.apps++;
       // classical Gram-Schmidt, twice: each pass is one fused projection onto V_0..V_j and one fused update
-      for (int pass = 0; pass < 2; ++pass) {
-        multi_dot(ctx, V.data(), j + 1, V[j + 1], n, hcol.data());
-        for (int i = 0; i <= j; ++i) {
-          H[i * m + j] += hcol[i];
-          hcol[i] = -hcol[i];
-        }
-        multi_axpby(ctx, V.data(), hcol.data(), j + 1, 1.0, V[j + 1], n);
+      multi_dot_dev(ctx, V.data(), j + 1, V[j + 1], n, dh1);
+      multi_axpby_dev(ctx, V.data(), dh1, -1.0, j + 1, 1.0, V[j + 1], n);
+      multi_dot_dev(ctx, V.data(), j + 1, V[j + 1], n, dh2);
+      multi_axpby_dev(ctx, V.data(), dh2, -1.0, j + 1, 1.0, V[j + 1], n);
+      normalize_dev(ctx, V[j + 1], n, dhn, dhn + 1);
+      MERA_HIP(hipMemcpyAsync(hsc.data(), dsc, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+      ctx.sync();
+      for (int i = 0; i <= j; ++i) {
+        H[i * m + j] += hsc[i];
+        H[i * m + j] += hsc[(m + 1) + i];
       }
-      double hn = nrm2(ctx, V[j + 1], n);
+      const double hn = hsc[2 * (m + 1)];
       MERA_CHECK(std::isfinite(hn), MERA_ENONFINITE, "non-finite Krylov vector");
       H[(j + 1) * m + j] = hn;
-      if (hn > 0.0) scal(ctx, 1.0 / hn, V[j + 1], n);
       // rotated copy for the least-squares solve
       for (int i = 0; i <= j + 1; ++i) Hr[i * m + j] = H[i * m + j];
       for (int i = 0; i < j; ++i) {
@@ -816,9 +826,6 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
         extrap = std::isfinite(theta) && theta != 0.0;
       }
     }
-    std::swap(warm->pts[0], warm->pts[1]);
-    copy(ctx, VPtr{warm->pts[0].ptr, Prec::F64}, VPtr{cur, Prec::F64}, ne);
-    warm->npts = std::min(2, warm->npts + 1);
   }
 
   const double tol = ko.tol > 0 ? ko.tol : (prec == Prec::F64 ? 1e-13 : 1e-7);
@@ -842,10 +849,12 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
     add_diag(ctx, rho, chi3, 1.0 / (double)chi3);
   }
   copy(ctx, sigma, rho, n6);
+  double* opsc = static_cast<double*>(ctx.buf("krylov.opscalar", sizeof(double)));
   auto op_rho = [&](VPtr in, VPtr o) {
     descend_raw(ctx, S, lt[T], in, o, prec);
     axpby(ctx, 1.0, in, -1.0, o, n6);
-    axpby(ctx, trace(ctx, in, chi3), sigma, 1.0, o, n6);
+    trace_dev(ctx, in, chi3, opsc);
+    axpby_dev(ctx, opsc, 1.0, sigma, 1.0, o, n6);
   };
   KStat kr = gmres(ctx, op_rho, sigma, rho, n6, kdim, tol, kres, prec);
   MERA_CHECK(kr.converged, MERA_ENOCONV,
@@ -880,7 +889,8 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
   auto op_ht = [&](VPtr in, VPtr o) {
     ascend_raw(ctx, S, lt[T], in, o, prec);
     axpby(ctx, 1.0, in, -1.0, o, n6);
-    add_diag(ctx, o, chi3, dot(ctx, in, rho, n6));
+    dot_dev(ctx, in, rho, n6, opsc);
+    add_diag_dev(ctx, o, chi3, opsc, 1.0);
   };
   KStat kh = gmres(ctx, op_ht, hp, ht, n6, kdim, tol, kres, prec);
   MERA_CHECK(kh.converged, MERA_ENOCONV, "h~ solve did not converge (residual " + std::to_string(kh.res) + ")");
@@ -904,6 +914,13 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
     copy(ctx, VPtr{warm->rho.ptr, Prec::F64}, rho, n6);
     copy(ctx, VPtr{warm->ht.ptr, Prec::F64}, ht, n6);
     warm->has_rho = warm->has_ht = true;
+    if (ko.extrapolate) {
+      // this point joins the history only with its solutions, so points and solutions stay paired even when an
+      // evaluation fails before this
+      std::swap(warm->pts[0], warm->pts[1]);
+      copy(ctx, VPtr{warm->pts[0].ptr, Prec::F64}, VPtr{ctx.buf("warm.cur", 0), Prec::F64}, warm->pt_elems);
+      warm->npts = std::min(2, warm->npts + 1);
+    }
   }
 
   // gradients, top down; rl[t] = density matrix at the top of layer t (rl[T] = rho_s)

@@ -31,6 +31,18 @@ void symmetrize(Ctx& ctx, VPtr x, int64_t dim);
 void add_diag(Ctx& ctx, VPtr x, int64_t dim, double c);
 double trace(Ctx& ctx, VPtr x, int64_t dim);                   // syncs
 
+// The same reductions and updates with FP64 scalars that stay in device memory (no host synchronisation): results
+// are written to, and coefficients read from, device addresses; s scales a coefficient read from the device.
+void dot_dev(Ctx& ctx, VPtr x, VPtr y, int64_t n, double* out_dev);                       // *out = <x, y>
+void trace_dev(Ctx& ctx, VPtr x, int64_t dim, double* out_dev);                           // *out = Tr X
+void axpby_dev(Ctx& ctx, const double* a_dev, double s, VPtr x, double b, VPtr y, int64_t n);  // y = s*a x + b y
+void add_diag_dev(Ctx& ctx, VPtr x, int64_t dim, const double* c_dev, double s);          // X_ii += s*c
+void multi_dot_dev(Ctx& ctx, const VPtr* v, int k, VPtr w, int64_t n, double* out_dev);    // out[j] = <w, v_j>
+// y <- b y + sum_j (s c[j]) v_j
+void multi_axpby_dev(Ctx& ctx, const VPtr* v, const double* c_dev, double s, int k, double b, VPtr y, int64_t n);
+// *nrm = |x|, then x <- x / |x| when |x| > 0 (work_dev: one double of scratch)
+void normalize_dev(Ctx& ctx, VPtr x, int64_t n, double* nrm_dev, double* work_dev);
+
 // Symmetric eigendecomposition of a dim x dim FP64 matrix (row-major, device) by cyclic two-sided Jacobi
 // rotations in tournament order: A = V diag(lam) V^T, eigenvectors in the columns of V. `a` is overwritten.
 // v_init: v holds an orthogonal basis Q on entry and a = Q^T A Q; the rotations are then accumulated onto Q, so

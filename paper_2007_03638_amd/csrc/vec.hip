@@ -105,6 +105,52 @@ __global__ void multi_axpby_kernel(VecList<T> L, int k, double b, T* __restrict_
   }
 }
 
+// y <- b y + sum_j (s c[j]) v_j with the coefficients read from device memory.
+template <typename T>
+__global__ void multi_axpby_dev_kernel(VecList<T> L, int k, const double* __restrict__ c, double s, double b,
+                                       T* __restrict__ y, int64_t n) {
+  double cj[kMulti];
+#pragma unroll
+  for (int j = 0; j < kMulti; ++j) cj[j] = (j < k) ? s * c[j] : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double t = (b != 0.0) ? b * (double)y[i] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kMulti; ++j)
+      if (j < k) t += cj[j] * (double)L.v[j][i];
+    y[i] = (T)t;
+  }
+}
+
+// y = (s a) x + b y with a read from device memory.
+template <typename TX, typename TY>
+__global__ void axpby_dev_kernel(const double* __restrict__ a, double s, const TX* __restrict__ x, double b,
+                                 TY* __restrict__ y, int64_t n) {
+  const double av = s * a[0];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v = av * (double)x[i];
+    if (b != 0.0) v += b * (double)y[i];
+    y[i] = (TY)v;
+  }
+}
+
+template <typename T>
+__global__ void add_diag_dev_kernel(T* x, int64_t dim, const double* __restrict__ c, double s) {
+  const double cv = s * c[0];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += (int64_t)gridDim.x * blockDim.x)
+    x[i * dim + i] = (T)((double)x[i * dim + i] + cv);
+}
+
+// nrm[0] = sqrt(sum of the squares in sq[0]); x <- x / nrm[0] when positive (one thread writes nrm)
+template <typename T>
+__global__ void normalize_dev_kernel(T* x, int64_t n, const double* __restrict__ sq, double* __restrict__ nrm) {
+  const double hn = sqrt(sq[0]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) nrm[0] = hn;
+  if (!(hn > 0.0)) return;
+  const double a = 1.0 / hn;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (T)(a * (double)x[i]);
+}
+
 template <typename T>
 VecList<T> vec_list(const VPtr* v, const double* c, int k) {
   VecList<T> L{};
@@ -608,6 +654,120 @@ double trace(Ctx& ctx, VPtr x, int64_t dim) {
                        ctx.red.as<double>());
   MERA_HIP(hipGetLastError());
   return finish_partials(ctx, blocks);
+}
+
+// ---- device-resident scalars ----------------------------------------------------------------------------
+
+void dot_dev(Ctx& ctx, VPtr x, VPtr y, int64_t n, double* out_dev) {
+  ctx.red.ensure(RED_BLOCKS * sizeof(double));
+  const int blocks = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + TPB - 1) / TPB));
+  double* part = ctx.red.as<double>();
+  if (x.dbl() && y.dbl())
+    hipLaunchKernelGGL((dot_kernel<double, double>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const double*)x.p, (const double*)y.p, n, part);
+  else if (x.dbl())
+    hipLaunchKernelGGL((dot_kernel<double, float>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const double*)x.p, (const float*)y.p, n, part);
+  else if (y.dbl())
+    hipLaunchKernelGGL((dot_kernel<float, double>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const float*)x.p, (const double*)y.p, n, part);
+  else
+    hipLaunchKernelGGL((dot_kernel<float, float>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const float*)x.p, (const float*)y.p, n, part);
+  MERA_HIP(hipGetLastError());
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, ctx.stream, (const double*)part, blocks, out_dev);
+  MERA_HIP(hipGetLastError());
+}
+
+void trace_dev(Ctx& ctx, VPtr x, int64_t dim, double* out_dev) {
+  ctx.red.ensure(RED_BLOCKS * sizeof(double));
+  const int blocks = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (dim + TPB - 1) / TPB));
+  double* part = ctx.red.as<double>();
+  if (x.dbl())
+    hipLaunchKernelGGL(trace_kernel<double>, dim3(blocks), dim3(TPB), 0, ctx.stream, (const double*)x.p, dim, part);
+  else
+    hipLaunchKernelGGL(trace_kernel<float>, dim3(blocks), dim3(TPB), 0, ctx.stream, (const float*)x.p, dim, part);
+  MERA_HIP(hipGetLastError());
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, ctx.stream, (const double*)part, blocks, out_dev);
+  MERA_HIP(hipGetLastError());
+}
+
+void axpby_dev(Ctx& ctx, const double* a_dev, double s, VPtr x, double b, VPtr y, int64_t n) {
+  const int g = grid_for(n);
+  if (x.dbl() && y.dbl())
+    hipLaunchKernelGGL((axpby_dev_kernel<double, double>), dim3(g), dim3(TPB), 0, ctx.stream, a_dev, s,
+                       (const double*)x.p, b, (double*)y.p, n);
+  else if (x.dbl())
+    hipLaunchKernelGGL((axpby_dev_kernel<double, float>), dim3(g), dim3(TPB), 0, ctx.stream, a_dev, s,
+                       (const double*)x.p, b, (float*)y.p, n);
+  else if (y.dbl())
+    hipLaunchKernelGGL((axpby_dev_kernel<float, double>), dim3(g), dim3(TPB), 0, ctx.stream, a_dev, s,
+                       (const float*)x.p, b, (double*)y.p, n);
+  else
+    hipLaunchKernelGGL((axpby_dev_kernel<float, float>), dim3(g), dim3(TPB), 0, ctx.stream, a_dev, s,
+                       (const float*)x.p, b, (float*)y.p, n);
+  MERA_HIP(hipGetLastError());
+}
+
+void add_diag_dev(Ctx& ctx, VPtr x, int64_t dim, const double* c_dev, double s) {
+  const int g = grid_for(dim);
+  if (x.dbl())
+    hipLaunchKernelGGL(add_diag_dev_kernel<double>, dim3(g), dim3(TPB), 0, ctx.stream, (double*)x.p, dim, c_dev, s);
+  else
+    hipLaunchKernelGGL(add_diag_dev_kernel<float>, dim3(g), dim3(TPB), 0, ctx.stream, (float*)x.p, dim, c_dev, s);
+  MERA_HIP(hipGetLastError());
+}
+
+void multi_dot_dev(Ctx& ctx, const VPtr* v, int k, VPtr w, int64_t n, double* out_dev) {
+  for (int j = 0; j < k; ++j)
+    MERA_CHECK(v[j].dbl() == w.dbl(), MERA_EINVAL, "multi_dot: vectors of different precisions");
+  const int blocks = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + TPB - 1) / TPB));
+  ctx.red.ensure((size_t)kMulti * blocks * sizeof(double));
+  double* part = ctx.red.as<double>();
+  for (int j0 = 0; j0 < k; j0 += kMulti) {
+    const int kk = std::min(kMulti, k - j0);
+    if (w.dbl())
+      hipLaunchKernelGGL(multi_dot_kernel<double>, dim3(blocks), dim3(TPB), 0, ctx.stream,
+                         vec_list<double>(v + j0, nullptr, kk), kk, (const double*)w.p, n, part);
+    else
+      hipLaunchKernelGGL(multi_dot_kernel<float>, dim3(blocks), dim3(TPB), 0, ctx.stream,
+                         vec_list<float>(v + j0, nullptr, kk), kk, (const float*)w.p, n, part);
+    MERA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(kk), dim3(64), 0, ctx.stream, (const double*)part, blocks,
+                       out_dev + j0);
+    MERA_HIP(hipGetLastError());
+  }
+}
+
+void multi_axpby_dev(Ctx& ctx, const VPtr* v, const double* c_dev, double s, int k, double b, VPtr y, int64_t n) {
+  for (int j = 0; j < k; ++j) {
+    MERA_CHECK(v[j].dbl() == y.dbl(), MERA_EINVAL, "multi_axpby: vectors of different precisions");
+    MERA_CHECK(v[j].p != y.p, MERA_EINVAL, "multi_axpby: output aliases an input");
+  }
+  const int g = grid_for(n);
+  for (int j0 = 0; j0 < k; j0 += kMulti) {
+    const int kk = std::min(kMulti, k - j0);
+    const double bb = j0 == 0 ? b : 1.0;
+    if (y.dbl())
+      hipLaunchKernelGGL(multi_axpby_dev_kernel<double>, dim3(g), dim3(TPB), 0, ctx.stream,
+                         vec_list<double>(v + j0, nullptr, kk), kk, c_dev + j0, s, bb, (double*)y.p, n);
+    else
+      hipLaunchKernelGGL(multi_axpby_dev_kernel<float>, dim3(g), dim3(TPB), 0, ctx.stream,
+                         vec_list<float>(v + j0, nullptr, kk), kk, c_dev + j0, s, bb, (float*)y.p, n);
+    MERA_HIP(hipGetLastError());
+  }
+}
+
+void normalize_dev(Ctx& ctx, VPtr x, int64_t n, double* nrm_dev, double* work_dev) {
+  dot_dev(ctx, x, x, n, work_dev);
+  const int g = grid_for(n);
+  if (x.dbl())
+    hipLaunchKernelGGL(normalize_dev_kernel<double>, dim3(g), dim3(TPB), 0, ctx.stream, (double*)x.p, n,
+                       (const double*)work_dev, nrm_dev);
+  else
+    hipLaunchKernelGGL(normalize_dev_kernel<float>, dim3(g), dim3(TPB), 0, ctx.stream, (float*)x.p, n,
+                       (const double*)work_dev, nrm_dev);
+  MERA_HIP(hipGetLastError());
 }
 
 void jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol, int max_sweeps, bool v_init) {

@@ -94,12 +94,13 @@ def test_gradient_directional_derivative_chi16(ctx):
 
 def test_fp32_energy_matches_fp64_chi16(ctx):
     """FP32 and split-bf16 energies against the FP64 path (itself the oracle's to 1e-12 in the parity tests) at the
-    size of the FP64 configuration (chi = 16, T = 3), relative to the energy, at a point near the identity (energy
-    far from zero; a Haar-random MERA's energy is near zero): FP32 within 1e-6, split-bf16 within 1e-5."""
+    size of the FP64 configuration (chi = 16, T = 3), relative to the energy, at a point near the identity (near the
+    product state of energy -2 per blocked site, far from zero; a Haar-random MERA's energy is near zero): FP32 within
+    1e-6, split-bf16 within 1e-5."""
     from paper_2007_03638_amd import api
     T, chi = 3, 16
     dims = om.layer_dims(chi, T)
-    params = inputs.mera_init_near_identity(1, dims, 0.1)
+    params = inputs.mera_init_near_identity(1, dims, 0.02)
     h3 = api.h3_tfim(1.0)
     u = [p[0] for p in params]
     w = [p[1] for p in params]
@@ -107,6 +108,6 @@ def test_fp32_energy_matches_fp64_chi16(ctx):
     e32 = ctx.energy_grad(T, chi, u, w, h3, prec="fp32")["energy"]
     eb = ctx.energy_grad(T, chi, u, w, h3, prec="bf16x3")["energy"]
     print(f"chi=16 energy fp64 {e64:.15e} fp32 {e32:.15e} bf16x3 {eb:.15e}", flush=True)
-    assert abs(e64) > 0.1
+    assert abs(e64) > 1.0
     assert abs(e32 - e64) <= 1e-6 * abs(e64)
     assert abs(eb - e64) <= 1e-5 * abs(e64)
