@@ -98,6 +98,10 @@ int mera_ctx_kernel_stats(mera_ctx* ctx, mera_kernel_stat* out, int cap);
  * 2 (2 a^6 + a^4 b^2 + a^2 b^4) elements per layer, fits; results equal up to rounding order either way). */
 mera_status mera_ctx_set_intermediate_limit(mera_ctx* ctx, size_t bytes);
 
+/* Progress reports on stderr: level > 0 prints a line at every restart of the two Krylov solves of an evaluation
+ * (applications so far, relative residual); 0 (default) prints nothing. For long evaluations at large chi. */
+mera_status mera_ctx_set_verbose(mera_ctx* ctx, int level);
+
 /* Layer dimensions: a_out[0..T], b_out[0..T] (host arrays of T+1 ints). */
 mera_status mera_layer_dims(const mera_shape* shape, int* a_out, int* b_out);
 

@@ -66,6 +66,7 @@ SIGNATURES = {
     "mera_ctx_trim": (c_int, [c_void_p]),
     "mera_ctx_macs": (c_double, [c_void_p]),
     "mera_ctx_set_intermediate_limit": (c_int, [c_void_p, c_size_t]),
+    "mera_ctx_set_verbose": (c_int, [c_void_p, c_int]),
     "mera_layer_dims": (c_int, [ctypes.POINTER(MeraShape), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "mera_h3_tfim": (c_int, [c_double, ctypes.POINTER(c_double)]),
     "mera_h3_xxz": (c_int, [c_double, ctypes.POINTER(c_double)]),

@@ -139,6 +139,9 @@ class Context:
     def set_intermediate_limit(self, nbytes):
         self._check(self._lib.mera_ctx_set_intermediate_limit(self.ptr, int(nbytes)), "mera_ctx_set_intermediate_limit")
 
+    def set_verbose(self, level=1):
+        self._check(self._lib.mera_ctx_set_verbose(self.ptr, int(level)), "mera_ctx_set_verbose")
+
     def profile(self, enable=True):
         self._check(self._lib.mera_ctx_profile(self.ptr, 1 if enable else 0), "mera_ctx_profile")
 

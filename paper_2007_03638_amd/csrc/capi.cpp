@@ -135,6 +135,12 @@ mera_status mera_ctx_trim(mera_ctx* ctx) {
 
 double mera_ctx_macs(const mera_ctx* ctx) { return ctx ? ctx->c.macs : 0.0; }
 
+mera_status mera_ctx_set_verbose(mera_ctx* ctx, int level) {
+  if (!ctx) return MERA_EINVAL;
+  ctx->c.verbose = level;
+  return MERA_OK;
+}
+
 mera_status mera_ctx_set_intermediate_limit(mera_ctx* ctx, size_t bytes) {
   if (!ctx || bytes == 0) return MERA_EINVAL;
   ctx->c.inter_limit = bytes;

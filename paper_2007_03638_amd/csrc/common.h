@@ -95,6 +95,7 @@ struct Ctx {
   DevBuf red;        // reduction partials (doubles)
   size_t inter_limit = (size_t)32 << 30;  // largest 7-leg intermediate built in one piece (bytes)
   bool profiling = false;
+  int verbose = 0;  // > 0: Krylov solves report each restart on stderr
   std::vector<LaunchRecord> records;
   std::vector<hipEvent_t> event_pool;
   hipEvent_t take_event() {

@@ -562,7 +562,7 @@ struct KStat {
 // Arnoldi step the projection coefficients and the new vector's norm stay in device memory (the operator, too,
 // must not synchronise); one copy to the host per step brings them back for the Hessenberg matrix.
 KStat gmres(Ctx& ctx, const std::function<void(VPtr, VPtr)>& op, VPtr b, VPtr x, int64_t n, int m, double tol,
-            int max_restarts, Prec prec) {
+            int max_restarts, Prec prec, const char* label) {
   KStat st;
   const size_t bytes = (size_t)n * elem_bytes(prec);
   std::vector<VPtr> V(m + 1);
@@ -589,6 +589,11 @@ KStat gmres(Ctx& ctx, const std::function<void(VPtr, VPtr)>& op, VPtr b, VPtr x,
   std::vector<double> hsc(2 * (m + 1) + 2);
   for (int restart = 0; restart <= max_restarts; ++restart) {
     st.res = beta / bnorm;
+    if (ctx.verbose > 0) {
+      std::fprintf(stderr, "[mera] %s solve: restart %d, %d applications, relative residual %.3e\n", label, restart,
+                   st.apps, st.res);
+      std::fflush(stderr);
+    }
     if (beta <= tol * bnorm) {
       st.converged = true;
       break;
@@ -856,7 +861,7 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
     trace_dev(ctx, in, chi3, opsc);
     axpby_dev(ctx, opsc, 1.0, sigma, 1.0, o, n6);
   };
-  KStat kr = gmres(ctx, op_rho, sigma, rho, n6, kdim, tol, kres, prec);
+  KStat kr = gmres(ctx, op_rho, sigma, rho, n6, kdim, tol, kres, prec, "fixed-point");
   MERA_CHECK(kr.converged, MERA_ENOCONV,
              "fixed-point solve did not converge (residual " + std::to_string(kr.res) + ")");
   symmetrize(ctx, rho, chi3);
@@ -892,7 +897,7 @@ EvalOut energy_grad(Ctx& ctx, const mera_shape& shape, const Point& pt, const do
     dot_dev(ctx, in, rho, n6, opsc);
     add_diag_dev(ctx, o, chi3, opsc, 1.0);
   };
-  KStat kh = gmres(ctx, op_ht, hp, ht, n6, kdim, tol, kres, prec);
+  KStat kh = gmres(ctx, op_ht, hp, ht, n6, kdim, tol, kres, prec, "h~");
   MERA_CHECK(kh.converged, MERA_ENOCONV, "h~ solve did not converge (residual " + std::to_string(kh.res) + ")");
   symmetrize(ctx, ht, chi3);
   add_diag(ctx, ht, chi3, -dot(ctx, ht, rho, n6));  // gauge Tr[h~ rho] = 0

@@ -57,6 +57,8 @@ def main():
 
     from . import api, inputs
     ctx = api.Context(0)
+    if a.progress:
+        ctx.set_verbose(1)
     if a.inter_limit_gib > 0:
         ctx.set_intermediate_limit(int(a.inter_limit_gib * (1 << 30)))
     ter = a.geometry == "ternary"
