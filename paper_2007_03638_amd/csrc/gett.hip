@@ -409,6 +409,19 @@ __device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
+// The same split for two elements: one packed conversion gives both hi values, whose FP32 values are the packed
+// word's halves moved to the top 16 bits (the subtraction is exact), then one packed conversion of the two lo.
+// The empty asm statement (no instruction) hides the packed word's origin from the optimiser, which would
+// otherwise convert x0 a second time to rebuild its FP32 hi.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ inline void split_bf16x2(float x0, float x1, bf16x2& hi, bf16x2& lo) {
+  uint32_t hb = __builtin_bit_cast(uint32_t, bf16x2{(__bf16)x0, (__bf16)x1});
+  __asm__("" : "+v"(hb));
+  hi = __builtin_bit_cast(bf16x2, hb);
+  const float h0 = __uint_as_float(hb << 16), h1 = __uint_as_float(hb & 0xffff0000u);
+  lo = bf16x2{(__bf16)(x0 - h0), (__bf16)(x1 - h1)};
+}
+
 // Epilogue of the split-bf16 kernels: 16 x 16 accumulator blocks (acc[i] -> row 4 (lane / 16) + i, col lane % 16),
 // written as split-K partials or as C = alpha acc + beta C through the C offset tables.
 template <int FM, int FN>
@@ -558,10 +571,14 @@ __global__ void __launch_bounds__(256) gett_bf16x3_kernel(Args g) {
 }
 
 // Split-bf16 form with 16-byte tile loads (both operands' layouts allow them): 128 x 128 tiles, BK = 32, each
-// thread loading four 4-element vectors per operand and tile. A k-walking operand's vector is 4 consecutive k of
-// one row; a row-walking operand's four vectors are the same 4 rows at 4 consecutive k, transposed in registers.
-// Either way a thread stages 4 k of a row at a time: split into hi and lo and written as one 8-byte LDS store per
-// plane (planes row-major with k contiguous, pitch BK + 8, as in the kernel above).
+// thread loading four 4-element vectors per operand and tile. Thread t owns rows 4 (t / 8) .. 4 (t / 8) + 3 and
+// k 4 (t % 8) .. 4 (t % 8) + 3 of the tile. A k-walking operand's vector is 4 consecutive k of one row; a
+// row-walking operand's four vectors are the same 4 rows at 4 consecutive k, transposed in registers. Either way a
+// thread stages 4 k of a row at a time: split into hi and lo and written as one 8-byte LDS store per plane (planes
+// row-major with k contiguous, pitch BK + 8, as in the kernel above). Eight consecutive lanes fill 64 contiguous
+// bytes of one row and the next eight lanes start 4 rows (80 dwords) further, so the stores of 32 lanes cover 64
+// distinct banks; with the older assignment (a row-walking thread on rows 4 (t % 32) ..) 32 lanes wrote 4 rows
+// apart at one k, all into 4 bank pairs, and the kernel spent over a third of its wave cycles waiting on LDS.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 template <bool KFAST, int NKL>
 struct Bf16VecLoader {
@@ -571,31 +588,28 @@ struct Bf16VecLoader {
   f32x4 reg[4];
 
   __device__ inline void init(const float* base, const int64_t* off_r, int64_t rbase, int tid) {
+    r0 = 4 * (tid / 8);  // rows r0 .. r0 + 3
+    k0 = 4 * (tid % 8);
     if (KFAST) {
-      r0 = tid / 8;  // rows r0 + 32 i
-      k0 = 4 * (tid % 8);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) rowp[i] = base + off_r[rbase + r0 + 32 * i];
+      for (int i = 0; i < 4; ++i) rowp[i] = base + off_r[rbase + r0 + i];
     } else {
-      r0 = 4 * (tid % 32);  // rows r0 .. r0 + 3
-      k0 = 4 * (tid / 32);
       rowp[0] = base + off_r[rbase + r0];
     }
   }
+  // The fastest contracted leg's extent is a multiple of 4 (required by the launch), and kt + k0 is one too, so
+  // the thread's 4 k's differ only in that leg's digit: one offset, then steps of that leg's stride.
   __device__ inline void load(int64_t kt, int64_t K, const GettKLegs& kl, const uint32_t* stride) {
+    const uint32_t k = (uint32_t)kt + (uint32_t)k0, klast = (uint32_t)K - 4;
+    const uint64_t o = k_offset<NKL>(k < klast ? k : klast, kl, stride);
     if (KFAST) {
-      const uint32_t k = (uint32_t)kt + (uint32_t)k0, klast = (uint32_t)K - 4;
-      const uint64_t o = k_offset<NKL>(k < klast ? k : klast, kl, stride);
 #pragma unroll
       for (int i = 0; i < 4; ++i) reg[i] = *reinterpret_cast<const f32x4*>(rowp[i] + o);
     } else {
-      const uint32_t klast = (uint32_t)K - 1;
+      const float* p = rowp[0] + o;
+      const uint64_t s0 = stride[0];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t k = (uint32_t)kt + (uint32_t)k0 + j;
-        const uint64_t o = k_offset<NKL>(k < klast ? k : klast, kl, stride);
-        reg[j] = *reinterpret_cast<const f32x4*>(rowp[0] + o);
-      }
+      for (int j = 0; j < 4; ++j) reg[j] = *reinterpret_cast<const f32x4*>(p + j * s0);
     }
   }
   // stages the tile starting at kt; KMASK: zero past kend
@@ -603,17 +617,17 @@ struct Bf16VecLoader {
   __device__ inline void store(__bf16* hi, __bf16* lo, int64_t kt, int64_t kend) const {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      bf16x4 h, l;
+      float x[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        float x = KFAST ? reg[i][j] : reg[j][i];
-        if (KMASK && kt + k0 + j >= kend) x = 0.f;
-        __bf16 a, b;
-        split_bf16(x, a, b);
-        h[j] = a;
-        l[j] = b;
+        x[j] = KFAST ? reg[i][j] : reg[j][i];
+        if (KMASK && kt + k0 + j >= kend) x[j] = 0.f;
       }
-      const int row = KFAST ? r0 + 32 * i : r0 + i;
+      bf16x2 h01, l01, h23, l23;
+      split_bf16x2(x[0], x[1], h01, l01);
+      split_bf16x2(x[2], x[3], h23, l23);
+      const bf16x4 h{h01[0], h01[1], h23[0], h23[1]}, l{l01[0], l01[1], l23[0], l23[1]};
+      const int row = r0 + i;
       *reinterpret_cast<bf16x4*>(&hi[row * LDK + k0]) = h;
       *reinterpret_cast<bf16x4*>(&lo[row * LDK + k0]) = l;
     }
@@ -877,7 +891,8 @@ void gett_run(Ctx& ctx, const GettTables& t, const GettLaunch& l) {
   bool vec = t.a_vw >= vw && t.b_vw >= vw;
   for (int g = 0; g < G; ++g)
     vec = vec && ((uintptr_t)l.A[g] % 16 == 0) && ((uintptr_t)l.B[g] % 16 == 0);
-  if (l.prec == Prec::BF16X3) vec = vec && BMsel == 128 && BNsel == 128;  // the vector split-bf16 kernel's tile
+  // the vector split-bf16 kernel's tile; its loads take 4 consecutive k within the fastest contracted leg
+  if (l.prec == Prec::BF16X3) vec = vec && BMsel == 128 && BNsel == 128 && t.kl.n >= 1 && t.kl.ext[0] % 4 == 0;
   hipStream_t s = ctx.stream;
   LaunchRecord rec;
   if (ctx.profiling) {
