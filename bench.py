@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--serve-leg-jobs", type=int, default=12)
     ap.add_argument("--no-group", action="store_true", help="serving: no grouped launches across jobs")
     ap.add_argument("--no-graphs", action="store_true", help="serving: no HIP graph replay")
+    ap.add_argument("--max-wait-us", type=float, default=-1.0,
+                    help="serving: fixed bound of a leader's wait for same-shape jobs (< 0: the library's default, "
+                         "a tenth of the program's estimated run time)")
     ap.add_argument("--profile-all", action="store_true",
                     help="time every contraction launch of the run (not only the timed steps) and print the per-variant "
                          "launch counts, algorithmic flops and bytes to stderr, for comparison with a rocprofv3 trace")
@@ -298,7 +301,7 @@ def run_serve_bench(a):
     rng = np.random.default_rng(3)
     ctx = api.Context(0)
     srv = api.Server(ctx, hbm_budget=200 << 30, max_slots=a.slots, group_launches=not a.no_group,
-                     graph_capture=not a.no_graphs)
+                     graph_capture=not a.no_graphs, max_wait_us=None if a.max_wait_us < 0 else a.max_wait_us)
     jobs = []
     t_arr = 0.0
     for k in range(a.jobs):
@@ -361,6 +364,7 @@ def run_serve_bench(a):
                   "polish_iter": results[i][1]["polish_iter"], "energy": results[i][1]["energy"],
                   "latency_s": float(lat[k])} for k, i in enumerate(ids)],
         "slots": a.slots, "grouped_launches": not a.no_group, "graph_replay": not a.no_graphs,
+        "leader_wait_us": "program-cost bound" if a.max_wait_us < 0 else a.max_wait_us,
         "batcher": stats,
     }
 

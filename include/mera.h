@@ -338,8 +338,10 @@ mera_status run_optimize(mera_ctx* ctx, const mera_job* job, mera_result* out, d
 mera_status mera_server_create(mera_ctx* ctx, size_t hbm_budget, int max_slots, mera_server** out);
 /* Batching options, before the first submit (MERA_EBUSY afterwards): group_launches != 0 groups the same
  * program across jobs (default on); graph_capture != 0 replays repeated sequences from HIP graphs (default
- * on); max_wait_us bounds how long a job waits for others of its shape to reach the same program (default
- * 2000). With both off every job launches its own kernels on its own stream. */
+ * on); max_wait_us >= 0 bounds how long a job waits for others of its shape to reach the same program; a
+ * negative value (the default) bounds the wait by a tenth of the program's estimated run time (its multiply-adds
+ * at 50e12 per second plus 10 us per kernel launch), at most 2000 us. NaN: MERA_EINVAL. With both options off
+ * every job launches its own kernels on its own stream. */
 mera_status mera_server_configure(mera_server* srv, int group_launches, int graph_capture, double max_wait_us);
 typedef struct {
   int64_t batches;          /* program runs (grouped or not) */

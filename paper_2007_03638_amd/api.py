@@ -446,14 +446,15 @@ class LBFGS:
 class Server:
     """Continuous-batching job server (mera_server_*)."""
 
-    def __init__(self, ctx, hbm_budget, max_slots, group_launches=True, graph_capture=True, max_wait_us=2000.0):
+    def __init__(self, ctx, hbm_budget, max_slots, group_launches=True, graph_capture=True, max_wait_us=None):
         self.ctx = ctx
         self._lib = ctx._lib
         self.ptr = ctypes.c_void_p()
         ctx._check(self._lib.mera_server_create(ctx.ptr, int(hbm_budget), int(max_slots), ctypes.byref(self.ptr)),
                    "mera_server_create")
         ctx._check(self._lib.mera_server_configure(self.ptr, int(bool(group_launches)), int(bool(graph_capture)),
-                                                   float(max_wait_us)), "mera_server_configure")
+                                                   -1.0 if max_wait_us is None else float(max_wait_us)),
+                   "mera_server_configure")
 
     def stats(self):
         st = L.ServerStats()

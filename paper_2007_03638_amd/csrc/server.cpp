@@ -5,6 +5,7 @@
 // buffers is replayed from a captured HIP graph. Each job's operands go through exactly the kernels, tiles and
 // reduction order they would alone, so its result is independent of the mix.
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -57,14 +58,22 @@ size_t job_footprint(const mera_shape& s, Prec prec, int krylov_dim = 0) {
 
 // Groups run_program calls of concurrently running jobs. A call opens a batch keyed by (program, extents,
 // precision, chunk) or joins the open batch of that key; the opener (leader) waits until every other worker
-// running a job of the same shape is itself waiting in the batcher (or the batch is full, or max_wait has
-// passed), then runs the group on its own stream. Stream order: the leader's stream waits for each member's
+// running a job of the same shape is itself waiting in the batcher (or the batch is full, or the wait bound has
+// passed), then runs the group on its own stream. By default the wait bound is a tenth of the program's estimated
+// run time (its multiply-adds at kMacRate plus kLaunchSeconds per kernel launch), at most kMaxAdaptiveWait: jobs of
+// one shape are usually at different points of their iterations, so most waits are lost, and a wait bounded by the
+// program's own cost keeps that loss small (a fixed 2 ms wait would dominate the sub-millisecond programs of small
+// chi). A configured max_wait >= 0 replaces it with a fixed bound. Stream order: the leader's stream waits for each member's
 // "ready" event (recorded on the member's stream at the call), and each member's stream waits for the
 // leader's "done" event afterwards, so a member continues exactly as if it had launched the work itself.
 struct GroupBatcher : Batcher {
   bool grouping = true;
   bool graphs = true;
-  double max_wait = 2e-3;  // seconds a leader waits for members
+  double max_wait = -1.0;  // fixed bound (seconds) of a leader's wait for members; < 0: bound by the program's cost
+  static constexpr double kWaitFraction = 0.1;
+  static constexpr double kMaxAdaptiveWait = 2e-3;
+  static constexpr double kMacRate = 50e12;       // multiply-adds per second of a large FP32 contraction
+  static constexpr double kLaunchSeconds = 10e-6;  // host and dispatch cost of one kernel launch
 
   struct WorkerState {
     std::string shape;  // shape of the job being run ("" while idle)
@@ -90,6 +99,7 @@ struct GroupBatcher : Batcher {
   std::condition_variable cv;
   std::map<const Ctx*, WorkerState> states;
   std::map<std::string, Batch*> open;
+  std::map<std::string, double> est_cache;  // batch key -> estimated run time (seconds)
   std::mutex gmu;
   std::map<std::string, GraphEntry> graph_cache;
   static constexpr size_t kMaxGraphs = 4096;
@@ -124,6 +134,25 @@ struct GroupBatcher : Batcher {
     for (size_t c = 0; c < dims.size(); ++c)
       if (dims[c]) k += "," + std::to_string(c) + ":" + std::to_string(dims[c]);
     return k;
+  }
+
+  // Estimated run time of one program run: every step's multiply-adds (the product of the extents of the legs of
+  // its two operands; a sliced loop covers the whole leg) at kMacRate, plus kLaunchSeconds per launch.
+  static double estimate_seconds(const Program& prog, const LegDims& dims, int64_t chunk) {
+    double macs = 0.0;
+    for (const StepDef& s : prog.steps) {
+      std::string legs = s.la + s.lb;
+      std::sort(legs.begin(), legs.end());
+      legs.erase(std::unique(legs.begin(), legs.end()), legs.end());
+      double m = 1.0;
+      for (char c : legs) m *= (double)std::max<int64_t>(1, dims[(unsigned char)c]);
+      macs += m;
+    }
+    int64_t launches = (int64_t)prog.steps.size();
+    const unsigned char L = (unsigned char)prog.slice_leg;
+    if (prog.slice_leg && chunk > 0 && chunk < dims[L] && prog.loop_begin >= 0)
+      launches += (int64_t)(prog.loop_end - prog.loop_begin) * (dims[L] / chunk - 1);
+    return macs / kMacRate + (double)launches * kLaunchSeconds;
   }
 
   // true while some other worker running a job of the same shape is neither waiting nor in the batch
@@ -170,7 +199,13 @@ struct GroupBatcher : Batcher {
     me.waiting = true;
     cv.notify_all();
     if (opened) {
-      const auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(max_wait);
+      double wait = max_wait;
+      if (wait < 0) {
+        auto est = est_cache.find(key);
+        if (est == est_cache.end()) est = est_cache.emplace(key, estimate_seconds(prog, dims, chunk)).first;
+        wait = std::min(kMaxAdaptiveWait, kWaitFraction * est->second);
+      }
+      const auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(wait);
       cv.wait_until(lk, deadline,
                     [&] { return (int)b.reqs.size() >= kGettMaxGroup || !others_coming(&ctx, b); });
       open.erase(key);
@@ -414,12 +449,12 @@ mera_status mera_server_create(mera_ctx* ctx, size_t hbm_budget, int max_slots, 
 }
 
 mera_status mera_server_configure(mera_server* srv, int group_launches, int graph_capture, double max_wait_us) {
-  if (!srv || max_wait_us < 0) return MERA_EINVAL;
+  if (!srv || std::isnan(max_wait_us)) return MERA_EINVAL;
   std::lock_guard<std::mutex> lk(srv->s.mu);
   if (srv->s.started) return MERA_EBUSY;
   srv->s.batcher.grouping = group_launches != 0;
   srv->s.batcher.graphs = graph_capture != 0;
-  srv->s.batcher.max_wait = max_wait_us * 1e-6;
+  srv->s.batcher.max_wait = max_wait_us < 0 ? -1.0 : max_wait_us * 1e-6;
   return MERA_OK;
 }
 

@@ -31,6 +31,12 @@ def _jobs():
     return out
 
 
+# Grouping needs jobs of one shape to meet at the same program; these tests exercise the grouped launches, so they
+# give the leader a fixed 2 ms to wait for its members (the default bound, a tenth of a small program's run time,
+# seldom lets the small jobs here meet).
+GROUP_WAIT_US = 2000.0
+
+
 def _wait(srv, ids, timeout=300):
     res = {}
     t0 = time.time()
@@ -64,7 +70,7 @@ def test_alone_equals_mix(ctx):
         r, st = _run_all(ctx, [j], 1, group_launches=False, graph_capture=False)
         assert st["grouped_batches"] == 0 and st["graph_launches"] == 0
         alone += r
-    mixed, st = _run_all(ctx, jobs, 4)
+    mixed, st = _run_all(ctx, jobs, 4, max_wait_us=GROUP_WAIT_US)
     print("mix stats", st, flush=True)
     for a, b in zip(alone, mixed):
         print(a["energy"], b["energy"], a["iterations"], b["iterations"], flush=True)
@@ -83,7 +89,7 @@ def test_grouping_and_graphs_separately(ctx):
     jobs = _jobs()[:2] + _jobs()[:2]       # two pairs of identical jobs
     ref, _ = _run_all(ctx, jobs[:2], 1, group_launches=False, graph_capture=False)
     for opts in (dict(group_launches=True, graph_capture=False), dict(group_launches=False, graph_capture=True)):
-        res, st = _run_all(ctx, jobs, 4, **opts)
+        res, st = _run_all(ctx, jobs, 4, max_wait_us=GROUP_WAIT_US, **opts)
         print(opts, st, flush=True)
         for k, r in enumerate(res):
             assert r["energy"] == ref[k % 2]["energy"]
@@ -93,6 +99,21 @@ def test_grouping_and_graphs_separately(ctx):
             assert st["grouped_batches"] > 0 and st["graph_launches"] == 0
         else:
             assert st["grouped_batches"] == 0 and st["graph_launches"] > 0
+
+
+def test_default_wait_policy_mix_equals_alone(ctx):
+    """With the default leader wait (bounded by the program's estimated run time) and a zero wait, a mix of two pairs
+    of identical jobs still gives each job exactly its result alone, whether or not launches were grouped."""
+    jobs = _jobs()[:2] + _jobs()[:2]
+    ref, _ = _run_all(ctx, jobs[:2], 1, group_launches=False, graph_capture=False)
+    for wait in (None, 0.0):
+        res, st = _run_all(ctx, jobs, 4, max_wait_us=wait)
+        print("max_wait_us", wait, st, flush=True)
+        for k, r in enumerate(res):
+            assert r["energy"] == ref[k % 2]["energy"]
+            assert r["gnorm"] == ref[k % 2]["gnorm"]
+            assert r["evaluations"] == ref[k % 2]["evaluations"]
+        assert st["bindings"] >= st["batches"] > 0
 
 
 def test_admission_budget(ctx):
@@ -125,7 +146,7 @@ def test_nonfinite_job_fails_alone_in_a_mix(ctx):
     bad_u = dict(jobs[1])
     bad_u["init"] = [m.copy() for m in bad_u["init"]]
     bad_u["init"][2][3, 1] = np.nan
-    srv = api.Server(ctx, hbm_budget=64 << 30, max_slots=4)
+    srv = api.Server(ctx, hbm_budget=64 << 30, max_slots=4, max_wait_us=GROUP_WAIT_US)
     ids = [srv.submit(**j) for j in (jobs[0], bad_h, jobs[1], bad_u, jobs[2], jobs[3])]
     t0 = time.time()
     out = {}
@@ -161,7 +182,7 @@ def test_job_arriving_mid_evaluation(ctx):
     jobs = _jobs()
     j8 = [jobs[1], jobs[3], dict(jobs[1])]  # chi = 8 jobs; the third repeats the first
     alone = [_run_all(ctx, [j], 1, group_launches=False, graph_capture=False)[0][0] for j in j8[:2]]
-    srv = api.Server(ctx, hbm_budget=64 << 30, max_slots=4)
+    srv = api.Server(ctx, hbm_budget=64 << 30, max_slots=4, max_wait_us=GROUP_WAIT_US)
     ids = [srv.submit(**j8[0]), srv.submit(**j8[1])]
     t0 = time.time()
     while srv.stats()["grouped_batches"] < 3:  # the two running jobs share launches by now
