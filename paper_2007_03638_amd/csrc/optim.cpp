@@ -15,7 +15,7 @@ namespace {
 
 VPtr d64(const MatView& m) { return VPtr{m.data, Prec::F64}; }
 int64_t numel(const MatView& m) { return (int64_t)m.n * m.p; }
-double* tmp(Ctx& ctx, const char* name, int64_t n) {
+double* tmp(Ctx& ctx, const std::string& name, int64_t n) {
   return static_cast<double*>(ctx.buf(name, (size_t)n * sizeof(double)));
 }
 
@@ -340,6 +340,10 @@ void Metric::compute(Ctx& ctx, const std::vector<MatView>& rho) {
   g.resize(k);
   warm.resize(k, 0);
   p.assign(k, 0);
+  // every factor's matrix is prepared first (each in its own scratch), then all are decomposed together: the
+  // small ones (p <= 64) in one launch, one workgroup each
+  std::vector<JacobiTask> tasks;
+  tasks.reserve(k);
   for (size_t i = 0; i < k; ++i) {
     const int q = rho[i].p;
     MERA_CHECK(rho[i].n == q, MERA_EINVAL, "metric must be square");
@@ -350,24 +354,26 @@ void Metric::compute(Ctx& ctx, const std::vector<MatView>& rho) {
     lam[i].ensure((size_t)q * 8);
     f[i].ensure((size_t)q * 8);
     g[i].ensure((size_t)q * 8);
-    double* a = tmp(ctx, "met.a", (int64_t)q * q);
+    const std::string tag = std::to_string(i);
+    double* a = tmp(ctx, "met.a" + tag, (int64_t)q * q);
     copy(ctx, VPtr{a, Prec::F64}, d64(rho[i]), (int64_t)q * q);
     symmetrize(ctx, VPtr{a, Prec::F64}, q);
     double* Q = V[i].as<double>();
     if (reuse) {
       const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', q}, {'q', q}, {'r', q}};
       double* t = tmp(ctx, "met.t", (int64_t)q * q);
-      double* b = tmp(ctx, "met.b", (int64_t)q * q);
+      double* b = tmp(ctx, "met.b" + tag, (int64_t)q * q);
       mm(ctx, "T[pq] = A[pr] * Q[rq]", dpp, {{"T", t}, {"A", a}, {"Q", Q}});
       mm(ctx, "B[pq] = Q[rp] * T[rq]", dpp, {{"B", b}, {"Q", Q}, {"T", t}});
       symmetrize(ctx, VPtr{b, Prec::F64}, q);
-      jacobi_eigh(ctx, b, lam[i].as<double>(), Q, q, 1e-15, 30, true);
+      tasks.push_back(JacobiTask{b, lam[i].as<double>(), Q, q, 1e-15, 30, true});
       warm[i]++;
     } else {
-      jacobi_eigh(ctx, a, lam[i].as<double>(), Q, q);
+      tasks.push_back(JacobiTask{a, lam[i].as<double>(), Q, q});
       warm[i] = 1;
     }
   }
+  jacobi_eigh_batch(ctx, tasks);
 }
 
 void precondition_one(Ctx& ctx, const MatView& W, const MatView& X, Metric& met, int i, double delta,

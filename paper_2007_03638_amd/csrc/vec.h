@@ -2,6 +2,8 @@
 // symmetrisation, traces, and the cyclic two-sided Jacobi eigensolver for small symmetric matrices.
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace mera {
@@ -50,6 +52,19 @@ void normalize_dev(Ctx& ctx, VPtr x, int64_t n, double* nrm_dev, double* work_de
 // launch (one workgroup, A and V in LDS); larger ones launch one kernel per round.
 void jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol = 1e-15, int max_sweeps = 30,
                  bool v_init = false);
+
+// Several independent decompositions (arguments as for jacobi_eigh, distinct buffers): those of matrices up to
+// 64 x 64 run together, up to 16 per launch, one workgroup each; larger ones as jacobi_eigh.
+struct JacobiTask {
+  double* a;
+  double* lam;
+  double* v;
+  int dim;
+  double tol = 1e-15;
+  int max_sweeps = 30;
+  bool v_init = false;
+};
+void jacobi_eigh_batch(Ctx& ctx, const std::vector<JacobiTask>& tasks);
 
 // Element-wise helpers for the preconditioner (all FP64, device):
 //   M_ij <- M_ij * 2 / (f_i + f_j)

@@ -303,12 +303,33 @@ __global__ void jacobi_round_kernel(const double* __restrict__ ain, double* __re
 // Matrices up to this size are decomposed by one workgroup, with A and V in LDS and every sweep in one launch.
 constexpr int kJacobiSmall = 64;
 
-// The same rounds and stopping rule as the multi-launch path, for dim <= kJacobiSmall: per round the rotations of
-// all pairs are taken from A, the 2x2 blocks of J^T A J are formed in registers (at most 4 blocks per thread) and
-// written back after a barrier, and V <- V J in place (each (row, pair) belongs to one thread).
-__global__ void __launch_bounds__(256) jacobi_small_kernel(double* a, double* lam, double* v,
-                                                           const int* __restrict__ pairs, int npairs, int rounds,
-                                                           int dim, double tol, int max_sweeps, int v_init) {
+// One decomposition of a batch launch (one workgroup each).
+struct JacobiSmallTask {
+  double* a;
+  double* lam;
+  double* v;
+  const int* pairs;
+  double tol;
+  int npairs, rounds, dim, max_sweeps, v_init;
+};
+constexpr int kJacobiBatch = 16;
+struct JacobiSmallBatch {
+  JacobiSmallTask t[kJacobiBatch];
+};
+
+// The same rounds and stopping rule as the multi-launch path, for dim <= kJacobiSmall, one matrix per workgroup
+// (workgroup b decomposes task b of the batch): per round the rotations of all pairs are taken from A, the 2x2
+// blocks of J^T A J are formed in registers (at most 4 blocks per thread) and written back after a barrier, and
+// V <- V J in place (each (row, pair) belongs to one thread).
+__global__ void __launch_bounds__(256) jacobi_small_kernel(JacobiSmallBatch batch) {
+  const JacobiSmallTask& task = batch.t[blockIdx.x];
+  double* const a = task.a;
+  double* const lam = task.lam;
+  double* const v = task.v;
+  const int* __restrict__ pairs = task.pairs;
+  const int npairs = task.npairs, rounds = task.rounds, dim = task.dim, max_sweeps = task.max_sweeps;
+  const int v_init = task.v_init;
+  const double tol = task.tol;
   constexpr int LD = kJacobiSmall + 1;
   constexpr int NB = (kJacobiSmall / 2) * (kJacobiSmall / 2) / 256;
   __shared__ double As[kJacobiSmall * LD], Vs[kJacobiSmall * LD];
@@ -770,13 +791,15 @@ void normalize_dev(Ctx& ctx, VPtr x, int64_t n, double* nrm_dev, double* work_de
   MERA_HIP(hipGetLastError());
 }
 
-void jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol, int max_sweeps, bool v_init) {
-  if (dim <= 0) return;
+namespace {
+
+// Tournament (circle) schedule of the rounds for one dimension, built once per device and dimension: m = dim
+// rounded up to even, index m - 1 a dummy when dim is odd.
+JacobiSchedule& jacobi_schedule(Ctx& ctx, int dim) {
   static thread_local std::unordered_map<std::string, std::unique_ptr<JacobiSchedule>> scheds;
   const std::string key = std::to_string(ctx.device) + ":" + std::to_string(dim);
   auto it = scheds.find(key);
   if (it == scheds.end()) {
-    // tournament (circle) schedule over m = dim rounded up to even; index m-1 is a dummy when dim is odd
     auto s = std::make_unique<JacobiSchedule>();
     const int m = dim + (dim & 1);
     s->dim = dim;
@@ -802,13 +825,41 @@ void jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double to
     MERA_HIP(hipStreamSynchronize(ctx.stream));
     it = scheds.emplace(key, std::move(s)).first;
   }
-  JacobiSchedule& s = *it->second;
-  if (dim <= kJacobiSmall) {
-    hipLaunchKernelGGL(jacobi_small_kernel, dim3(1), dim3(256), 0, ctx.stream, a, lam, v, s.pairs.as<int>(),
-                       s.npairs, s.rounds, dim, tol, max_sweeps, v_init ? 1 : 0);
+  return *it->second;
+}
+
+}  // namespace
+
+void jacobi_eigh_batch(Ctx& ctx, const std::vector<JacobiTask>& tasks) {
+  JacobiSmallBatch batch{};
+  int nb = 0;
+  auto flush = [&]() {
+    if (nb == 0) return;
+    hipLaunchKernelGGL(jacobi_small_kernel, dim3(nb), dim3(256), 0, ctx.stream, batch);
     MERA_HIP(hipGetLastError());
+    nb = 0;
+  };
+  for (const JacobiTask& t : tasks) {
+    if (t.dim <= 0) continue;
+    if (t.dim > kJacobiSmall) {
+      jacobi_eigh(ctx, t.a, t.lam, t.v, t.dim, t.tol, t.max_sweeps, t.v_init);
+      continue;
+    }
+    JacobiSchedule& s = jacobi_schedule(ctx, t.dim);
+    batch.t[nb++] = JacobiSmallTask{t.a, t.lam, t.v, s.pairs.as<int>(), t.tol, s.npairs, s.rounds, t.dim,
+                                    t.max_sweeps, t.v_init ? 1 : 0};
+    if (nb == kJacobiBatch) flush();
+  }
+  flush();
+}
+
+void jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol, int max_sweeps, bool v_init) {
+  if (dim <= 0) return;
+  if (dim <= kJacobiSmall) {
+    jacobi_eigh_batch(ctx, {JacobiTask{a, lam, v, dim, tol, max_sweeps, v_init}});
     return;
   }
+  JacobiSchedule& s = jacobi_schedule(ctx, dim);
   double* b = static_cast<double*>(ctx.buf("jacobi.pingpong", (size_t)dim * dim * sizeof(double)));
   const int g = grid_for((int64_t)dim * dim);
   if (!v_init) hipLaunchKernelGGL(eye_kernel, dim3(g), dim3(TPB), 0, ctx.stream, v, dim);
