@@ -417,11 +417,18 @@ mera_status stiefel_retract(mera_ctx* ctx, int count, const mera_mat* W, const m
       same_shapes(W, X_out, count, "stiefel_retract");
     }
     DeviceGuard g(ctx->c.device);
+    std::vector<MatView> wv(count), xv(count), wo(count), xo(count);
+    std::vector<const MatView*> xop(count, nullptr);
     for (int i = 0; i < count; ++i) {
-      MatView xo = X_out ? MatView{X_out[i].n, X_out[i].p, X_out[i].data} : MatView{};
-      stiefel_retract_one(ctx->c, MatView{W[i].n, W[i].p, W[i].data}, MatView{X[i].n, X[i].p, X[i].data}, alpha,
-                          MatView{W_out[i].n, W_out[i].p, W_out[i].data}, X_out ? &xo : nullptr);
+      wv[i] = MatView{W[i].n, W[i].p, W[i].data};
+      xv[i] = MatView{X[i].n, X[i].p, X[i].data};
+      wo[i] = MatView{W_out[i].n, W_out[i].p, W_out[i].data};
+      if (X_out) {
+        xo[i] = MatView{X_out[i].n, X_out[i].p, X_out[i].data};
+        xop[i] = &xo[i];
+      }
     }
+    if (count > 0) stiefel_retract_many(ctx->c, wv, xv, alpha, wo, xop);
     ctx->c.sync();
   });
 }

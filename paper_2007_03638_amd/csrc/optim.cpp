@@ -40,8 +40,18 @@ std::vector<MatView> Flat::views() const {
 }
 
 double inner(Ctx& ctx, const std::vector<MatView>& X, const std::vector<MatView>& Y) {
+  const size_t k = X.size();
+  std::vector<VPtr> x(k), y(k);
+  std::vector<int64_t> n(k);
+  std::vector<double> d(k);
+  for (size_t i = 0; i < k; ++i) {
+    x[i] = d64(X[i]);
+    y[i] = d64(Y[i]);
+    n[i] = numel(X[i]);
+  }
+  dots(ctx, x.data(), y.data(), n.data(), (int)k, d.data());
   double s = 0.0;
-  for (size_t i = 0; i < X.size(); ++i) s += dot(ctx, d64(X[i]), d64(Y[i]), numel(X[i]));
+  for (size_t i = 0; i < k; ++i) s += d[i];
   return s;
 }
 
@@ -55,74 +65,126 @@ void stiefel_project_one(Ctx& ctx, const MatView& W, const MatView& D, const Mat
      {{"G", G.data}, {"W", W.data}, {"S", S}});
 }
 
-void stiefel_retract_one(Ctx& ctx, const MatView& W, const MatView& X, double alpha, const MatView& Wout,
-                         const MatView* Xout) {
-  const int n = W.n, p = W.p;
-  const int64_t pp = (int64_t)p * p;
-  double* Y = tmp(ctx, "rt.Y", (int64_t)n * p);
-  double* M = tmp(ctx, "rt.M", pp);
-  double* Yk = tmp(ctx, "rt.Yk", pp);
-  double* Zk = tmp(ctx, "rt.Zk", pp);
-  double* Tk = tmp(ctx, "rt.T", pp);
-  double* Y2 = tmp(ctx, "rt.Y2", pp);
-  double* Z2 = tmp(ctx, "rt.Z2", pp);
-  copy(ctx, VPtr{Y, Prec::F64}, d64(W), (int64_t)n * p);
-  axpby(ctx, alpha, d64(X), 1.0, VPtr{Y, Prec::F64}, (int64_t)n * p);
-  // M = Y^T Y
-  mm(ctx, "M[pq] = Y[np] * Y2[nq]", {{'n', n}, {'p', p}, {'q', p}}, {{"M", M}, {"Y", Y}, {"Y2", Y}});
-  symmetrize(ctx, VPtr{M, Prec::F64}, p);
+void stiefel_retract_many(Ctx& ctx, const std::vector<MatView>& W, const std::vector<MatView>& X, double alpha,
+                          const std::vector<MatView>& Wout, const std::vector<const MatView*>& Xout) {
+  // Every factor runs the same sequence of operations as it would alone; the factors step through the
+  // Newton-Schulz iteration together, so that the convergence norms of all of them come back in one
+  // synchronisation per step. Scratch is per factor.
+  const size_t k = W.size();
+  struct Fac {
+    int n, p;
+    int64_t pp;
+    double *Y, *M, *Yk, *Zk, *Tk, *Y2, *Z2;
+    double c = 0.0;
+    int tail = 0;
+    bool conv = false;
+  };
+  std::vector<Fac> fs(k);
+  for (size_t i = 0; i < k; ++i) {
+    Fac& f = fs[i];
+    f.n = W[i].n;
+    f.p = W[i].p;
+    f.pp = (int64_t)f.p * f.p;
+    const std::string t = std::to_string(i);
+    f.Y = tmp(ctx, "rt.Y" + t, (int64_t)f.n * f.p);
+    f.M = tmp(ctx, "rt.M" + t, f.pp);
+    f.Yk = tmp(ctx, "rt.Yk" + t, f.pp);
+    f.Zk = tmp(ctx, "rt.Zk" + t, f.pp);
+    f.Tk = tmp(ctx, "rt.T" + t, f.pp);
+    f.Y2 = tmp(ctx, "rt.Y2" + t, f.pp);
+    f.Z2 = tmp(ctx, "rt.Z2" + t, f.pp);
+    copy(ctx, VPtr{f.Y, Prec::F64}, d64(W[i]), (int64_t)f.n * f.p);
+    axpby(ctx, alpha, d64(X[i]), 1.0, VPtr{f.Y, Prec::F64}, (int64_t)f.n * f.p);
+    // M = Y^T Y
+    mm(ctx, "M[pq] = Y[np] * Y2[nq]", {{'n', f.n}, {'p', f.p}, {'q', f.p}}, {{"M", f.M}, {"Y", f.Y}, {"Y2", f.Y}});
+    symmetrize(ctx, VPtr{f.M, Prec::F64}, f.p);
+  }
   // coupled Newton-Schulz iteration (Higham, "Functions of Matrices", the coupled square-root iteration):
   // Y_0 = M/c, Z_0 = I, T = (3I - Z Y)/2, Y <- Y T, Z <- T Z; Z -> (M/c)^{-1/2}
-  const double c = std::sqrt(dot(ctx, VPtr{M, Prec::F64}, VPtr{M, Prec::F64}, pp));
-  MERA_CHECK(std::isfinite(c) && c > 0.0, MERA_ENONFINITE, "retraction: non-finite Y^T Y");
-  copy(ctx, VPtr{Yk, Prec::F64}, VPtr{M, Prec::F64}, pp);
-  scal(ctx, 1.0 / c, VPtr{Yk, Prec::F64}, pp);
-  fill(ctx, VPtr{Zk, Prec::F64}, pp, 0.0);
-  add_diag(ctx, VPtr{Zk, Prec::F64}, p, 1.0);
-  const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', p}, {'q', p}, {'r', p}};
-  bool conv = false;
-  int tail = 0;
-  for (int it = 0; it < 100; ++it) {
-    mm(ctx, "T[pq] = -0.5 * Z[pr] * Yk[rq]", dpp, {{"T", Tk}, {"Z", Zk}, {"Yk", Yk}});
-    add_diag(ctx, VPtr{Tk, Prec::F64}, p, 1.5);
-    mm(ctx, "Y2[pq] = Yk[pr] * T[rq]", dpp, {{"Y2", Y2}, {"Yk", Yk}, {"T", Tk}});
-    mm(ctx, "Z2[pq] = T[pr] * Z[rq]", dpp, {{"Z2", Z2}, {"T", Tk}, {"Z", Zk}});
-    std::swap(Yk, Y2);
-    std::swap(Zk, Z2);
-    add_diag(ctx, VPtr{Tk, Prec::F64}, p, -1.0);
-    const double err = std::sqrt(dot(ctx, VPtr{Tk, Prec::F64}, VPtr{Tk, Prec::F64}, pp));
-    MERA_CHECK(std::isfinite(err), MERA_ENONFINITE, "retraction: Newton-Schulz diverged");
-    if (err < 1e-13) {
-      // quadratic convergence: one more step reaches rounding level
-      if (++tail >= 2) {
-        conv = true;
-        break;
-      }
+  std::vector<VPtr> xa(k);
+  std::vector<int64_t> na(k);
+  std::vector<double> d(k);
+  for (size_t i = 0; i < k; ++i) {
+    xa[i] = VPtr{fs[i].M, Prec::F64};
+    na[i] = fs[i].pp;
+  }
+  dots(ctx, xa.data(), xa.data(), na.data(), (int)k, d.data());
+  for (size_t i = 0; i < k; ++i) {
+    Fac& f = fs[i];
+    f.c = std::sqrt(d[i]);
+    MERA_CHECK(std::isfinite(f.c) && f.c > 0.0, MERA_ENONFINITE, "retraction: non-finite Y^T Y");
+    copy(ctx, VPtr{f.Yk, Prec::F64}, VPtr{f.M, Prec::F64}, f.pp);
+    scal(ctx, 1.0 / f.c, VPtr{f.Yk, Prec::F64}, f.pp);
+    fill(ctx, VPtr{f.Zk, Prec::F64}, f.pp, 0.0);
+    add_diag(ctx, VPtr{f.Zk, Prec::F64}, f.p, 1.0);
+  }
+  std::vector<size_t> active(k);
+  for (size_t i = 0; i < k; ++i) active[i] = i;
+  for (int it = 0; it < 100 && !active.empty(); ++it) {
+    for (size_t i : active) {
+      Fac& f = fs[i];
+      const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', f.p}, {'q', f.p}, {'r', f.p}};
+      mm(ctx, "T[pq] = -0.5 * Z[pr] * Yk[rq]", dpp, {{"T", f.Tk}, {"Z", f.Zk}, {"Yk", f.Yk}});
+      add_diag(ctx, VPtr{f.Tk, Prec::F64}, f.p, 1.5);
+      mm(ctx, "Y2[pq] = Yk[pr] * T[rq]", dpp, {{"Y2", f.Y2}, {"Yk", f.Yk}, {"T", f.Tk}});
+      mm(ctx, "Z2[pq] = T[pr] * Z[rq]", dpp, {{"Z2", f.Z2}, {"T", f.Tk}, {"Z", f.Zk}});
+      std::swap(f.Yk, f.Y2);
+      std::swap(f.Zk, f.Z2);
+      add_diag(ctx, VPtr{f.Tk, Prec::F64}, f.p, -1.0);
+    }
+    const size_t na_ = active.size();
+    for (size_t j = 0; j < na_; ++j) {
+      xa[j] = VPtr{fs[active[j]].Tk, Prec::F64};
+      na[j] = fs[active[j]].pp;
+    }
+    dots(ctx, xa.data(), xa.data(), na.data(), (int)na_, d.data());
+    std::vector<size_t> still;
+    for (size_t j = 0; j < na_; ++j) {
+      Fac& f = fs[active[j]];
+      const double err = std::sqrt(d[j]);
+      MERA_CHECK(std::isfinite(err), MERA_ENONFINITE, "retraction: Newton-Schulz diverged");
+      // quadratic convergence: one more step after the first below 1e-13 reaches rounding level
+      if (err < 1e-13 && ++f.tail >= 2) f.conv = true;
+      else still.push_back(active[j]);
+    }
+    active.swap(still);
+  }
+  for (const Fac& f : fs) MERA_CHECK(f.conv, MERA_ENOCONV, "retraction: Newton-Schulz did not converge");
+  for (size_t i = 0; i < k; ++i) {
+    Fac& f = fs[i];
+    const int n = f.n, p = f.p;
+    const int64_t pp = f.pp;
+    const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', p}, {'q', p}, {'r', p}};
+    // Z = M^{-1/2}
+    scal(ctx, 1.0 / std::sqrt(f.c), VPtr{f.Zk, Prec::F64}, pp);
+    double* Wt = tmp(ctx, "rt.W", (int64_t)n * p);
+    mm(ctx, "Wt[nq] = Y[np] * Z[pq]", {{'n', n}, {'p', p}, {'q', p}}, {{"Wt", Wt}, {"Y", f.Y}, {"Z", f.Zk}});
+    // one Newton-Schulz polar refinement: W <- W (3I - W^T W)/2
+    mm(ctx, "E[pq] = Wt[np] * Wt2[nq]", {{'n', n}, {'p', p}, {'q', p}}, {{"E", f.Tk}, {"Wt", Wt}, {"Wt2", Wt}});
+    scal(ctx, -0.5, VPtr{f.Tk, Prec::F64}, pp);
+    add_diag(ctx, VPtr{f.Tk, Prec::F64}, p, 1.5);
+    mm(ctx, "Wo[nq] = Wt[np] * E[pq]", {{'n', n}, {'p', p}, {'q', p}},
+       {{"Wo", Wout[i].data}, {"Wt", Wt}, {"E", f.Tk}});
+    if (Xout[i]) {
+      // M = I + alpha^2 K with K = X^T X (X tangent), and M commutes with K, so
+      // dR/dalpha = X Z + (W + alpha X) dZ/dalpha = X Z - alpha Y K Z^3.
+      double* K = tmp(ctx, "rt.K", pp);
+      mm(ctx, "K[pq] = X[np] * X2[nq]", {{'n', n}, {'p', p}, {'q', p}}, {{"K", K}, {"X", X[i].data}, {"X2", X[i].data}});
+      mm(ctx, "Y2[pq] = Z[pr] * Z2[rq]", dpp, {{"Y2", f.Y2}, {"Z", f.Zk}, {"Z2", f.Zk}});    // Z^2
+      mm(ctx, "T[pq] = Y2[pr] * Z[rq]", dpp, {{"T", f.Tk}, {"Y2", f.Y2}, {"Z", f.Zk}});      // Z^3
+      mm(ctx, "Y2[pq] = K[pr] * T[rq]", dpp, {{"Y2", f.Y2}, {"K", K}, {"T", f.Tk}});         // K Z^3
+      scal(ctx, -alpha, VPtr{f.Y2, Prec::F64}, pp);
+      mm(ctx, "Xo[nq] = X[np] * Z[pq]", {{'n', n}, {'p', p}, {'q', p}},
+         {{"Xo", Xout[i]->data}, {"X", X[i].data}, {"Z", f.Zk}});
+      mm(ctx, "Xo[nq] += Y[np] * KZ[pq]", {{'n', n}, {'p', p}, {'q', p}},
+         {{"Xo", Xout[i]->data}, {"Y", f.Y}, {"KZ", f.Y2}});
     }
   }
-  MERA_CHECK(conv, MERA_ENOCONV, "retraction: Newton-Schulz did not converge");
-  // Z = M^{-1/2}
-  scal(ctx, 1.0 / std::sqrt(c), VPtr{Zk, Prec::F64}, pp);
-  double* Wt = tmp(ctx, "rt.W", (int64_t)n * p);
-  mm(ctx, "Wt[nq] = Y[np] * Z[pq]", {{'n', n}, {'p', p}, {'q', p}}, {{"Wt", Wt}, {"Y", Y}, {"Z", Zk}});
-  // one Newton-Schulz polar refinement: W <- W (3I - W^T W)/2
-  mm(ctx, "E[pq] = Wt[np] * Wt2[nq]", {{'n', n}, {'p', p}, {'q', p}}, {{"E", Tk}, {"Wt", Wt}, {"Wt2", Wt}});
-  scal(ctx, -0.5, VPtr{Tk, Prec::F64}, pp);
-  add_diag(ctx, VPtr{Tk, Prec::F64}, p, 1.5);
-  mm(ctx, "Wo[nq] = Wt[np] * E[pq]", {{'n', n}, {'p', p}, {'q', p}}, {{"Wo", Wout.data}, {"Wt", Wt}, {"E", Tk}});
-  if (Xout) {
-    // M = I + alpha^2 K with K = X^T X (X tangent), and M commutes with K, so
-    // dR/dalpha = X Z + (W + alpha X) dZ/dalpha = X Z - alpha Y K Z^3.
-    double* K = tmp(ctx, "rt.K", pp);
-    mm(ctx, "K[pq] = X[np] * X2[nq]", {{'n', n}, {'p', p}, {'q', p}}, {{"K", K}, {"X", X.data}, {"X2", X.data}});
-    mm(ctx, "Y2[pq] = Z[pr] * Z2[rq]", dpp, {{"Y2", Y2}, {"Z", Zk}, {"Z2", Zk}});    // Z^2
-    mm(ctx, "T[pq] = Y2[pr] * Z[rq]", dpp, {{"T", Tk}, {"Y2", Y2}, {"Z", Zk}});      // Z^3
-    mm(ctx, "Y2[pq] = K[pr] * T[rq]", dpp, {{"Y2", Y2}, {"K", K}, {"T", Tk}});       // K Z^3
-    scal(ctx, -alpha, VPtr{Y2, Prec::F64}, pp);
-    mm(ctx, "Xo[nq] = X[np] * Z[pq]", {{'n', n}, {'p', p}, {'q', p}}, {{"Xo", Xout->data}, {"X", X.data}, {"Z", Zk}});
-    mm(ctx, "Xo[nq] += Y[np] * KZ[pq]", {{'n', n}, {'p', p}, {'q', p}},
-       {{"Xo", Xout->data}, {"Y", Y}, {"KZ", Y2}});
-  }
+}
+
+void stiefel_retract_one(Ctx& ctx, const MatView& W, const MatView& X, double alpha, const MatView& Wout,
+                         const MatView* Xout) {
+  stiefel_retract_many(ctx, {W}, {X}, alpha, {Wout}, {Xout});
 }
 
 void grassmann_project_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& G) {
@@ -458,7 +520,17 @@ void apply_precond(Ctx& ctx, const Flat& shape, const std::vector<MatView>& W, M
     return;
   }
   auto xv = views_of(shape, x), ov = views_of(shape, out);
-  for (int i = 0; i < shape.count(); ++i) precondition_one(ctx, W[i], xv[i], *met, i, -1.0, ov[i]);
+  // every factor's regularisation delta = |X_i| with one synchronisation
+  const int nf = shape.count();
+  std::vector<VPtr> xp(nf);
+  std::vector<int64_t> ne(nf);
+  std::vector<double> delta(nf);
+  for (int i = 0; i < nf; ++i) {
+    xp[i] = d64(xv[i]);
+    ne[i] = numel(xv[i]);
+  }
+  dots(ctx, xp.data(), xp.data(), ne.data(), nf, delta.data());
+  for (int i = 0; i < nf; ++i) precondition_one(ctx, W[i], xv[i], *met, i, std::sqrt(delta[i]), ov[i]);
 }
 
 }  // namespace
@@ -713,10 +785,16 @@ bool Optimizer::advance() {
 
   double f_trial = 0.0;
   auto phi = [&](double alpha, double& fa, double& dfa) {
-    for (int i = 0; i < W.count(); ++i) {
-      MatView xo = Xp.view(i);
-      if (expr) exp_retract_one(c, W.view(i), dir.view(i), frames[i], alpha, Wn.view(i), &xo);
-      else stiefel_retract_one(c, W.view(i), dir.view(i), alpha, Wn.view(i), &xo);
+    if (expr) {
+      for (int i = 0; i < W.count(); ++i) {
+        MatView xo = Xp.view(i);
+        exp_retract_one(c, W.view(i), dir.view(i), frames[i], alpha, Wn.view(i), &xo);
+      }
+    } else {
+      const std::vector<MatView> xo = Xp.views();
+      std::vector<const MatView*> xop(xo.size());
+      for (size_t i = 0; i < xo.size(); ++i) xop[i] = &xo[i];
+      stiefel_retract_many(c, W.views(), dir.views(), alpha, Wn.views(), xop);
     }
     fa = evaluate(Wn, Gn, rvn);
     dfa = inner(c, Gn.views(), Xp.views());

@@ -36,6 +36,9 @@ void stiefel_project_one(Ctx& ctx, const MatView& W, const MatView& D, const Mat
 // W_out = polar(W + alpha X), X_out = dW_out/dalpha (nullable)
 void stiefel_retract_one(Ctx& ctx, const MatView& W, const MatView& X, double alpha, const MatView& Wout,
                          const MatView* Xout);
+// The same for several factors at once (each computed exactly as alone; one synchronisation per iteration step)
+void stiefel_retract_many(Ctx& ctx, const std::vector<MatView>& W, const std::vector<MatView>& X, double alpha,
+                          const std::vector<MatView>& Wout, const std::vector<const MatView*>& Xout);
 
 // G = (1 - W W^T) D: Grassmann tangent projection (eq. grassmann_gradient, real case)
 void grassmann_project_one(Ctx& ctx, const MatView& W, const MatView& D, const MatView& G);

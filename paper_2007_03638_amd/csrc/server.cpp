@@ -48,10 +48,10 @@ size_t job_footprint(const mera_shape& s, Prec prec, int krylov_dim = 0) {
   // forward activations of the transition layers, kept within the default intermediate limit
   const double act = (double)activation_cache_bytes(dims, elem_bytes(prec));
   if (act <= (double)((size_t)32 << 30)) bytes += act;
-  // tensors, gradients, history (FP64)
+  // tensors, gradients, history, per-factor retraction scratch (FP64)
   double params = 0;
   for (const LayerDim& L : dims) params += (double)L.a * L.a * L.a * L.a + (double)L.wrows() * L.b;
-  bytes += 8.0 * params * (9 + 2 * 8);
+  bytes += 8.0 * params * (16 + 2 * 8);
   return (size_t)(bytes * 1.1) + ((size_t)64 << 20);
 }
 

@@ -16,6 +16,8 @@ struct VPtr {
 };
 
 double dot(Ctx& ctx, VPtr x, VPtr y, int64_t n);               // sum x*y in FP64 (syncs)
+// out[i] = <x_i, y_i> (lengths n_i) for count pairs with one synchronisation; each equals dot(x_i, y_i) bitwise
+void dots(Ctx& ctx, const VPtr* x, const VPtr* y, const int64_t* n, int count, double* out);
 double nrm2(Ctx& ctx, VPtr x, int64_t n);
 void axpby(Ctx& ctx, double a, VPtr x, double b, VPtr y, int64_t n);  // y = a x + b y
 // out[j] = <w, v_j>, j < k (host array), FP64 accumulation, one pass over w per 17 vectors (syncs). All vectors of

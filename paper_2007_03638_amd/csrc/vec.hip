@@ -529,6 +529,52 @@ struct JacobiSchedule {
 
 }  // namespace
 
+namespace {
+
+// Launches the partial sums of <x, y> into out[0 .. blocks) and returns the block count.
+int dot_launch(Ctx& ctx, VPtr x, VPtr y, int64_t n, double* out) {
+  const int blocks = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + TPB - 1) / TPB));
+  if (x.dbl() && y.dbl())
+    hipLaunchKernelGGL((dot_kernel<double, double>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const double*)x.p, (const double*)y.p, n, out);
+  else if (x.dbl())
+    hipLaunchKernelGGL((dot_kernel<double, float>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const double*)x.p, (const float*)y.p, n, out);
+  else if (y.dbl())
+    hipLaunchKernelGGL((dot_kernel<float, double>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const float*)x.p, (const double*)y.p, n, out);
+  else
+    hipLaunchKernelGGL((dot_kernel<float, float>), dim3(blocks), dim3(TPB), 0, ctx.stream,
+                       (const float*)x.p, (const float*)y.p, n, out);
+  MERA_HIP(hipGetLastError());
+  return blocks;
+}
+
+}  // namespace
+
+void dots(Ctx& ctx, const VPtr* x, const VPtr* y, const int64_t* n, int count, double* out) {
+  if (count <= 0) return;
+  ctx.red.ensure((size_t)count * RED_BLOCKS * sizeof(double));
+  double* part = ctx.red.as<double>();
+  std::vector<int> blocks(count);
+  int64_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    blocks[i] = dot_launch(ctx, x[i], y[i], n[i], part + total);
+    total += blocks[i];
+  }
+  std::vector<double> host((size_t)total);
+  MERA_HIP(hipMemcpyAsync(host.data(), part, (size_t)total * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  // each product summed over its partials in order, as dot() does
+  int64_t o = 0;
+  for (int i = 0; i < count; ++i) {
+    double s = 0.0;
+    for (int b = 0; b < blocks[i]; ++b) s += host[(size_t)(o + b)];
+    out[i] = s;
+    o += blocks[i];
+  }
+}
+
 double dot(Ctx& ctx, VPtr x, VPtr y, int64_t n) {
   ctx.red.ensure(RED_BLOCKS * sizeof(double));
   int blocks = (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + TPB - 1) / TPB));
