@@ -65,6 +65,38 @@ void stiefel_project_one(Ctx& ctx, const MatView& W, const MatView& D, const Mat
      {{"G", G.data}, {"W", W.data}, {"S", S}});
 }
 
+void project_many(Ctx& ctx, const std::vector<MatView>& W, const std::vector<MatView>& D,
+                  const std::vector<MatView>& G, const std::vector<bool>& grassmann) {
+  // items of equal shape run in grouped launches; each item computes what stiefel_project_one (or
+  // grassmann_project_one) computes for it alone
+  const size_t k = W.size();
+  std::vector<bool> done(k, false);
+  for (size_t a = 0; a < k; ++a) {
+    if (done[a]) continue;
+    std::vector<size_t> grp;
+    for (size_t b = a; b < k && grp.size() < (size_t)kGettMaxGroup; ++b)
+      if (!done[b] && W[b].n == W[a].n && W[b].p == W[a].p) {
+        grp.push_back(b);
+        done[b] = true;
+      }
+    const int n = W[a].n, p = W[a].p;
+    std::vector<std::vector<void*>> s1, s2;
+    std::vector<double*> S(grp.size());
+    for (size_t j = 0; j < grp.size(); ++j) {
+      S[j] = tmp(ctx, "pj.S" + std::to_string(j), (int64_t)p * p);
+      s1.push_back({S[j], W[grp[j]].data, D[grp[j]].data});
+    }
+    mm_group(ctx, "S[pq] = W[np] * D[nq]", {{'n', n}, {'p', p}, {'q', p}}, {"S", "W", "D"}, s1);
+    for (size_t j = 0; j < grp.size(); ++j) {
+      const size_t i = grp[j];
+      if (!grassmann[i]) symmetrize(ctx, VPtr{S[j], Prec::F64}, p);
+      if (G[i].data != D[i].data) copy(ctx, d64(G[i]), d64(D[i]), (int64_t)n * p);
+      s2.push_back({G[i].data, W[i].data, S[j]});
+    }
+    mm_group(ctx, "G[nq] += -1.0 * W[np] * S[pq]", {{'n', n}, {'p', p}, {'q', p}}, {"G", "W", "S"}, s2);
+  }
+}
+
 void stiefel_retract_many(Ctx& ctx, const std::vector<MatView>& W, const std::vector<MatView>& X, double alpha,
                           const std::vector<MatView>& Wout, const std::vector<const MatView*>& Xout) {
   // Every factor runs the same sequence of operations as it would alone; the factors step through the
@@ -579,20 +611,36 @@ double Lbfgs::step(Ctx& ctx, const std::vector<MatView>& W, const std::vector<Ma
 bool Lbfgs::push(Ctx& ctx, const std::vector<MatView>& Wn, const std::vector<MatView>& d, double alpha,
                  const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew) {
   const Transport T = [&](int i, const MatView& in, const MatView& out) { stiefel_project_one(ctx, Wn[i], in, out); };
-  return push(ctx, T, d, alpha, Gold, Gnew);
+  const TransportMany TM = [&](const std::vector<int>& fac, const std::vector<MatView>& in,
+                               const std::vector<MatView>& out) {
+    std::vector<MatView> w;
+    for (int i : fac) w.push_back(Wn[i]);
+    project_many(ctx, w, in, out, std::vector<bool>(fac.size(), false));
+  };
+  return push(ctx, T, d, alpha, Gold, Gnew, TM);
 }
 
 bool Lbfgs::push(Ctx& ctx, const Transport& T, const std::vector<MatView>& d, double alpha,
-                 const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew) {
+                 const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew, const TransportMany& TM) {
   const int64_t N = shape.total;
-  // transport the stored pairs to the new point
+  // transport the stored pairs to the new point (all at once when TM is given)
+  std::vector<int> fac;
+  std::vector<MatView> items;
   for (int sl : order) {
     auto sv = views_of(shape, S[sl].as<double>()), yv = views_of(shape, Y[sl].as<double>());
     for (int i = 0; i < shape.count(); ++i) {
-      T(i, sv[i], sv[i]);
-      T(i, yv[i], yv[i]);
+      if (TM) {
+        fac.push_back(i);
+        items.push_back(sv[i]);
+        fac.push_back(i);
+        items.push_back(yv[i]);
+      } else {
+        T(i, sv[i], sv[i]);
+        T(i, yv[i], yv[i]);
+      }
     }
   }
+  if (TM && !items.empty()) TM(fac, items, items);
   if (m == 0) return false;
   // candidate slot: a free one, or the oldest
   int slot;
@@ -727,7 +775,17 @@ double Optimizer::evaluate(const Flat& X, Flat& Gout, Flat& rvout) {
   EvalOut r = energy_grad(*ctx, job.shape, pt, h3dev.as<double>(), prec, &warm, job.krylov, go);
   evals++;
   krylov_apps += r.app_rho + r.app_ht;
-  for (int i = 0; i < X.count(); ++i) project_factor(i, X.view(i), D.view(i), Gout.view(i));
+  {
+    std::vector<MatView> w, dv, gv;
+    std::vector<bool> gr;
+    for (int i = 0; i < X.count(); ++i) {
+      w.push_back(X.view(i));
+      dv.push_back(D.view(i));
+      gv.push_back(Gout.view(i));
+      gr.push_back(grass[i] != 0);
+    }
+    project_many(*ctx, w, dv, gv, gr);
+  }
   return r.energy;
 }
 
@@ -891,7 +949,21 @@ bool Optimizer::advance() {
     cg_slope_prev = slope;
     cg_have = true;
   } else {
-    hist.push(c, T, dir.views(), alpha, G.views(), Gn.views());
+    const Lbfgs::TransportMany TM = [&](const std::vector<int>& fac, const std::vector<MatView>& in,
+                                        const std::vector<MatView>& out) {
+      if (job.retraction == 1) {
+        for (size_t j = 0; j < fac.size(); ++j) transport_factor(fac[j], in[j], out[j]);
+        return;
+      }
+      std::vector<MatView> w;
+      std::vector<bool> gr;
+      for (int i : fac) {
+        w.push_back(Wn.view(i));
+        gr.push_back(grass[i]);
+      }
+      project_many(c, w, in, out, gr);
+    };
+    hist.push(c, T, dir.views(), alpha, G.views(), Gn.views(), TM);
   }
   std::swap(W.buf, Wn.buf);
   std::swap(G.buf, Gn.buf);

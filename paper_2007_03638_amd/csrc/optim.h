@@ -36,6 +36,10 @@ void stiefel_project_one(Ctx& ctx, const MatView& W, const MatView& D, const Mat
 // W_out = polar(W + alpha X), X_out = dW_out/dalpha (nullable)
 void stiefel_retract_one(Ctx& ctx, const MatView& W, const MatView& X, double alpha, const MatView& Wout,
                          const MatView* Xout);
+// Projections G_j = D_j - W_j sym(W_j^T D_j) (Grassmann items: without sym) of several items, those of equal shape
+// in grouped launches; each item computes exactly what the one-item call computes (G_j may alias D_j).
+void project_many(Ctx& ctx, const std::vector<MatView>& W, const std::vector<MatView>& D,
+                  const std::vector<MatView>& G, const std::vector<bool>& grassmann);
 // The same for several factors at once (each computed exactly as alone; one synchronisation per iteration step)
 void stiefel_retract_many(Ctx& ctx, const std::vector<MatView>& W, const std::vector<MatView>& X, double alpha,
                           const std::vector<MatView>& Wout, const std::vector<const MatView*>& Xout);
@@ -96,9 +100,12 @@ struct Lbfgs {
               const std::vector<MatView>& dout);
   // After an accepted step: transport the stored pairs with T, form s = T(alpha d), y = G_new - T(G_old), store the
   // pair if <s, y> > 1e-12 |s||y|. T(i, in, out) transports factor i (out may alias in).
+  // TM, when given, transports the stored pairs all at once: TM(factor[j], in[j], out[j]) for every item j.
   using Transport = std::function<void(int, const MatView&, const MatView&)>;
+  using TransportMany =
+      std::function<void(const std::vector<int>&, const std::vector<MatView>&, const std::vector<MatView>&)>;
   bool push(Ctx& ctx, const Transport& T, const std::vector<MatView>& d, double alpha,
-            const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew);
+            const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew, const TransportMany& TM = nullptr);
   // Same with the projection transport onto the tangent spaces at Wn.
   bool push(Ctx& ctx, const std::vector<MatView>& Wn, const std::vector<MatView>& d, double alpha,
             const std::vector<MatView>& Gold, const std::vector<MatView>& Gnew);
