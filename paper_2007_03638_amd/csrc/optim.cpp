@@ -153,16 +153,33 @@ void stiefel_retract_many(Ctx& ctx, const std::vector<MatView>& W, const std::ve
   std::vector<size_t> active(k);
   for (size_t i = 0; i < k; ++i) active[i] = i;
   for (int it = 0; it < 100 && !active.empty(); ++it) {
-    for (size_t i : active) {
-      Fac& f = fs[i];
-      const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', f.p}, {'q', f.p}, {'r', f.p}};
-      mm(ctx, "T[pq] = -0.5 * Z[pr] * Yk[rq]", dpp, {{"T", f.Tk}, {"Z", f.Zk}, {"Yk", f.Yk}});
-      add_diag(ctx, VPtr{f.Tk, Prec::F64}, f.p, 1.5);
-      mm(ctx, "Y2[pq] = Yk[pr] * T[rq]", dpp, {{"Y2", f.Y2}, {"Yk", f.Yk}, {"T", f.Tk}});
-      mm(ctx, "Z2[pq] = T[pr] * Z[rq]", dpp, {{"Z2", f.Z2}, {"T", f.Tk}, {"Z", f.Zk}});
-      std::swap(f.Yk, f.Y2);
-      std::swap(f.Zk, f.Z2);
-      add_diag(ctx, VPtr{f.Tk, Prec::F64}, f.p, -1.0);
+    // one step for every active factor; factors of equal size share grouped launches
+    std::vector<bool> stepped(active.size(), false);
+    for (size_t a = 0; a < active.size(); ++a) {
+      if (stepped[a]) continue;
+      std::vector<Fac*> g;
+      for (size_t b = a; b < active.size() && g.size() < (size_t)kGettMaxGroup; ++b)
+        if (!stepped[b] && fs[active[b]].p == fs[active[a]].p) {
+          g.push_back(&fs[active[b]]);
+          stepped[b] = true;
+        }
+      const int p = g[0]->p;
+      const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', p}, {'q', p}, {'r', p}};
+      std::vector<std::vector<void*>> b1, b2, b3;
+      for (Fac* f : g) b1.push_back({f->Tk, f->Zk, f->Yk});
+      mm_group(ctx, "T[pq] = -0.5 * Z[pr] * Yk[rq]", dpp, {"T", "Z", "Yk"}, b1);
+      for (Fac* f : g) {
+        add_diag(ctx, VPtr{f->Tk, Prec::F64}, p, 1.5);
+        b2.push_back({f->Y2, f->Yk, f->Tk});
+        b3.push_back({f->Z2, f->Tk, f->Zk});
+      }
+      mm_group(ctx, "Y2[pq] = Yk[pr] * T[rq]", dpp, {"Y2", "Yk", "T"}, b2);
+      mm_group(ctx, "Z2[pq] = T[pr] * Z[rq]", dpp, {"Z2", "T", "Z"}, b3);
+      for (Fac* f : g) {
+        std::swap(f->Yk, f->Y2);
+        std::swap(f->Zk, f->Z2);
+        add_diag(ctx, VPtr{f->Tk, Prec::F64}, p, -1.0);
+      }
     }
     const size_t na_ = active.size();
     for (size_t j = 0; j < na_; ++j) {
@@ -504,6 +521,83 @@ void precondition_one(Ctx& ctx, const MatView& W, const MatView& X, Metric& met,
   mm(ctx, "Xo[nq] += W[np] * A[pq]", dnp, {{"Xo", Xout.data}, {"W", W.data}, {"A", A}});
 }
 
+void precondition_many(Ctx& ctx, const std::vector<MatView>& W, const std::vector<MatView>& X, Metric& met,
+                       const std::vector<double>& delta, const std::vector<MatView>& Xout) {
+  // factors of equal shape share grouped launches; each factor computes what precondition_one computes for it
+  const size_t k = W.size();
+  std::vector<bool> done(k, false);
+  for (size_t a = 0; a < k; ++a) {
+    if (done[a]) continue;
+    std::vector<size_t> grp;
+    for (size_t b = a; b < k && grp.size() < (size_t)kGettMaxGroup; ++b)
+      if (!done[b] && W[b].n == W[a].n && W[b].p == W[a].p) {
+        grp.push_back(b);
+        done[b] = true;
+      }
+    const int n = W[a].n, p = W[a].p;
+    const int64_t pp = (int64_t)p * p;
+    const size_t G = grp.size();
+    std::vector<double*> A(G), T1(G), Ah(G), Bp(G), T3(G), V(G), f(G), g(G);
+    for (size_t j = 0; j < G; ++j) {
+      const size_t i = grp[j];
+      MERA_CHECK(met.p[i] == p, MERA_EINVAL, "metric size does not match the tensor");
+      const std::string t = std::to_string(j);
+      A[j] = tmp(ctx, "pc.A" + t, pp);
+      T1[j] = tmp(ctx, "pc.T1" + t, pp);
+      Ah[j] = tmp(ctx, "pc.Ah" + t, pp);
+      Bp[j] = tmp(ctx, "pc.B" + t, (int64_t)n * p);
+      T3[j] = tmp(ctx, "pc.T3" + t, (int64_t)n * p);
+      V[j] = met.V[i].as<double>();
+      f[j] = met.f[i].as<double>();
+      g[j] = met.g[i].as<double>();
+      reg_spectrum(ctx, met.lam[i].as<double>(), delta[i], f[j], g[j], p);
+    }
+    const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', p}, {'q', p}, {'r', p}};
+    const std::initializer_list<std::pair<char, int64_t>> dnp = {{'n', n}, {'p', p}, {'q', p}};
+    // A = W^T X; X = W A + (X - W A) with (X - W A) = W_perp B
+    {
+      std::vector<std::vector<void*>> s1(G), s2(G);
+      for (size_t j = 0; j < G; ++j) {
+        const size_t i = grp[j];
+        s1[j] = {A[j], W[i].data, X[i].data};
+        s2[j] = {Bp[j], W[i].data, A[j]};
+      }
+      mm_group(ctx, "A[pq] = W[np] * X[nq]", dnp, {"A", "W", "X"}, s1);
+      for (size_t j = 0; j < G; ++j) copy(ctx, VPtr{Bp[j], Prec::F64}, d64(X[grp[j]]), (int64_t)n * p);
+      mm_group(ctx, "B[nq] += -1.0 * W[np] * A[pq]", dnp, {"B", "W", "A"}, s2);
+    }
+    // A~ = V [ (V^T A V)_ij 2 / (f_i + f_j) ] V^T
+    {
+      std::vector<std::vector<void*>> s1(G), s2(G), s3(G), s4(G);
+      for (size_t j = 0; j < G; ++j) {
+        s1[j] = {T1[j], V[j], A[j]};
+        s2[j] = {Ah[j], T1[j], V[j]};
+        s3[j] = {T1[j], V[j], Ah[j]};
+        s4[j] = {A[j], T1[j], V[j]};
+      }
+      mm_group(ctx, "T1[pq] = V[rp] * A[rq]", dpp, {"T1", "V", "A"}, s1);
+      mm_group(ctx, "Ah[pq] = T1[pr] * V[rq]", dpp, {"Ah", "T1", "V"}, s2);
+      for (size_t j = 0; j < G; ++j) scale_sylvester(ctx, Ah[j], f[j], p);
+      mm_group(ctx, "T1[pq] = V[pr] * Ah[rq]", dpp, {"T1", "V", "Ah"}, s3);
+      mm_group(ctx, "A[pq] = T1[pr] * V[qr]", dpp, {"A", "T1", "V"}, s4);
+    }
+    // B~ part: (W_perp B) V diag(1/f) V^T
+    {
+      std::vector<std::vector<void*>> s1(G), s2(G), s3(G);
+      for (size_t j = 0; j < G; ++j) {
+        const size_t i = grp[j];
+        s1[j] = {T3[j], Bp[j], V[j]};
+        s2[j] = {Xout[i].data, T3[j], V[j]};
+        s3[j] = {Xout[i].data, W[i].data, A[j]};
+      }
+      mm_group(ctx, "T3[nq] = B[np] * V[pq]", dnp, {"T3", "B", "V"}, s1);
+      for (size_t j = 0; j < G; ++j) scale_cols(ctx, T3[j], g[j], n, p);
+      mm_group(ctx, "Xo[nq] = T3[np] * V[qp]", dnp, {"Xo", "T3", "V"}, s2);
+      mm_group(ctx, "Xo[nq] += W[np] * A[pq]", dnp, {"Xo", "W", "A"}, s3);
+    }
+  }
+}
+
 // ---- L-BFGS ------------------------------------------------------------------------------------------
 
 void Lbfgs::init(Ctx& ctx, const std::vector<int>& n, const std::vector<int>& p, int m_) {
@@ -562,7 +656,8 @@ void apply_precond(Ctx& ctx, const Flat& shape, const std::vector<MatView>& W, M
     ne[i] = numel(xv[i]);
   }
   dots(ctx, xp.data(), xp.data(), ne.data(), nf, delta.data());
-  for (int i = 0; i < nf; ++i) precondition_one(ctx, W[i], xv[i], *met, i, std::sqrt(delta[i]), ov[i]);
+  for (double& d : delta) d = std::sqrt(d);
+  precondition_many(ctx, W, xv, *met, delta, ov);
 }
 
 }  // namespace

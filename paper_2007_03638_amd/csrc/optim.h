@@ -84,6 +84,10 @@ struct Metric {
 // takes delta = ||X||_F (Sec. 4). X_out may alias X.
 void precondition_one(Ctx& ctx, const MatView& W, const MatView& X, Metric& met, int i, double delta,
                       const MatView& Xout);
+// The same for several factors (delta[i] >= 0 given per factor), those of equal shape in grouped launches; each
+// factor computes exactly what precondition_one computes for it.
+void precondition_many(Ctx& ctx, const std::vector<MatView>& W, const std::vector<MatView>& X, Metric& met,
+                       const std::vector<double>& delta, const std::vector<MatView>& Xout);
 
 struct Lbfgs {
   int m = 8;
