@@ -455,6 +455,7 @@ void Metric::compute(Ctx& ctx, const std::vector<MatView>& rho) {
   // small ones (p <= 64) in one launch, one workgroup each
   std::vector<JacobiTask> tasks;
   tasks.reserve(k);
+  std::vector<std::pair<size_t, double*>> rotate;  // warm-started factors and their symmetrised rho
   for (size_t i = 0; i < k; ++i) {
     const int q = rho[i].p;
     MERA_CHECK(rho[i].n == q, MERA_EINVAL, "metric must be square");
@@ -471,18 +472,38 @@ void Metric::compute(Ctx& ctx, const std::vector<MatView>& rho) {
     symmetrize(ctx, VPtr{a, Prec::F64}, q);
     double* Q = V[i].as<double>();
     if (reuse) {
-      const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', q}, {'q', q}, {'r', q}};
-      double* t = tmp(ctx, "met.t", (int64_t)q * q);
       double* b = tmp(ctx, "met.b" + tag, (int64_t)q * q);
-      mm(ctx, "T[pq] = A[pr] * Q[rq]", dpp, {{"T", t}, {"A", a}, {"Q", Q}});
-      mm(ctx, "B[pq] = Q[rp] * T[rq]", dpp, {{"B", b}, {"Q", Q}, {"T", t}});
-      symmetrize(ctx, VPtr{b, Prec::F64}, q);
       tasks.push_back(JacobiTask{b, lam[i].as<double>(), Q, q, 1e-15, 30, true});
+      rotate.push_back({i, a});
       warm[i]++;
     } else {
       tasks.push_back(JacobiTask{a, lam[i].as<double>(), Q, q});
       warm[i] = 1;
     }
+  }
+  // B = Q^T A Q for the warm-started factors, those of equal size in grouped launches
+  std::vector<bool> done(rotate.size(), false);
+  for (size_t a0 = 0; a0 < rotate.size(); ++a0) {
+    if (done[a0]) continue;
+    const int q = p[rotate[a0].first];
+    std::vector<std::vector<void*>> s1, s2;
+    std::vector<double*> bs;
+    for (size_t b0 = a0; b0 < rotate.size() && s1.size() < (size_t)kGettMaxGroup; ++b0) {
+      const size_t i = rotate[b0].first;
+      if (done[b0] || p[i] != q) continue;
+      done[b0] = true;
+      const std::string tag = std::to_string(i);
+      double* t = tmp(ctx, "met.t" + tag, (int64_t)q * q);
+      double* b = tmp(ctx, "met.b" + tag, (int64_t)q * q);
+      double* Q = V[i].as<double>();
+      s1.push_back({t, rotate[b0].second, Q});
+      s2.push_back({b, Q, t});
+      bs.push_back(b);
+    }
+    const std::initializer_list<std::pair<char, int64_t>> dpp = {{'p', q}, {'q', q}, {'r', q}};
+    mm_group(ctx, "T[pq] = A[pr] * Q[rq]", dpp, {"T", "A", "Q"}, s1);
+    mm_group(ctx, "B[pq] = Q[rp] * T[rq]", dpp, {"B", "Q", "T"}, s2);
+    for (double* b : bs) symmetrize(ctx, VPtr{b, Prec::F64}, q);
   }
   jacobi_eigh_batch(ctx, tasks);
 }
