@@ -430,6 +430,110 @@ __global__ void __launch_bounds__(256) jacobi_small_kernel(JacobiSmallBatch batc
   }
 }
 
+// Matrices above kJacobiSmall and up to this size are decomposed by one workgroup of kMidThreads threads each, A
+// (ping-pong) and V in global memory (L2-resident at these sizes), every sweep in one launch: no launch per round
+// and no host synchronisation per sweep, and the matrices of one batch run side by side.
+constexpr int kJacobiMid = 256;
+constexpr int kMidThreads = 1024;
+
+struct JacobiMidTask {
+  double* a;  // in: the matrix; out: the rotated matrix (diagonal = eigenvalues)
+  double* b;  // ping-pong buffer, dim x dim
+  double* lam;
+  double* v;
+  const int* pairs;
+  double tol;
+  int npairs, rounds, dim, max_sweeps, v_init;
+};
+struct JacobiMidBatch {
+  JacobiMidTask t[kJacobiBatch];
+};
+
+// The rounds, rotations and block updates of jacobi_round_kernel, and the stopping rule of the multi-launch path
+// (off-diagonal and Frobenius norms summed in the workgroup), with a barrier between rounds.
+__global__ void __launch_bounds__(kMidThreads) jacobi_mid_kernel(JacobiMidBatch batch) {
+  const JacobiMidTask& task = batch.t[blockIdx.x];
+  const int dim = task.dim, npairs = task.npairs, rounds = task.rounds;
+  const int* __restrict__ pairs = task.pairs;
+  double* const v = task.v;
+  __shared__ double cs[kJacobiMid / 2], sn[kJacobiMid / 2];
+  __shared__ double part[kMidThreads / 64];
+  const int tid = threadIdx.x;
+  const int64_t n2 = (int64_t)dim * dim;
+  auto block_sum = [&](double x) {
+    x = wave_sum(x);
+    if ((tid & 63) == 0) part[tid >> 6] = x;
+    __syncthreads();
+    double tot = 0.0;
+    for (int w = 0; w < kMidThreads / 64; ++w) tot += part[w];
+    __syncthreads();
+    return tot;
+  };
+  if (!task.v_init)
+    for (int64_t t = tid; t < n2; t += kMidThreads) v[t] = (t / dim == t % dim) ? 1.0 : 0.0;
+  double* cur = task.a;
+  double* nxt = task.b;
+  double f2 = 0.0;
+  for (int64_t t = tid; t < n2; t += kMidThreads) f2 += cur[t] * cur[t];
+  const double fro = sqrt(block_sum(f2));
+  double prev_off = INFINITY;
+  for (int sweep = 0; sweep < task.max_sweeps; ++sweep) {
+    double o2 = 0.0;
+    for (int64_t t = tid; t < n2; t += kMidThreads)
+      if (t / dim != t % dim) o2 += cur[t] * cur[t];
+    const double off = sqrt(block_sum(o2));
+    if (!(off > task.tol * fro) || dim == 1) break;
+    // rounding floor: off-diagonal mass no longer shrinks quadratically
+    if (sweep >= 4 && off > 0.25 * prev_off && off < 1e-12 * fro) break;
+    prev_off = off;
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int* pr = pairs + (size_t)rd * npairs * 2;
+      if (tid < npairs) {
+        double c, s;
+        rot_of(cur, dim, pr[2 * tid], pr[2 * tid + 1], c, s);
+        cs[tid] = c;
+        sn[tid] = s;
+      }
+      __syncthreads();
+      for (int id = tid; id < npairs * npairs; id += kMidThreads) {
+        const int P = id / npairs, Q = id - P * npairs;
+        const int i = pr[2 * P], j = pr[2 * P + 1], k = pr[2 * Q], l = pr[2 * Q + 1];
+        const double cp = cs[P], sp = sn[P], cq = cs[Q], sq = sn[Q];
+        double aik = (i >= 0 && k >= 0) ? cur[(int64_t)i * dim + k] : 0.0;
+        double ail = (i >= 0 && l >= 0) ? cur[(int64_t)i * dim + l] : 0.0;
+        double ajk = (j >= 0 && k >= 0) ? cur[(int64_t)j * dim + k] : 0.0;
+        double ajl = (j >= 0 && l >= 0) ? cur[(int64_t)j * dim + l] : 0.0;
+        double t0k = cp * aik - sp * ajk, t0l = cp * ail - sp * ajl;
+        double t1k = sp * aik + cp * ajk, t1l = sp * ail + cp * ajl;
+        double n_ik = cq * t0k - sq * t0l, n_il = sq * t0k + cq * t0l;
+        double n_jk = cq * t1k - sq * t1l, n_jl = sq * t1k + cq * t1l;
+        if (P == Q) { n_il = 0.0; n_jk = 0.0; }
+        if (i >= 0 && k >= 0) nxt[(int64_t)i * dim + k] = n_ik;
+        if (i >= 0 && l >= 0) nxt[(int64_t)i * dim + l] = n_il;
+        if (j >= 0 && k >= 0) nxt[(int64_t)j * dim + k] = n_jk;
+        if (j >= 0 && l >= 0) nxt[(int64_t)j * dim + l] = n_jl;
+      }
+      for (int id = tid; id < dim * npairs; id += kMidThreads) {
+        const int r = id / npairs, P = id - r * npairs;
+        const int i = pr[2 * P], j = pr[2 * P + 1];
+        if (i >= 0 && j >= 0) {
+          const double cp = cs[P], sp = sn[P];
+          const double vi = v[(int64_t)r * dim + i], vj = v[(int64_t)r * dim + j];
+          v[(int64_t)r * dim + i] = cp * vi - sp * vj;
+          v[(int64_t)r * dim + j] = sp * vi + cp * vj;
+        }
+      }
+      __syncthreads();
+      double* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+  }
+  for (int t = tid; t < dim; t += kMidThreads) task.lam[t] = cur[(int64_t)t * dim + t];
+  if (cur != task.a)
+    for (int64_t t = tid; t < n2; t += kMidThreads) task.a[t] = cur[t];
+}
+
 __global__ void offdiag_kernel(const double* a, int dim, double* out) {
   double s = 0.0;
   const int64_t n = (int64_t)dim * dim;
@@ -876,35 +980,60 @@ JacobiSchedule& jacobi_schedule(Ctx& ctx, int dim) {
 
 }  // namespace
 
+// The multi-launch path (one kernel per round) for matrices above kJacobiMid.
+void jacobi_eigh_rounds(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol, int max_sweeps,
+                        bool v_init);
+
 void jacobi_eigh_batch(Ctx& ctx, const std::vector<JacobiTask>& tasks) {
   JacobiSmallBatch batch{};
-  int nb = 0;
+  JacobiMidBatch mid{};
+  int nb = 0, nm = 0;
   auto flush = [&]() {
     if (nb == 0) return;
     hipLaunchKernelGGL(jacobi_small_kernel, dim3(nb), dim3(256), 0, ctx.stream, batch);
     MERA_HIP(hipGetLastError());
     nb = 0;
   };
+  auto flush_mid = [&]() {
+    if (nm == 0) return;
+    hipLaunchKernelGGL(jacobi_mid_kernel, dim3(nm), dim3(kMidThreads), 0, ctx.stream, mid);
+    MERA_HIP(hipGetLastError());
+    nm = 0;
+  };
   for (const JacobiTask& t : tasks) {
     if (t.dim <= 0) continue;
-    if (t.dim > kJacobiSmall) {
-      jacobi_eigh(ctx, t.a, t.lam, t.v, t.dim, t.tol, t.max_sweeps, t.v_init);
+    if (t.dim > kJacobiMid) {
+      jacobi_eigh_rounds(ctx, t.a, t.lam, t.v, t.dim, t.tol, t.max_sweeps, t.v_init);
       continue;
     }
     JacobiSchedule& s = jacobi_schedule(ctx, t.dim);
-    batch.t[nb++] = JacobiSmallTask{t.a, t.lam, t.v, s.pairs.as<int>(), t.tol, s.npairs, s.rounds, t.dim,
-                                    t.max_sweeps, t.v_init ? 1 : 0};
-    if (nb == kJacobiBatch) flush();
+    if (t.dim <= kJacobiSmall) {
+      batch.t[nb++] = JacobiSmallTask{t.a, t.lam, t.v, s.pairs.as<int>(), t.tol, s.npairs, s.rounds, t.dim,
+                                      t.max_sweeps, t.v_init ? 1 : 0};
+      if (nb == kJacobiBatch) flush();
+    } else {
+      double* b = static_cast<double*>(ctx.buf("jacobi.mid" + std::to_string(nm),
+                                               (size_t)t.dim * t.dim * sizeof(double)));
+      mid.t[nm++] = JacobiMidTask{t.a, b, t.lam, t.v, s.pairs.as<int>(), t.tol, s.npairs, s.rounds, t.dim,
+                                  t.max_sweeps, t.v_init ? 1 : 0};
+      if (nm == kJacobiBatch) flush_mid();
+    }
   }
   flush();
+  flush_mid();
 }
 
 void jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol, int max_sweeps, bool v_init) {
   if (dim <= 0) return;
-  if (dim <= kJacobiSmall) {
+  if (dim <= kJacobiMid) {
     jacobi_eigh_batch(ctx, {JacobiTask{a, lam, v, dim, tol, max_sweeps, v_init}});
     return;
   }
+  jacobi_eigh_rounds(ctx, a, lam, v, dim, tol, max_sweeps, v_init);
+}
+
+void jacobi_eigh_rounds(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol, int max_sweeps,
+                        bool v_init) {
   JacobiSchedule& s = jacobi_schedule(ctx, dim);
   double* b = static_cast<double*>(ctx.buf("jacobi.pingpong", (size_t)dim * dim * sizeof(double)));
   const int g = grid_for((int64_t)dim * dim);
