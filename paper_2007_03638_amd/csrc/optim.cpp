@@ -691,25 +691,31 @@ double Lbfgs::step(Ctx& ctx, const std::vector<MatView>& W, const std::vector<Ma
   double* tp = t.as<double>();
   VPtr Q{qp, Prec::F64}, Z{zp, Prec::F64}, Tt{tp, Prec::F64};
   gather(ctx, shape, G, qp);
-  std::vector<double> alphas(order.size());
-  for (int k = (int)order.size() - 1; k >= 0; --k) {
+  // The inner products stay on the device (one slot each: <s_k, q> and <y_k, z> of every pair, and the two of the
+  // initial scaling), and every coefficient is formed there exactly as on the host (r <s_k, q>, then
+  // r <s_k, q> - r <y_k, z>): the two loops need no host synchronisation.
+  const size_t np = order.size();
+  double* dsc = static_cast<double*>(ctx.buf("lb.scalars", (2 * np + 2) * sizeof(double)));
+  double* dS = dsc;           // <s_k, q>
+  double* dY = dsc + np;      // <y_k, z>
+  double* dG = dsc + 2 * np;  // <s, y>, <y, H0 y> of the newest pair
+  for (int k = (int)np - 1; k >= 0; --k) {
     const int sl = order[k];
-    const double a = r[sl] * dot(ctx, VPtr{S[sl].ptr, Prec::F64}, Q, N);
-    alphas[k] = a;
-    axpby(ctx, -a, VPtr{Y[sl].ptr, Prec::F64}, 1.0, Q, N);
+    dot_dev_exact(ctx, S[sl].as<double>(), qp, N, dS + k);
+    axpby_dev(ctx, dS + k, -r[sl], VPtr{Y[sl].ptr, Prec::F64}, 1.0, Q, N);  // q -= (r <s_k, q>) y_k
   }
   apply_precond(ctx, shape, W, met, qp, zp);
   if (!order.empty()) {
     const int sl = order.back();
     apply_precond(ctx, shape, W, met, Y[sl].as<double>(), tp);
-    const double gamma = dot(ctx, VPtr{S[sl].ptr, Prec::F64}, VPtr{Y[sl].ptr, Prec::F64}, N) /
-                         dot(ctx, VPtr{Y[sl].ptr, Prec::F64}, Tt, N);
-    scal(ctx, gamma, Z, N);
+    dot_dev_exact(ctx, S[sl].as<double>(), Y[sl].as<double>(), N, dG);
+    dot_dev_exact(ctx, Y[sl].as<double>(), tp, N, dG + 1);
+    scal_ratio_dev(ctx, dG, dG + 1, zp, N);  // z *= <s, y> / <y, H0 y>
   }
-  for (size_t k = 0; k < order.size(); ++k) {
+  for (size_t k = 0; k < np; ++k) {
     const int sl = order[k];
-    const double b = r[sl] * dot(ctx, VPtr{Y[sl].ptr, Prec::F64}, Z, N);
-    axpby(ctx, alphas[k] - b, VPtr{S[sl].ptr, Prec::F64}, 1.0, Z, N);
+    dot_dev_exact(ctx, Y[sl].as<double>(), zp, N, dY + k);
+    axpby_diff_dev(ctx, r[sl], dS + k, dY + k, S[sl].as<double>(), 1.0, zp, N);  // z += (alpha_k - beta_k) s_k
   }
   // d = -z
   gather(ctx, shape, G, tp);

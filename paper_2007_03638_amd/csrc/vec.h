@@ -38,6 +38,12 @@ double trace(Ctx& ctx, VPtr x, int64_t dim);                   // syncs
 // The same reductions and updates with FP64 scalars that stay in device memory (no host synchronisation): results
 // are written to, and coefficients read from, device addresses; s scales a coefficient read from the device.
 void dot_dev(Ctx& ctx, VPtr x, VPtr y, int64_t n, double* out_dev);                       // *out = <x, y>
+// FP64 device scalars computed exactly as their host counterparts: <x, y> with the partials added in order, as
+// dot() adds them; x <- (num / den) x as scal(num / den); y <- (r p - r q) x + b y as axpby(r p - r q, x, b, y)
+void dot_dev_exact(Ctx& ctx, const double* x, const double* y, int64_t n, double* out_dev);
+void scal_ratio_dev(Ctx& ctx, const double* num_dev, const double* den_dev, double* x, int64_t n);
+void axpby_diff_dev(Ctx& ctx, double r, const double* p_dev, const double* q_dev, const double* x, double b,
+                    double* y, int64_t n);
 void trace_dev(Ctx& ctx, VPtr x, int64_t dim, double* out_dev);                           // *out = Tr X
 void axpby_dev(Ctx& ctx, const double* a_dev, double s, VPtr x, double b, VPtr y, int64_t n);  // y = s*a x + b y
 void add_diag_dev(Ctx& ctx, VPtr x, int64_t dim, const double* c_dev, double s);          // X_ii += s*c

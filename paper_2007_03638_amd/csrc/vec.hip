@@ -161,6 +161,42 @@ VecList<T> vec_list(const VPtr* v, const double* c, int k) {
   return L;
 }
 
+// *out = the partial sums added one after another in order (as the host adds them after a copy).
+__global__ void sum_partials_seq_kernel(const double* __restrict__ part, int blocks, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double t = 0.0;
+  for (int b = 0; b < blocks; ++b) t += part[b];
+  out[0] = t;
+}
+
+// x <- (num / den) x, the ratio of two device scalars (the same operations as scal with the ratio formed on the host).
+template <typename T>
+__global__ void scal_ratio_kernel(const double* __restrict__ num, const double* __restrict__ den, T* x, int64_t n) {
+  const double a = num[0] / den[0];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (T)(a * (double)x[i]);
+}
+
+// r p - r q with both products rounded before the subtraction, as the host forms it
+__device__ inline double rounded_diff(double r, double p, double q) {
+#pragma clang fp contract(off)
+  const double rp = r * p;
+  const double rq = r * q;
+  return rp - rq;
+}
+
+// y <- (r p - r q) x + b y with p, q device scalars (the loop of axpby_kernel with the coefficient formed on the
+// device as the host forms it).
+__global__ void axpby_diff_kernel(double r, const double* __restrict__ p, const double* __restrict__ q,
+                                  const double* __restrict__ x, double b, double* __restrict__ y, int64_t n) {
+  const double a = rounded_diff(r, p[0], q[0]);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v = a * (double)x[i];
+    if (b != 0.0) v += b * (double)y[i];
+    y[i] = (double)v;
+  }
+}
+
 template <typename T>
 __global__ void scal_kernel(double a, T* x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -847,6 +883,25 @@ void dot_dev(Ctx& ctx, VPtr x, VPtr y, int64_t n, double* out_dev) {
                        (const float*)x.p, (const float*)y.p, n, part);
   MERA_HIP(hipGetLastError());
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, ctx.stream, (const double*)part, blocks, out_dev);
+  MERA_HIP(hipGetLastError());
+}
+
+void dot_dev_exact(Ctx& ctx, const double* x, const double* y, int64_t n, double* out_dev) {
+  ctx.red.ensure(RED_BLOCKS * sizeof(double));
+  double* part = ctx.red.as<double>();
+  const int blocks = dot_launch(ctx, VPtr{(void*)x, Prec::F64}, VPtr{(void*)y, Prec::F64}, n, part);
+  hipLaunchKernelGGL(sum_partials_seq_kernel, dim3(1), dim3(64), 0, ctx.stream, (const double*)part, blocks, out_dev);
+  MERA_HIP(hipGetLastError());
+}
+
+void scal_ratio_dev(Ctx& ctx, const double* num_dev, const double* den_dev, double* x, int64_t n) {
+  hipLaunchKernelGGL(scal_ratio_kernel<double>, dim3(grid_for(n)), dim3(TPB), 0, ctx.stream, num_dev, den_dev, x, n);
+  MERA_HIP(hipGetLastError());
+}
+
+void axpby_diff_dev(Ctx& ctx, double r, const double* p_dev, const double* q_dev, const double* x, double b,
+                    double* y, int64_t n) {
+  hipLaunchKernelGGL(axpby_diff_kernel, dim3(grid_for(n)), dim3(TPB), 0, ctx.stream, r, p_dev, q_dev, x, b, y, n);
   MERA_HIP(hipGetLastError());
 }
 
