@@ -56,13 +56,13 @@ void normalize_dev(Ctx& ctx, VPtr x, int64_t n, double* nrm_dev, double* work_de
 // Symmetric eigendecomposition of a dim x dim FP64 matrix (row-major, device) by cyclic two-sided Jacobi
 // rotations in tournament order: A = V diag(lam) V^T, eigenvectors in the columns of V. `a` is overwritten.
 // v_init: v holds an orthogonal basis Q on entry and a = Q^T A Q; the rotations are then accumulated onto Q, so
-// that v returns the eigenvectors of A (few sweeps when Q nearly diagonalises A). Matrices up to 256 x 256 run in one
+// that v returns the eigenvectors of A (few sweeps when Q nearly diagonalises A). Matrices up to 160 x 160 run in one
 // launch (one workgroup; A and V in LDS up to 64 x 64); larger ones launch one kernel per round.
 void jacobi_eigh(Ctx& ctx, double* a, double* lam, double* v, int dim, double tol = 1e-15, int max_sweeps = 30,
                  bool v_init = false);
 
 // Several independent decompositions (arguments as for jacobi_eigh, distinct buffers): those of matrices up to
-// 256 x 256 run together, up to 16 per launch, one workgroup each (up to 64 x 64 with A and V in LDS, above that with
+// 160 x 160 run together, up to 16 per launch, one workgroup each (up to 64 x 64 with A and V in LDS, above that with
 // both in global memory and a 1024-thread workgroup); larger ones launch one kernel per round.
 struct JacobiTask {
   double* a;

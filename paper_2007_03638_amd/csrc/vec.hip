@@ -468,8 +468,9 @@ __global__ void __launch_bounds__(256) jacobi_small_kernel(JacobiSmallBatch batc
 
 // Matrices above kJacobiSmall and up to this size are decomposed by one workgroup of kMidThreads threads each, A
 // (ping-pong) and V in global memory (L2-resident at these sizes), every sweep in one launch: no launch per round
-// and no host synchronisation per sweep, and the matrices of one batch run side by side.
-constexpr int kJacobiMid = 256;
+// and no host synchronisation per sweep, and the matrices of one batch run side by side. A round's work grows
+// as dim^2 on one workgroup, so above this size the per-round launches over the whole GPU are faster.
+constexpr int kJacobiMid = 160;
 constexpr int kMidThreads = 1024;
 
 struct JacobiMidTask {

@@ -9,8 +9,9 @@ from paper_2007_03638_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-# shapes of MERA factors: square disentanglers and tall isometries, several tile sizes and ragged tails; square
-# factors of 97 (odd) and 256 rows exercise the one-workgroup eigensolver above 64 in the preconditioner
+# shapes of MERA factors: square disentanglers and tall isometries, several tile sizes and ragged tails; in the
+# preconditioner, square factors of 97 (odd) and 144 rows exercise the one-workgroup eigensolver above 64, and 256
+# rows the per-round one
 SHAPES = [(16, 16), (16, 4), (256, 24), (576, 24), (81, 9), (5, 1), (144, 144), (400, 20), (97, 97), (256, 256)]
 
 
