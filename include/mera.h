@@ -211,8 +211,9 @@ mera_status stiefel_project_noalloc(mera_ctx* ctx, int count, const mera_mat* W,
 /* Polar retraction W_out = (W + alpha X)(I + alpha^2 X^T X)^{-1/2} computed as the polar factor of
  * Y = W + alpha X, with (Y^T Y)^{-1/2} by a coupled Newton-Schulz iteration in FP64 (retraction as defined in
  * Sec. 2.3; the polar form is this library's choice). X_out (nullable) receives dR/dalpha at alpha, the
- * curve tangent used in the Wolfe slope (Sec. 3). The factors are processed together (every W and X is read
- * before any W_out is written), so W_out may alias W; X_out must not alias any X. */
+ * curve tangent used in the Wolfe slope (Sec. 3). The factors are processed together and every W is read before
+ * any output is written, so W_out may alias W; X is read again for X_out, so neither W_out nor X_out may alias
+ * any X. */
 mera_status stiefel_retract(mera_ctx* ctx, int count, const mera_mat* W, const mera_mat* X, double alpha,
                             mera_mat* W_out, mera_mat* X_out);
 /* Vector transport by projection onto the tangent space at W_new. Y_out may alias Y. */
